@@ -1,0 +1,247 @@
+"""FP64 CPU oracle for the central-moment MRT lattice Boltzmann update.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the benchmark's CPU-baseline leg, never by the product library.  It shares
+no code with the HIP path.  The arithmetic lives in ``cmlb_oracle.c`` (plain C,
+double precision); this module only marshals numpy arrays through ctypes, plus
+plain-definition analysis helpers (mode amplitudes, decay fits, closed-form
+dispersion relations, global diagnostics) in :mod:`oracle.analysis`.
+
+Lattice kinds: ``"D2Q9"``, ``"D3Q27"``, ``"D2Q37"``.  Velocities crossing
+this API are in lattice units (cells per step); theta is the paper's
+dimensionless temperature (reference value 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cmlb_oracle.c")
+_LIB = os.path.join(_HERE, "libcmlb_oracle.so")
+
+KINDS = {"D2Q9": 0, "D3Q27": 1, "D2Q37": 2}
+MODELS = {"cm": 0, "raw_mrt": 1, "reg_bgk": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        d, i, l = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_long
+        L.orc_lattice_info.argtypes = [ctypes.c_int, i, i, i, d, d, d]
+        L.orc_hermite.argtypes = [ctypes.c_int, ctypes.c_int, d, d]
+        L.orc_symprod.argtypes = [ctypes.c_int, ctypes.c_int, d, ctypes.c_int, d, d]
+        L.orc_maxwell_coeffs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, d, ctypes.c_double, d]
+        L.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, d, ctypes.c_double, d]
+        L.orc_collide.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d]
+        L.orc_collide_definitional.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d]
+        L.orc_run.argtypes = [ctypes.POINTER(_Cfg), l, l, l, d, l, ctypes.c_int]
+        L.orc_step_nodes.argtypes = [ctypes.POINTER(_Cfg), l, l, l, d, l,
+                                     ctypes.POINTER(ctypes.c_int64), d, ctypes.c_int]
+        L.orc_init_equilibrium.argtypes = [ctypes.POINTER(_Cfg), l, l, l, d, d, d, d, ctypes.c_int]
+        L.orc_moments.argtypes = [ctypes.c_int, l, d, d, d, d]
+        _lib = L
+    return _lib
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int), ("model", ctypes.c_int), ("thermal", ctypes.c_int),
+                ("pad", ctypes.c_int), ("theta0", ctypes.c_double),
+                ("omega", ctypes.c_double * 8), ("delta_coef", ctypes.c_double)]
+
+
+@dataclass
+class Cfg:
+    """Collision configuration.
+
+    ``tau[n]`` is the relaxation time of central-moment order n (the paper's
+    omega_n = 1/tau_n, eq:omega); orders missing from the dict use ``tau_hi``.
+    ``delta_coef`` is the coefficient of the delta term of the fourth-order
+    relaxation (eq:mrt): 6 follows from eq:omega, 72 is as printed.
+    """
+    lattice: str = "D3Q27"
+    tau: dict = field(default_factory=lambda: {2: 0.8})
+    tau_hi: float = 1.0
+    model: str = "cm"
+    thermal: bool = False
+    theta0: float = 1.0
+    delta_coef: float = 6.0
+
+    def omega(self):
+        return [0.0, 0.0] + [1.0 / self.tau.get(n, self.tau_hi) for n in range(2, 8)]
+
+    def c(self):
+        c = _Cfg()
+        c.lattice = KINDS[self.lattice]
+        c.model = MODELS[self.model]
+        c.thermal = 1 if self.thermal else 0
+        c.theta0 = self.theta0
+        for n, w in enumerate(self.omega()):
+            c.omega[n] = w
+        c.delta_coef = self.delta_coef
+        return c
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lattice(kind: str):
+    """Quadrature table: dict(D, Q, e (Q,3) int, w (Q,), r, resid)."""
+    D, Q = ctypes.c_int(), ctypes.c_int()
+    e = np.zeros(37 * 3, np.int32)
+    w = np.zeros(37)
+    r, resid = ctypes.c_double(), ctypes.c_double()
+    rc = lib().orc_lattice_info(KINDS[kind], ctypes.byref(D), ctypes.byref(Q),
+                                e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(w),
+                                ctypes.byref(r), ctypes.byref(resid))
+    if rc:
+        raise RuntimeError("oracle lattice failed")
+    q = Q.value
+    return dict(D=D.value, Q=q, e=e[:3 * q].reshape(q, 3).astype(np.int64), w=w[:q].copy(),
+                r=r.value, resid=resid.value)
+
+
+def hermite(D: int, nmax: int, xi) -> list:
+    """Tensor Hermite polynomials H^(0..nmax)(xi) as full index arrays."""
+    xi = np.ascontiguousarray(xi, np.float64)
+    n_tot = sum(D ** k for k in range(nmax + 1))
+    H = np.zeros(n_tot)
+    if lib().orc_hermite(D, nmax, _p(xi), _p(H)):
+        raise ValueError("bad hermite request")
+    out, o = [], 0
+    for k in range(nmax + 1):
+        out.append(H[o:o + D ** k].reshape((D,) * k) if k else H[o:o + 1].reshape(()))
+        o += D ** k
+    return out
+
+
+def symprod(A, B):
+    """Symmetric product Sym(A (x) B) of two full-index tensors."""
+    A = np.ascontiguousarray(A, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    D = (A.shape + B.shape)[0]
+    out = np.zeros((D,) * (A.ndim + B.ndim))
+    if lib().orc_symprod(D, A.ndim, _p(A.reshape(-1)), B.ndim, _p(B.reshape(-1)), _p(out)):
+        raise ValueError("rank too high")
+    return out
+
+
+def maxwell_coeffs(D: int, nmax: int, rho: float, u_xi, theta: float) -> list:
+    """Hermite coefficients a^(0..nmax) of the Maxwellian (u in xi-units)."""
+    u = np.zeros(3)
+    u[:D] = u_xi
+    n_tot = sum(D ** k for k in range(nmax + 1))
+    a = np.zeros(n_tot)
+    if lib().orc_maxwell_coeffs(D, nmax, rho, _p(u), theta, _p(a)):
+        raise ValueError("nmax > 4")
+    out, o = [], 0
+    for k in range(nmax + 1):
+        out.append(a[o:o + D ** k].reshape((D,) * k) if k else a[o:o + 1].reshape(()))
+        o += D ** k
+    return out
+
+
+def equilibrium(kind: str, rho: float, u_lat, theta: float = 1.0) -> np.ndarray:
+    u = np.zeros(3)
+    u[:len(u_lat)] = u_lat
+    f0 = np.zeros(37)
+    lib().orc_equilibrium(KINDS[kind], rho, _p(u), theta, _p(f0))
+    return f0[:lattice(kind)["Q"]].copy()
+
+
+def collide(cfg: Cfg, f: np.ndarray) -> np.ndarray:
+    """Post-collision populations for a batch of nodes f[n, Q] (paper's route)."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    out = np.zeros_like(f)
+    c = cfg.c()
+    if lib().orc_collide(ctypes.byref(c), f.shape[0], _p(f), _p(out)):
+        raise RuntimeError("collide failed")
+    return out
+
+
+def collide_definitional(cfg: Cfg, f: np.ndarray) -> np.ndarray:
+    """Post-collision populations from the defining moment conditions (dense solve)."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    out = np.zeros_like(f)
+    c = cfg.c()
+    if lib().orc_collide_definitional(ctypes.byref(c), f.shape[0], _p(f), _p(out)):
+        raise RuntimeError("singular moment system")
+    return out
+
+
+def _dims(S):
+    Q = S.shape[0]
+    if S.ndim == 3:
+        return Q, 1, S.shape[1], S.shape[2]
+    return Q, S.shape[1], S.shape[2], S.shape[3]
+
+
+def run(cfg: Cfg, S: np.ndarray, nsteps: int, threads: int | None = None) -> np.ndarray:
+    """Advance the state S[Q, (nz,) ny, nx] by nsteps pull-stream + collide steps (in place)."""
+    assert S.dtype == np.float64 and S.flags.c_contiguous
+    Q, nz, ny, nx = _dims(S)
+    threads = threads or os.cpu_count() or 1
+    if lib().orc_run(ctypes.byref(cfg.c()), nx, ny, nz, _p(S), nsteps, threads):
+        raise RuntimeError("run failed")
+    return S
+
+
+def step_nodes(cfg: Cfg, S: np.ndarray, nodes, threads: int | None = None) -> np.ndarray:
+    """One step of state S evaluated at flat node indices; returns [n, Q]."""
+    S = np.ascontiguousarray(S, np.float64)
+    Q, nz, ny, nx = _dims(S)
+    nodes = np.ascontiguousarray(nodes, np.int64)
+    out = np.zeros((len(nodes), Q))
+    threads = threads or os.cpu_count() or 1
+    lib().orc_step_nodes(ctypes.byref(cfg.c()), nx, ny, nz, _p(S), len(nodes),
+                         nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out), threads)
+    return out
+
+
+def init_equilibrium(cfg: Cfg, rho: np.ndarray, u: np.ndarray, theta=None,
+                     threads: int | None = None) -> np.ndarray:
+    """S_0 = f0(rho, u, theta) on a grid; rho[(nz,)ny,nx], u[D, ...]."""
+    L = lattice(cfg.lattice)
+    rho = np.ascontiguousarray(rho, np.float64)
+    shape = rho.shape
+    nz, ny, nx = (1,) + shape if rho.ndim == 2 else shape
+    u = np.ascontiguousarray(u, np.float64)
+    th = None if theta is None else np.ascontiguousarray(theta, np.float64)
+    S = np.zeros((L["Q"],) + shape)
+    threads = threads or os.cpu_count() or 1
+    lib().orc_init_equilibrium(ctypes.byref(cfg.c()), nx, ny, nz, _p(rho), _p(u),
+                               None if th is None else _p(th), _p(S), threads)
+    return S
+
+
+def moments(kind: str, S: np.ndarray):
+    """rho, u (lattice units, [D, ...]) and theta of a state."""
+    L = lattice(kind)
+    S = np.ascontiguousarray(S, np.float64)
+    shape = S.shape[1:]
+    n = int(np.prod(shape))
+    rho = np.zeros(shape)
+    u = np.zeros((L["D"],) + shape)
+    th = np.zeros(shape)
+    lib().orc_moments(KINDS[kind], n, _p(S), _p(rho), _p(u), _p(th))
+    return rho, u, th

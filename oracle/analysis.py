@@ -1,0 +1,95 @@
+"""Plain-definition analysis for the oracle (test infrastructure only).
+
+* transport coefficients from relaxation times (Chapman-Enskog, Sec. II.C
+  eq:sigma, with the lattice correction tau - 1/2);
+* single-wavenumber mode amplitudes and exponential-decay fits (Sec. III.A);
+* the closed-form dispersion relations eq:dr;
+* global FP64 diagnostics of a state (mass, momentum, energy, kinetic energy,
+  enstrophy, non-finite count).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import lattice
+
+
+def nu_lattice(kind: str, tau2: float, theta: float = 1.0) -> float:
+    """Kinematic viscosity in lattice units: nu_xi = theta (tau2 - 1/2), nu_lat = nu_xi / r^2."""
+    r = lattice(kind)["r"]
+    return theta * (tau2 - 0.5) / r ** 2
+
+
+def tau_from_nu_xi(nu_xi: float, theta: float = 1.0) -> float:
+    """Relaxation time giving a diffusivity nu_xi (xi-units) at temperature theta."""
+    return 0.5 + nu_xi / theta
+
+
+def mode_amplitude(field: np.ndarray, kvec) -> complex:
+    """(2/N) sum_x field(x) exp(-i k.x) for integer mode numbers kvec (x fastest)."""
+    shape = field.shape
+    idx = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    coords = list(reversed(idx))
+    phase = sum(2 * np.pi * kvec[d] * coords[d] / shape[::-1][d] for d in range(len(kvec)))
+    return 2.0 * np.sum(field * np.exp(-1j * phase)) / field.size
+
+
+def fit_decay(t, amp) -> float:
+    """Least-squares slope of -ln|amp| against t (a positive decay rate)."""
+    t = np.asarray(t, np.float64)
+    y = np.log(np.abs(np.asarray(amp)))
+    A = np.stack([t, np.ones_like(t)], 1)
+    slope = np.linalg.lstsq(A, y, rcond=None)[0][0]
+    return -slope
+
+
+def dispersion(nu: float, kappa: float, theta0: float, k: float, D: int = 2):
+    """Closed forms eq:dr (all quantities in xi-units).
+
+    Returns (viscous decay rate, thermal decay rate, acoustic decay rate,
+    acoustic angular frequency), rates positive; gamma = (D + 2) / D.
+    """
+    g = (D + 2.0) / D
+    cs = np.sqrt(g * theta0)
+    pr = nu / kappa
+    lam = 1.0 + (g - 3.0) * pr
+    pe = cs / (kappa * k)
+    visc = nu * k * k
+    therm = cs * k * (1.0 / pe + (g - 1.0) * lam / pe ** 3)
+    ac_re = cs * k * ((g - lam) / (2 * pe) - (g - 1.0) * lam / (2 * pe ** 3))
+    ac_im = cs * k * (1.0 - ((g + lam) ** 2 - 4 * lam) / (8 * pe ** 2))
+    return visc, therm, ac_re, ac_im
+
+
+def globals_of_state(kind: str, S: np.ndarray) -> dict:
+    """FP64 global diagnostics: mass, momentum (lattice units), energy
+    (sum f |e|^2 / 2, lattice units), kinetic energy 1/2 sum rho |u|^2,
+    enstrophy 1/2 sum |curl u|^2 with second-order central differences on the
+    periodic grid, and the count of non-finite populations."""
+    L = lattice(kind)
+    Q, D = L["Q"], L["D"]
+    e = L["e"][:, :D].astype(np.float64)
+    F = S.reshape(Q, -1)
+    nonfinite = int((~np.isfinite(F)).sum())
+    rho = F.sum(0)
+    mom = e.T @ F
+    u = mom / rho
+    energy = 0.5 * ((e ** 2).sum(1) @ F).sum()
+    ke = 0.5 * (rho * (u ** 2).sum(0)).sum()
+    shape = S.shape[1:]
+    uf = u.reshape((D,) + shape)
+
+    def ddx(a, d):  # derivative along spatial direction d (0 = x = last axis)
+        ax = a.ndim - 1 - d
+        return 0.5 * (np.roll(a, -1, axis=ax) - np.roll(a, 1, axis=ax))
+
+    if D == 2:
+        wz = ddx(uf[1], 0) - ddx(uf[0], 1)
+        ens = 0.5 * (wz ** 2).sum()
+    else:
+        wx = ddx(uf[2], 1) - ddx(uf[1], 2)
+        wy = ddx(uf[0], 2) - ddx(uf[2], 0)
+        wz = ddx(uf[1], 0) - ddx(uf[0], 1)
+        ens = 0.5 * (wx ** 2 + wy ** 2 + wz ** 2).sum()
+    return dict(mass=rho.sum(), momentum=mom.sum(1), energy=energy, ke=ke,
+                enstrophy=ens, nonfinite=nonfinite)

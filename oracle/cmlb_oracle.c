@@ -1,0 +1,938 @@
+/*
+ * FP64 CPU oracle for the central-moment multiple-relaxation-time (CM-MRT)
+ * lattice Boltzmann update of X. Shan, "A central-moment multiple-relaxation-
+ * time collision model" (arXiv:1808.04406).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * execute this file: only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * constant generator with the HIP library; it derives every table itself.
+ *
+ * Everything is double precision, written for readability rather than speed:
+ * symmetric tensors are stored with all D^n index components, symmetrisation
+ * averages over all n! index permutations, and linear systems are solved by
+ * Gaussian elimination with partial pivoting.
+ *
+ * Units.  Lattice velocities e_i are integer vectors; the abscissas of the
+ * quadrature are xi_i = r e_i (Sec. II.A, eq:quad).  The Hermite machinery
+ * works in xi-units, where the reference temperature is theta = 1.  The API
+ * exchanges velocities in lattice units (cells per step): u_lat = u_xi / r.
+ *
+ * Parity: every function below is pinned by the CPU test suite against
+ * closed forms, library quadrature, brute force or the paper's printed
+ * constants, except the storage codecs (none here) and the learned-closure
+ * network, whose pin is a finite-difference gradient check.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXQ 37
+#define ORC_MAXN 6   /* highest tensor rank handled */
+
+enum { ORC_D2Q9 = 0, ORC_D3Q27 = 1, ORC_D2Q37 = 2 };
+enum { ORC_CM = 0, ORC_RAW_MRT = 1, ORC_REG_BGK = 2 };
+
+typedef struct {
+    int D, Q;
+    int e[ORC_MAXQ][3];
+    double w[ORC_MAXQ];
+    double r;
+} orc_lattice;
+
+/* Collision configuration (passed from Python as a flat struct). */
+typedef struct {
+    int lattice;       /* ORC_D2Q9 / ORC_D3Q27 / ORC_D2Q37 */
+    int model;         /* ORC_CM (this paper), ORC_RAW_MRT (eq:regnmrt, right), ORC_REG_BGK (eq:lbgk-reg) */
+    int thermal;       /* 1: theta is computed from f; 0: theta is frozen at theta0 (Sec. III.B) */
+    int pad;
+    double theta0;     /* frozen temperature (isothermal runs) */
+    double omega[8];   /* omega[n]: relaxation frequency of order n; n = 0, 1 unused */
+    double delta_coef; /* coefficient of the delta term in the fourth-order relaxation; 6 satisfies eq:omega, 72 is as printed */
+} orc_cfg;
+
+/* ------------------------------------------------------------------------- */
+/* Dense linear algebra                                                      */
+/* ------------------------------------------------------------------------- */
+
+/* Solve A x = b in place (A is n x n row-major and is destroyed; b becomes x).
+ * Returns 0, or -1 if A is numerically singular. */
+static int solve_dense(int n, double *A, double *b)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = fabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > best) { best = fabs(A[i * n + k]); piv = i; }
+        if (best == 0.0) return -1;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double m = A[i * n + k] / A[k * n + k];
+            if (m == 0.0) continue;
+            for (int j = k; j < n; ++j) A[i * n + j] -= m * A[k * n + j];
+            b[i] -= m * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * b[j];
+        b[k] = s / A[k * n + k];
+    }
+    return 0;
+}
+
+static double determinant(int n, double *A)
+{
+    double det = 1.0;
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (A[piv * n + k] == 0.0) return 0.0;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+            det = -det;
+        }
+        det *= A[k * n + k];
+        for (int i = k + 1; i < n; ++i) {
+            double m = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= m * A[k * n + j];
+        }
+    }
+    return det;
+}
+
+static double factorial(int n) { double f = 1.0; for (int k = 2; k <= n; ++k) f *= k; return f; }
+static double binom(int n, int k) { return factorial(n) / (factorial(k) * factorial(n - k)); }
+static int ipow(int b, int e) { int p = 1; while (e-- > 0) p *= b; return p; }
+
+/* ------------------------------------------------------------------------- */
+/* Lattices (quadratures, Sec. II.A eq:quad)                                  */
+/* ------------------------------------------------------------------------- */
+
+/* 1D Gaussian moment E[X^p], X ~ N(0,1): (p-1)!! for even p, 0 for odd p. */
+static double gauss_moment(int p)
+{
+    if (p % 2) return 0.0;
+    double m = 1.0;
+    for (int k = p - 1; k > 0; k -= 2) m *= k;
+    return m;
+}
+
+/* All distinct images of (a, b) under sign changes and axis exchange. */
+static int shell_images(int a, int b, int out[8][2])
+{
+    int n = 0;
+    int base[2][2] = {{a, b}, {b, a}};
+    for (int t = 0; t < 2; ++t)
+        for (int sx = 1; sx >= -1; sx -= 2)
+            for (int sy = 1; sy >= -1; sy -= 2) {
+                int x = sx * base[t][0], y = sy * base[t][1], dup = 0;
+                for (int k = 0; k < n; ++k) if (out[k][0] == x && out[k][1] == y) dup = 1;
+                if (!dup) { out[n][0] = x; out[n][1] = y; ++n; }
+            }
+    return n;
+}
+
+/* The 37-velocity ninth-degree 2D rule: shells (0,0),(1,0),(1,1),(2,0),(2,1),
+ * (2,2),(3,0),(3,1) with all their images.  The eight shell weights and the
+ * scale r solve the nine independent even-moment conditions of a degree-9
+ * rule (odd moments vanish by symmetry): sum_i w_i xi_x^p xi_y^q = E[X^p]E[Y^q]
+ * for (p,q) in the list below.  With x = 1/r^2 the conditions read
+ * A w = b(x), b_k = E[X^p]E[Y^q] x^((p+q)/2); a solution exists where
+ * det[A | b(x)] = 0.  The root is found by bisection and the weights by
+ * solving eight of the equations; the ninth is the consistency check. */
+static int make_d2q37(orc_lattice *L, double *resid_out)
+{
+    static const int shells[8][2] = {{0,0},{1,0},{1,1},{2,0},{2,1},{2,2},{3,0},{3,1}};
+    /* (8,0) last: the other eight conditions form a well-conditioned square system */
+    static const int mons[9][2] = {{0,0},{2,0},{4,0},{2,2},{6,0},{4,2},{6,2},{4,4},{8,0}};
+    int img[8][8][2], nimg[8];
+    double A[9][8];
+    for (int s = 0; s < 8; ++s) nimg[s] = shell_images(shells[s][0], shells[s][1], img[s]);
+    for (int k = 0; k < 9; ++k)
+        for (int s = 0; s < 8; ++s) {
+            double acc = 0.0;
+            for (int j = 0; j < nimg[s]; ++j)
+                acc += pow(img[s][j][0], mons[k][0]) * pow(img[s][j][1], mons[k][1]);
+            A[k][s] = acc;
+        }
+    double M[81];
+#define AUGDET(x, out) do {                                                   \
+        for (int k_ = 0; k_ < 9; ++k_) {                                      \
+            for (int s_ = 0; s_ < 8; ++s_) M[k_ * 9 + s_] = A[k_][s_];        \
+            M[k_ * 9 + 8] = gauss_moment(mons[k_][0]) * gauss_moment(mons[k_][1]) \
+                          * pow((x), (mons[k_][0] + mons[k_][1]) / 2);        \
+        }                                                                     \
+        (out) = determinant(9, M);                                            \
+    } while (0)
+    /* scan for the sign change, then bisect */
+    double lo = 0.0, hi = 0.0, flo = 0.0, prev_x = 0.3, prev_f;
+    AUGDET(prev_x, prev_f);
+    int found = 0;
+    for (int k = 1; k <= 1200 && !found; ++k) {
+        double x = 0.3 + k * 0.001, fx;
+        AUGDET(x, fx);
+        if ((fx < 0) != (prev_f < 0)) { lo = prev_x; hi = x; flo = prev_f; found = 1; }
+        prev_x = x; prev_f = fx;
+    }
+    if (!found) return -1;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi), fm;
+        AUGDET(mid, fm);
+        if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
+    }
+#undef AUGDET
+    double x = 0.5 * (lo + hi);
+    double S[64], wv[8];
+    for (int k = 0; k < 8; ++k) {
+        for (int s = 0; s < 8; ++s) S[k * 8 + s] = A[k][s];
+        wv[k] = gauss_moment(mons[k][0]) * gauss_moment(mons[k][1]) * pow(x, (mons[k][0] + mons[k][1]) / 2);
+    }
+    if (solve_dense(8, S, wv)) return -1;
+    double r9 = -gauss_moment(mons[8][0]) * gauss_moment(mons[8][1]) * pow(x, 4);
+    for (int s = 0; s < 8; ++s) r9 += A[8][s] * wv[s];
+    if (resid_out) *resid_out = r9;
+    /* populations ordered by (e_y, e_x) lexicographically */
+    L->D = 2; L->Q = 37; L->r = 1.0 / sqrt(x);
+    int q = 0;
+    for (int ey = -3; ey <= 3; ++ey)
+        for (int ex = -3; ex <= 3; ++ex)
+            for (int s = 0; s < 8; ++s)
+                for (int j = 0; j < nimg[s]; ++j)
+                    if (img[s][j][0] == ex && img[s][j][1] == ey) {
+                        L->e[q][0] = ex; L->e[q][1] = ey; L->e[q][2] = 0;
+                        L->w[q] = wv[s];
+                        ++q;
+                    }
+    return q == 37 ? 0 : -1;
+}
+
+/* D2Q9 and D3Q27: the tensor products of the three-point Gauss-Hermite rule
+ * {0, +-sqrt(3)} with weights {2/3, 1/6, 1/6}; degree 5 per axis.  Populations
+ * are ordered lexicographically with e_x fastest, i = (ex+1) + 3(ey+1) + 9(ez+1). */
+static void make_tensor_lattice(int D, orc_lattice *L)
+{
+    static const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    L->D = D; L->Q = ipow(3, D); L->r = sqrt(3.0);
+    for (int i = 0; i < L->Q; ++i) {
+        int ix = i % 3, iy = (i / 3) % 3, iz = (D == 3) ? i / 9 : 1;
+        L->e[i][0] = ix - 1; L->e[i][1] = iy - 1; L->e[i][2] = (D == 3) ? iz - 1 : 0;
+        L->w[i] = w1[ix] * w1[iy] * (D == 3 ? w1[iz] : 1.0);
+    }
+}
+
+static int get_lattice(int kind, orc_lattice *L)
+{
+    if (kind == ORC_D2Q9) { make_tensor_lattice(2, L); return 0; }
+    if (kind == ORC_D3Q27) { make_tensor_lattice(3, L); return 0; }
+    if (kind == ORC_D2Q37) return make_d2q37(L, NULL);
+    return -1;
+}
+
+/* Lattice tables are built once per kind. */
+static orc_lattice g_lat[3];
+static int g_lat_ok[3];
+
+static void build_tables(const orc_lattice *L, int kind);
+
+/* Lattice and its Hermite tables; built on first use, before any parallel region. */
+static const orc_lattice *lattice(int kind)
+{
+    if (kind < 0 || kind > 2) return NULL;
+    if (!g_lat_ok[kind]) {
+        orc_lattice L;
+        if (get_lattice(kind, &L)) return NULL;
+        g_lat[kind] = L;
+        build_tables(&g_lat[kind], kind);
+        g_lat_ok[kind] = 1;
+    }
+    return &g_lat[kind];
+}
+
+int orc_lattice_info(int kind, int *D, int *Q, int *e, double *w, double *r, double *resid)
+{
+    const orc_lattice *L = lattice(kind);
+    if (!L) return -1;
+    *D = L->D; *Q = L->Q; *r = L->r;
+    for (int i = 0; i < L->Q; ++i) {
+        w[i] = L->w[i];
+        for (int d = 0; d < 3; ++d) e[3 * i + d] = L->e[i][d];
+    }
+    if (resid) {
+        *resid = 0.0;
+        if (kind == ORC_D2Q37) { orc_lattice T; make_d2q37(&T, resid); }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Symmetric tensors (Sec. II, definitions of Sym and the symmetric product)  */
+/* ------------------------------------------------------------------------- */
+/* A rank-n tensor in D dimensions is stored with all D^n components, index
+ * (i_0, ..., i_{n-1}) at offset sum_k i_k D^(n-1-k). */
+
+static int next_perm(int n, int *p)
+{
+    int i = n - 2;
+    while (i >= 0 && p[i] >= p[i + 1]) --i;
+    if (i < 0) return 0;
+    int j = n - 1;
+    while (p[j] <= p[i]) --j;
+    int t = p[i]; p[i] = p[j]; p[j] = t;
+    for (int a = i + 1, b = n - 1; a < b; ++a, --b) { t = p[a]; p[a] = p[b]; p[b] = t; }
+    return 1;
+}
+
+/* Sym(A): average of A over the n! permutations of its indices. */
+static void t_sym(int D, int n, const double *A, double *out)
+{
+    int size = ipow(D, n);
+    if (n <= 1) { memcpy(out, A, sizeof(double) * size); return; }
+    double nf = factorial(n);
+    for (int I = 0; I < size; ++I) {
+        int idx[ORC_MAXN], perm[ORC_MAXN];
+        for (int k = n - 1, t = I; k >= 0; --k) { idx[k] = t % D; t /= D; }
+        for (int k = 0; k < n; ++k) perm[k] = k;
+        double acc = 0.0;
+        do {
+            int J = 0;
+            for (int k = 0; k < n; ++k) J = J * D + idx[perm[k]];
+            acc += A[J];
+        } while (next_perm(n, perm));
+        out[I] = acc / nf;
+    }
+}
+
+/* Ordinary tensor product A (rank n) (x) B (rank m). */
+static void t_outer(int D, int n, const double *A, int m, const double *B, double *out)
+{
+    int sa = ipow(D, n), sb = ipow(D, m);
+    for (int i = 0; i < sa; ++i)
+        for (int j = 0; j < sb; ++j) out[i * sb + j] = A[i] * B[j];
+}
+
+/* Symmetric product AB = Sym(A (x) B). */
+static void t_symprod(int D, int n, const double *A, int m, const double *B, double *out)
+{
+    double tmp[729];
+    t_outer(D, n, A, m, B, tmp);
+    t_sym(D, n + m, tmp, out);
+}
+
+static double t_contract(int D, int n, const double *A, const double *B)
+{
+    int s = ipow(D, n);
+    double acc = 0.0;
+    for (int i = 0; i < s; ++i) acc += A[i] * B[i];
+    return acc;
+}
+
+static void t_delta(int D, double *out)
+{
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) out[i * D + j] = (i == j) ? 1.0 : 0.0;
+}
+
+/* Offsets of ranks 0..nmax packed one after another. */
+static int t_offset(int D, int n) { int o = 0; for (int k = 0; k < n; ++k) o += ipow(D, k); return o; }
+
+/* Tensor Hermite polynomials H^(0..nmax)(xi) by the recursion of Appendix A:
+ * xi H^(n) = H^(n+1) + n delta H^(n-1), all products symmetric. */
+static void hermite_tensors(int D, int nmax, const double *xi, double *H)
+{
+    double delta[9], t1[729], t2[729];
+    t_delta(D, delta);
+    H[0] = 1.0;
+    if (nmax >= 1) for (int d = 0; d < D; ++d) H[1 + d] = xi[d];
+    for (int n = 1; n < nmax; ++n) {
+        double *Hn = H + t_offset(D, n), *Hm = H + t_offset(D, n - 1), *Hp = H + t_offset(D, n + 1);
+        t_symprod(D, 1, xi, n, Hn, t1);
+        t_symprod(D, 2, delta, n - 1, Hm, t2);
+        int s = ipow(D, n + 1);
+        for (int i = 0; i < s; ++i) Hp[i] = t1[i] - n * t2[i];
+    }
+}
+
+int orc_hermite(int D, int nmax, const double *xi, double *H)
+{
+    if (D < 1 || D > 3 || nmax < 0 || nmax > ORC_MAXN) return -1;
+    hermite_tensors(D, nmax, xi, H);
+    return 0;
+}
+
+int orc_symprod(int D, int n, const double *A, int m, const double *B, double *out)
+{
+    if (n + m > ORC_MAXN) return -1;
+    t_symprod(D, n, A, m, B, out);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Maxwellian Hermite coefficients (eq:maxwellian, Appendix A eq:trans-a)     */
+/* ------------------------------------------------------------------------- */
+/* In the frame moving with u the Maxwellian of temperature theta has Hermite
+ * coefficients b^(0) = rho, b^(1) = b^(3) = 0, b^(2) = rho (theta-1) delta,
+ * b^(4) = 3 rho (theta-1)^2 delta delta (Gaussian moments of H^(n)(c)).  The
+ * absolute-frame coefficients follow from the binomial transform
+ * a^(n) = sum_i C(n,i) b^(i) u^(n-i). */
+static void maxwell_coeffs(int D, int nmax, double rho, const double *u_xi, double theta, double *a)
+{
+    double b[1 + 3 + 9 + 27 + 81];
+    double delta[9] = {0}, dd[81];
+    t_delta(D, delta);
+    t_symprod(D, 2, delta, 2, delta, dd);
+    memset(b, 0, sizeof(b));
+    b[t_offset(D, 0)] = rho;
+    if (nmax >= 2) for (int i = 0; i < D * D; ++i) b[t_offset(D, 2) + i] = rho * (theta - 1.0) * delta[i];
+    if (nmax >= 4) for (int i = 0; i < ipow(D, 4); ++i) b[t_offset(D, 4) + i] = 3.0 * rho * (theta - 1.0) * (theta - 1.0) * dd[i];
+    /* powers u^k as symmetric tensors */
+    double upow[5][81];
+    upow[0][0] = 1.0;
+    for (int k = 1; k <= nmax; ++k) t_symprod(D, k - 1, upow[k - 1], 1, u_xi, upow[k]);
+    for (int n = 0; n <= nmax; ++n) {
+        double *an = a + t_offset(D, n);
+        int s = ipow(D, n);
+        for (int j = 0; j < s; ++j) an[j] = 0.0;
+        for (int i = 0; i <= n; ++i) {
+            double tmp[729];
+            t_symprod(D, i, b + t_offset(D, i), n - i, upow[n - i], tmp);
+            double c = binom(n, i);
+            for (int j = 0; j < s; ++j) an[j] += c * tmp[j];
+        }
+    }
+}
+
+int orc_maxwell_coeffs(int D, int nmax, double rho, const double *u_xi, double theta, double *a)
+{
+    if (nmax > 4) return -1;
+    maxwell_coeffs(D, nmax, rho, u_xi, theta, a);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Moments of one node (Sec. II.A, eq. after eq:fi)                           */
+/* ------------------------------------------------------------------------- */
+static void node_moments(const orc_lattice *L, const double *f, double *rho, double *u_xi, double *theta)
+{
+    double m0 = 0.0, m1[3] = {0, 0, 0}, m2 = 0.0;
+    for (int i = 0; i < L->Q; ++i) {
+        double xi2 = 0.0;
+        m0 += f[i];
+        for (int d = 0; d < L->D; ++d) {
+            double xi = L->r * L->e[i][d];
+            m1[d] += f[i] * xi;
+            xi2 += xi * xi;
+        }
+        m2 += f[i] * xi2;
+    }
+    *rho = m0;
+    double uu = 0.0;
+    for (int d = 0; d < 3; ++d) { u_xi[d] = (d < L->D) ? m1[d] / m0 : 0.0; uu += u_xi[d] * u_xi[d]; }
+    /* rho (u^2 + D theta) = sum f xi^2 */
+    *theta = (m2 / m0 - uu) / L->D;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-axis (tensor-product) Hermite basis for D2Q9 and D3Q27 (Sec. II.A)     */
+/* ------------------------------------------------------------------------- */
+/* On the lattices {-1,0,1}^D the complete set of Q functions used is
+ * H_p(xi) = prod_d He_{p_d}(xi_d), p_d <= 2, with He_0 = 1, He_1 = x,
+ * He_2 = x^2 - 1 (H^(0..2) of Appendix A in one dimension).  They are the
+ * components of the tensor Hermite polynomials with at most two equal
+ * indices and are orthogonal under the quadrature with norm prod p_d!. */
+static double he1d(int p, double x)
+{
+    /* He_{p+1} = x He_p - p He_{p-1} (the one-dimensional recursion) */
+    double hm = 1.0, h = x;
+    if (p == 0) return 1.0;
+    for (int k = 1; k < p; ++k) { double hn = x * h - k * hm; hm = h; h = hn; }
+    return h;
+}
+
+static int n_tp(int D) { return ipow(3, D); }
+static void tp_index(int D, int p, int *pd) { pd[0] = p % 3; pd[1] = (p / 3) % 3; pd[2] = (D == 3) ? p / 9 : 0; }
+
+static double tp_hermite(int D, int p, const double *xi);
+
+/* H_p(xi_i) for every basis function p and velocity i, built once per lattice. */
+static double g_Htp[2][27][27];
+static int g_Htp_ok[2];
+
+static const double (*tp_table(const orc_lattice *L))[27]
+{
+    int k = (L->D == 3) ? 1 : 0;
+    if (!g_Htp_ok[k]) {
+        for (int p = 0; p < n_tp(L->D); ++p)
+            for (int i = 0; i < L->Q; ++i) {
+                double xi[3] = {L->r * L->e[i][0], L->r * L->e[i][1], L->r * L->e[i][2]};
+                g_Htp[k][p][i] = tp_hermite(L->D, p, xi);
+            }
+        g_Htp_ok[k] = 1;
+    }
+    return (const double (*)[27])g_Htp[k];
+}
+
+static double tp_hermite(int D, int p, const double *xi)
+{
+    int pd[3];
+    tp_index(D, p, pd);
+    double h = 1.0;
+    for (int d = 0; d < D; ++d) h *= he1d(pd[d], xi[d]);
+    return h;
+}
+
+/* Per-axis 3x3 map from Hermite coefficients (He_0..He_2 in the absolute
+ * frame) to central monomial moments (c^0, c^1, c^2), c = xi - u.  Built from
+ * eq:binomial-transform, He_k(c) = sum_i (-1)^(k-i) C(k,i) He_i(xi) u^(k-i),
+ * and eq:hermite-r, c^2 = He_2(c) + He_0(c). */
+static void axis_herm_to_central(double u, double P[3][3])
+{
+    double B[3][3] = {{0}};  /* He_k(c) in terms of He_i(xi) */
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i <= k; ++i) B[k][i] = ((k - i) % 2 ? -1.0 : 1.0) * binom(k, i) * pow(u, k - i);
+    double Mh[3][3] = {{1, 0, 0}, {0, 1, 0}, {1, 0, 1}};  /* c^k in terms of He_j(c) */
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) s += Mh[k][j] * B[j][i];
+            P[k][i] = s;
+        }
+}
+
+/* Inverse of the above: central monomials back to absolute-frame Hermite
+ * coefficients, from He_2(c) = c^2 - 1 and He_n(xi) = sum_i C(n,i) He_i(c) u^(n-i). */
+static void axis_central_to_herm(double u, double P[3][3])
+{
+    double Hm[3][3] = {{1, 0, 0}, {0, 1, 0}, {-1, 0, 1}};  /* He_k(c) in terms of c^j */
+    double Bi[3][3] = {{0}};                                /* He_k(xi) in terms of He_i(c) */
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i <= k; ++i) Bi[k][i] = binom(k, i) * pow(u, k - i);
+    /* a_xi[k] = sum f He_k(xi) = sum_i Bi[k][i] b[i], b[i] = sum f He_i(c) = sum_j Hm[i][j] kappa[j] */
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) s += Bi[k][i] * Hm[i][j];
+            P[k][j] = s;
+        }
+}
+
+/* Coefficient-space maps are linear over the basis; on the tensor-product
+ * basis a coefficient vector indexed by p transforms with the Kronecker
+ * product of the per-axis maps. */
+static void tp_apply(int D, const double P[3][3][3], const double *in, double *out)
+{
+    int n = n_tp(D);
+    for (int p = 0; p < n; ++p) {
+        int pd[3];
+        tp_index(D, p, pd);
+        double acc = 0.0;
+        for (int q = 0; q < n; ++q) {
+            int qd[3];
+            tp_index(D, q, qd);
+            double m = 1.0;
+            for (int d = 0; d < D; ++d) m *= P[d][pd[d]][qd[d]];
+            acc += m * in[q];
+        }
+        out[p] = acc;
+    }
+}
+
+static int tp_order(int D, int p) { int pd[3]; tp_index(D, p, pd); return pd[0] + pd[1] + pd[2]; }
+static double tp_norm(int D, int p) { int pd[3]; tp_index(D, p, pd); double n = 1.0; for (int d = 0; d < D; ++d) n *= factorial(pd[d]); return n; }
+
+/* Hermite coefficients on the tensor-product basis of a complete-basis
+ * equilibrium: a_p = rho prod_d E[He_{p_d}(X_d)], X_d ~ N(u_d, theta), i.e.
+ * per axis 1, u, u^2 + theta - 1 (the components of eq:trans-a applied to the
+ * relative-frame Maxwellian coefficients). */
+static void tp_maxwell(int D, double rho, const double *u_xi, double theta, double *a)
+{
+    for (int p = 0; p < n_tp(D); ++p) {
+        int pd[3];
+        tp_index(D, p, pd);
+        double v = rho;
+        for (int d = 0; d < D; ++d) {
+            double u = u_xi[d];
+            v *= (pd[d] == 0) ? 1.0 : (pd[d] == 1 ? u : u * u + theta - 1.0);
+        }
+        a[p] = v;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Equilibria                                                                */
+/* ------------------------------------------------------------------------- */
+
+/* Discrete equilibrium f0_i, eq:fi applied to the Maxwellian coefficients:
+ *   D2Q9/D3Q27: complete tensor-product basis (every resolved central moment
+ *               is the Maxwellian's);
+ *   D2Q37:      Hermite truncation at order M = 4 (Sec. II.B). */
+static void h37_init(const orc_lattice *L);
+static double g_H37[ORC_MAXQ][31];
+
+static void equilibrium(const orc_lattice *L, int kind, double rho, const double *u_xi, double theta, double *f0)
+{
+    if (kind == ORC_D2Q37) {
+        const int D = 2, M = 4;
+        double a[1 + 2 + 4 + 8 + 16];
+        h37_init(L);
+        maxwell_coeffs(D, M, rho, u_xi, theta, a);
+        for (int i = 0; i < L->Q; ++i) {
+            const double *H = g_H37[i];  /* H^(0..4)(xi_i) */
+            double s = 0.0;
+            for (int n = 0; n <= M; ++n) s += t_contract(D, n, a + t_offset(D, n), H + t_offset(D, n)) / factorial(n);
+            f0[i] = L->w[i] * s;
+        }
+    } else {
+        int D = L->D;
+        double a[27];
+        const double (*Ht)[27] = tp_table(L);
+        tp_maxwell(D, rho, u_xi, theta, a);
+        for (int i = 0; i < L->Q; ++i) {
+            double s = 0.0;
+            for (int p = 0; p < n_tp(D); ++p) s += a[p] * Ht[p][i] / tp_norm(D, p);
+            f0[i] = L->w[i] * s;
+        }
+    }
+}
+
+int orc_equilibrium(int kind, double rho, const double *u_lat, double theta, double *f0)
+{
+    const orc_lattice *L = lattice(kind);
+    if (!L) return -1;
+    double u_xi[3] = {0, 0, 0};
+    for (int d = 0; d < L->D; ++d) u_xi[d] = L->r * u_lat[d];
+    equilibrium(L, kind, rho, u_xi, theta, f0);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Collision, D2Q9 / D3Q27 (complete basis)                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Paper's route (Sec. II.C, last paragraph): f1 = f - f0 -> Hermite
+ * coefficients a1 (eq:an) -> a_Omega -> Omega_i (eq:fi) -> f* = f^ + Omega.
+ * On the complete basis f^ = f, and eq:omega "for all n" fixes a_Omega:
+ * map a1 to central monomial moments with the binomial transform, scale
+ * each by -omega_{|p|}, and map back.  On the raw-MRT switch a_Omega =
+ * -omega_n a1 (eq:regnmrt); on regularised BGK every order uses omega[2]. */
+static void collide_tp(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+{
+    int D = L->D, n = n_tp(D);
+    double rho, u[3], th;
+    node_moments(L, f, &rho, u, &th);
+    if (!cfg->thermal) th = cfg->theta0;
+    const double (*Ht)[27] = tp_table(L);
+    double af[27], aeq[27], a1[27], k1[27], kO[27], aO[27];
+    for (int p = 0; p < n; ++p) {
+        double s = 0.0;
+        for (int i = 0; i < L->Q; ++i) s += f[i] * Ht[p][i];   /* eq:an */
+        af[p] = s;
+    }
+    tp_maxwell(D, rho, u, th, aeq);
+    for (int p = 0; p < n; ++p) a1[p] = af[p] - aeq[p];
+    double om[8];
+    for (int k = 0; k < 8; ++k) om[k] = (cfg->model == ORC_REG_BGK) ? cfg->omega[2] : cfg->omega[k];
+    om[0] = om[1] = 0.0;  /* mass and momentum are conserved: a1 vanishes there */
+    if (cfg->model == ORC_CM) {
+        double P[3][3][3], Pi[3][3][3];
+        for (int d = 0; d < 3; ++d) { axis_herm_to_central(u[d], P[d]); axis_central_to_herm(u[d], Pi[d]); }
+        tp_apply(D, (const double(*)[3][3])P, a1, k1);
+        for (int p = 0; p < n; ++p) kO[p] = -om[tp_order(D, p)] * k1[p];
+        tp_apply(D, (const double(*)[3][3])Pi, kO, aO);
+    } else {
+        for (int p = 0; p < n; ++p) aO[p] = -om[tp_order(D, p)] * a1[p];
+    }
+    for (int i = 0; i < L->Q; ++i) {
+        double s = 0.0;
+        for (int p = 0; p < n; ++p) s += (af[p] + aO[p]) * Ht[p][i] / tp_norm(D, p);   /* eq:fi */
+        out[i] = L->w[i] * s;
+    }
+}
+
+/* Definition (eq:omega for every central moment the lattice resolves): with
+ * K_{p,i} = prod_d (e_{i,d} - u_d)^{p_d} (lattice units), kappa = K f and
+ * kappa_eq,p = rho prod_d m(p_d), m = (1, 0, theta/r^2), the post-collision
+ * state solves K f* = kappa - omega_{|p|} (kappa - kappa_eq). */
+static int collide_tp_definitional(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+{
+    int D = L->D, Q = L->Q;
+    double rho, u[3], th;
+    node_moments(L, f, &rho, u, &th);
+    if (!cfg->thermal) th = cfg->theta0;
+    double ul[3] = {u[0] / L->r, u[1] / L->r, u[2] / L->r};
+    double K[27 * 27], ks[27];
+    for (int p = 0; p < Q; ++p) {
+        int pd[3];
+        tp_index(D, p, pd);
+        double kap = 0.0, keq = rho;
+        for (int i = 0; i < Q; ++i) {
+            double m = 1.0;
+            for (int d = 0; d < D; ++d) m *= pow(L->e[i][d] - ul[d], pd[d]);
+            K[p * Q + i] = m;
+            kap += m * f[i];
+        }
+        for (int d = 0; d < D; ++d) keq *= (pd[d] == 0) ? 1.0 : (pd[d] == 1 ? 0.0 : th / (L->r * L->r));
+        int ord = pd[0] + pd[1] + pd[2];
+        double om = (ord < 2) ? 0.0 : ((cfg->model == ORC_REG_BGK) ? cfg->omega[2] : cfg->omega[ord]);
+        ks[p] = kap - om * (kap - keq);
+    }
+    if (solve_dense(Q, K, ks)) return -1;
+    for (int i = 0; i < Q; ++i) out[i] = ks[i];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Collision, D2Q37 (N = M = 4, Sec. II.C)                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Hermite tensors of the 37 abscissas, built once. */
+static int g_H37_ok;
+
+static void h37_init(const orc_lattice *L)
+{
+    if (g_H37_ok) return;
+    for (int i = 0; i < L->Q; ++i) {
+        double xi[2] = {L->r * L->e[i][0], L->r * L->e[i][1]};
+        hermite_tensors(2, 4, xi, g_H37[i]);
+    }
+    g_H37_ok = 1;
+}
+
+/* The paper's procedure for the truncated basis:
+ *  1. rho, u, theta (theta frozen at theta0 when isothermal);
+ *  2. f0 = the order-4 Hermite equilibrium;
+ *  3. a1^(n) = sum_i (f_i - f0_i) H^(n)(xi_i), n = 2, 3, 4 (eq:an);
+ *  4. a_Omega^(n) from eq:mrt, with the delta term of the fourth order
+ *     carrying cfg->delta_coef (6 satisfies eq:omega; the paper prints 72);
+ *     raw MRT uses -omega_n a1^(n), regularised BGK -omega a1^(n) (eq:regnmrt);
+ *  5. f*_i = f^_i + Omega_i, where f^ is the order-4 projection of eq:reg and
+ *     Omega_i = w_i sum_n a_Omega^(n):H^(n)(xi_i)/n! (eq:fi). */
+static void collide_d2q37(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+{
+    const int D = 2, N = 4;
+    h37_init(L);
+    double rho, u[3], th;
+    node_moments(L, f, &rho, u, &th);
+    if (!cfg->thermal) th = cfg->theta0;
+    double f0[ORC_MAXQ], af[31], a1[31], aO[31];
+    equilibrium(L, ORC_D2Q37, rho, u, th, f0);
+    memset(af, 0, sizeof(af));
+    memset(a1, 0, sizeof(a1));
+    for (int i = 0; i < L->Q; ++i)
+        for (int k = 0; k < 31; ++k) {
+            af[k] += f[i] * g_H37[i][k];
+            a1[k] += (f[i] - f0[i]) * g_H37[i][k];
+        }
+    memset(aO, 0, sizeof(aO));
+    const double *A2 = a1 + t_offset(D, 2), *A3 = a1 + t_offset(D, 3), *A4 = a1 + t_offset(D, 4);
+    double *O2 = aO + t_offset(D, 2), *O3 = aO + t_offset(D, 3), *O4 = aO + t_offset(D, 4);
+    if (cfg->model == ORC_CM) {
+        double w2 = cfg->omega[2], w3 = cfg->omega[3], w4 = cfg->omega[4];
+        double delta[4], uu[4], ua2[8], ua3[16], uua2[16], da2[16];
+        t_delta(D, delta);
+        t_symprod(D, 1, u, 1, u, uu);
+        t_symprod(D, 1, u, 2, A2, ua2);
+        t_symprod(D, 1, u, 3, A3, ua3);
+        t_symprod(D, 2, uu, 2, A2, uua2);
+        t_symprod(D, 2, delta, 2, A2, da2);
+        for (int k = 0; k < 4; ++k) O2[k] = -w2 * A2[k];                                   /* eq:mrt-a */
+        for (int k = 0; k < 8; ++k) O3[k] = -w3 * A3[k] + 3.0 * (w3 - w2) * ua2[k];         /* eq:mrt-b */
+        for (int k = 0; k < 16; ++k)
+            O4[k] = -w4 * A4[k] + 4.0 * (w4 - w3) * ua3[k]
+                  - 6.0 * (w4 + w2 - 2.0 * w3) * uua2[k] - cfg->delta_coef * (w4 - w2) * da2[k];
+    } else {
+        for (int n = 2; n <= N; ++n) {
+            double om = (cfg->model == ORC_REG_BGK) ? cfg->omega[2] : cfg->omega[n];
+            for (int k = t_offset(D, n); k < t_offset(D, n + 1); ++k) aO[k] = -om * a1[k];
+        }
+    }
+    for (int i = 0; i < L->Q; ++i) {
+        double s = 0.0;
+        for (int n = 0; n <= N; ++n) {
+            int o = t_offset(D, n);
+            s += t_contract(D, n, af + o, g_H37[i] + o) / factorial(n);
+            s += t_contract(D, n, aO + o, g_H37[i] + o) / factorial(n);
+        }
+        out[i] = L->w[i] * s;
+    }
+}
+
+/* Definitional form for D2Q37: f* lies in the span of w_i H_m(xi_i) (the 15
+ * components of order <= 4) and its central monomial moments of order <= 4
+ * are sum_i f*_i c_i^p = (1 - omega_{|p|}) sum_i f_i c_i^p + omega_{|p|} rho mu_px mu_py,
+ * with mu the Gaussian central moments (1, 0, theta, 0, 3 theta^2) (eq:omega
+ * for every resolved order).  Solved as a 15 x 15 system. */
+static int collide_d2q37_definitional(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+{
+    double rho, u[3], th;
+    node_moments(L, f, &rho, u, &th);
+    if (!cfg->thermal) th = cfg->theta0;
+    int basis[15][2], nb = 0;
+    for (int n = 0; n <= 4; ++n)
+        for (int k = 0; k <= n; ++k) { basis[nb][0] = k; basis[nb][1] = n - k; ++nb; }
+    double mu[5] = {1.0, 0.0, th, 0.0, 3.0 * th * th};
+    double A[225], rhs[15];
+    for (int row = 0; row < 15; ++row) {
+        int px = basis[row][0], py = basis[row][1], ord = px + py;
+        double kap = 0.0;
+        for (int i = 0; i < L->Q; ++i) {
+            double cx = L->r * L->e[i][0] - u[0], cy = L->r * L->e[i][1] - u[1];
+            kap += f[i] * pow(cx, px) * pow(cy, py);
+        }
+        double om = (ord < 2) ? 0.0 : ((cfg->model == ORC_REG_BGK) ? cfg->omega[2] : cfg->omega[ord]);
+        rhs[row] = (1.0 - om) * kap + om * rho * mu[px] * mu[py];
+        for (int col = 0; col < 15; ++col) {
+            double s = 0.0;
+            for (int i = 0; i < L->Q; ++i) {
+                double xx = L->r * L->e[i][0], yy = L->r * L->e[i][1];
+                double phi = L->w[i] * he1d(basis[col][0], xx) * he1d(basis[col][1], yy);
+                s += phi * pow(xx - u[0], px) * pow(yy - u[1], py);
+            }
+            A[row * 15 + col] = s;
+        }
+    }
+    if (solve_dense(15, A, rhs)) return -1;
+    for (int i = 0; i < L->Q; ++i) {
+        double xx = L->r * L->e[i][0], yy = L->r * L->e[i][1], s = 0.0;
+        for (int col = 0; col < 15; ++col) s += rhs[col] * L->w[i] * he1d(basis[col][0], xx) * he1d(basis[col][1], yy);
+        out[i] = s;
+    }
+    return 0;
+}
+
+static void build_tables(const orc_lattice *L, int kind)
+{
+    if (kind == ORC_D2Q37) h37_init(L);
+    else (void)tp_table(L);
+}
+
+static int collide_node(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+{
+    if (cfg->lattice == ORC_D2Q37) collide_d2q37(L, cfg, f, out);
+    else collide_tp(L, cfg, f, out);
+    return 0;
+}
+
+int orc_collide(const orc_cfg *cfg, int n_nodes, const double *f, double *out)
+{
+    const orc_lattice *L = lattice(cfg->lattice);
+    if (!L) return -1;
+    if (cfg->lattice == ORC_D2Q37) h37_init(L);
+    for (int k = 0; k < n_nodes; ++k) collide_node(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q);
+    return 0;
+}
+
+int orc_collide_definitional(const orc_cfg *cfg, int n_nodes, const double *f, double *out)
+{
+    const orc_lattice *L = lattice(cfg->lattice);
+    if (!L) return -1;
+    for (int k = 0; k < n_nodes; ++k) {
+        int rc = (cfg->lattice == ORC_D2Q37)
+            ? collide_d2q37_definitional(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q)
+            : collide_tp_definitional(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Periodic grid: state, streaming, steps (eq:lbgk update form)              */
+/* ------------------------------------------------------------------------- */
+/* State S_t: post-collision populations, layout S[i][z][y][x] (x fastest).
+ * One step: S_{t+1}(x)_i = C[ S_t(x - e_i)_i ]  (pull, then collide), which is
+ * the update f_i(x + xi_i, t + 1) = f*_i(x, t) re-indexed. */
+
+static inline size_t wrap(long v, long n) { v %= n; if (v < 0) v += n; return (size_t)v; }
+
+static void gather(const orc_lattice *L, long nx, long ny, long nz, const double *S, long x, long y, long z, double *f)
+{
+    size_t plane = (size_t)nx * ny * nz;
+    for (int i = 0; i < L->Q; ++i) {
+        size_t xs = wrap(x - L->e[i][0], nx), ys = wrap(y - L->e[i][1], ny), zs = wrap(z - L->e[i][2], nz);
+        f[i] = S[i * plane + (zs * ny + ys) * nx + xs];
+    }
+}
+
+int orc_run(const orc_cfg *cfg, long nx, long ny, long nz, double *S, long nsteps, int nthreads)
+{
+    const orc_lattice *L = lattice(cfg->lattice);
+    if (!L || nx < 1 || ny < 1 || nz < 1) return -1;
+    if (L->D == 2 && nz != 1) return -1;
+    if (cfg->lattice == ORC_D2Q37) h37_init(L);
+    size_t plane = (size_t)nx * ny * nz;
+    double *T = (double *)malloc(sizeof(double) * plane * L->Q);
+    if (!T) return -2;
+    for (long s = 0; s < nsteps; ++s) {
+        #pragma omp parallel for collapse(2) schedule(static) num_threads(nthreads)
+        for (long z = 0; z < nz; ++z)
+            for (long y = 0; y < ny; ++y)
+                for (long x = 0; x < nx; ++x) {
+                    double f[ORC_MAXQ], o[ORC_MAXQ];
+                    gather(L, nx, ny, nz, S, x, y, z, f);
+                    collide_node(L, cfg, f, o);
+                    size_t node = ((size_t)z * ny + y) * nx + x;
+                    for (int i = 0; i < L->Q; ++i) T[i * plane + node] = o[i];
+                }
+        memcpy(S, T, sizeof(double) * plane * L->Q);
+    }
+    free(T);
+    return 0;
+}
+
+/* One step evaluated only at the listed nodes (flat index (z*ny+y)*nx+x);
+ * out[k*Q + i] receives population i of node k. */
+int orc_step_nodes(const orc_cfg *cfg, long nx, long ny, long nz, const double *S,
+                   long n_nodes, const int64_t *nodes, double *out, int nthreads)
+{
+    const orc_lattice *L = lattice(cfg->lattice);
+    if (!L) return -1;
+    if (cfg->lattice == ORC_D2Q37) h37_init(L);
+    #pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (long k = 0; k < n_nodes; ++k) {
+        long idx = (long)nodes[k];
+        long x = idx % nx, y = (idx / nx) % ny, z = idx / (nx * ny);
+        double f[ORC_MAXQ];
+        gather(L, nx, ny, nz, S, x, y, z, f);
+        collide_node(L, cfg, f, out + (size_t)k * L->Q);
+    }
+    return 0;
+}
+
+/* Equilibrium initial state S_0 = f0(rho, u, theta); u in lattice units,
+ * fields laid out [comp][z][y][x]; theta may be NULL (then cfg->theta0). */
+int orc_init_equilibrium(const orc_cfg *cfg, long nx, long ny, long nz,
+                         const double *rho, const double *u, const double *theta, double *S, int nthreads)
+{
+    const orc_lattice *L = lattice(cfg->lattice);
+    if (!L) return -1;
+    size_t plane = (size_t)nx * ny * nz;
+    #pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (long n = 0; n < (long)plane; ++n) {
+        double ux[3] = {0, 0, 0}, f0[ORC_MAXQ];
+        for (int d = 0; d < L->D; ++d) ux[d] = L->r * u[d * plane + n];
+        equilibrium(L, cfg->lattice, rho[n], ux, theta ? theta[n] : cfg->theta0, f0);
+        for (int i = 0; i < L->Q; ++i) S[i * plane + n] = f0[i];
+    }
+    return 0;
+}
+
+/* Macroscopic fields of a state: rho, u (lattice units, [d][node]) and theta. */
+int orc_moments(int kind, long n_nodes, const double *S, double *rho, double *u, double *theta)
+{
+    const orc_lattice *L = lattice(kind);
+    if (!L) return -1;
+    for (long n = 0; n < n_nodes; ++n) {
+        double f[ORC_MAXQ], r_, ux[3], th;
+        for (int i = 0; i < L->Q; ++i) f[i] = S[i * n_nodes + n];
+        node_moments(L, f, &r_, ux, &th);
+        rho[n] = r_;
+        for (int d = 0; d < L->D; ++d) u[d * n_nodes + n] = ux[d] / L->r;
+        if (theta) theta[n] = th;
+    }
+    return 0;
+}
