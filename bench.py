@@ -1,0 +1,197 @@
+"""Benchmark: CM-MRT fused stream + collide, D3Q27 256^3 FP32, one MI355X.
+
+Workload: 3D Taylor-Green vortex on a 256^3 periodic grid, u0 = 0.05,
+Re = 1600 with L = N / (2 pi) (nu = u0 L / Re, tau_2 = 1/2 + 3 nu), central
+moments of order >= 3 relaxed at rate 1.  Populations are FP32 deviations
+f_i - w_i rho0 in HBM (27 planes of 256^3).  A step is one launch of the
+fused pull-stream + collide kernel over every node.
+
+Prints one JSON line: MLUPS (million lattice-node updates per second, whole
+job), ms per step, the kernel's HBM roofline (algorithmic bytes 2 Q s = 216 B
+per node update against MI355X's 8 TB/s), and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 256
+U0 = 0.05
+RE = 1600.0
+Q = 27
+STORAGE_BYTES = 4
+PEAK_HBM_GBS = 8000.0
+KERNEL = "k_step_tp<3, kF32>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q27_256_f32.json")
+KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/kernels.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
+                  "paper_1808_04406_amd/csrc/common.hpp"]
+
+
+def tau_shear(n=N, u0=U0, re=RE):
+    nu = u0 * (n / (2.0 * math.pi)) / re
+    return 0.5 + 3.0 * nu
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(tau, target_s=12.0):
+    """FP64 oracle (plain C, OpenMP) on the same TGV at 64^3: a bounded sample
+    of the workload, timed on the host cores; reported in MLUPS."""
+    import numpy as np
+    import oracle
+    from paper_1808_04406_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    n = 64
+    cfg = oracle.Cfg(lattice="D3Q27", tau={2: tau}, tau_hi=1.0)
+    rho, u = inputs.tgv3d(n, U0)
+    S = oracle.init_equilibrium(cfg, rho, u, threads=threads)
+    t0 = time.perf_counter()
+    oracle.run(cfg, S, 1, threads=threads)
+    one = time.perf_counter() - t0
+    steps = max(1, int(target_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.run(cfg, S, steps, threads=threads)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(S).all()
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"D3Q27 TGV 64^3 (same u0, tau), {steps} steps after 1 warm-up step, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def copy_bandwidth(torch, nbytes=4 << 30, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time) with torch."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+              "domain decomposition is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1808_04406_amd import cmlb, inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    tau = tau_shear()
+    nodes = N ** 3
+    nbytes = Q * nodes * STORAGE_BYTES
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ctx = cmlb.Context("D3Q27", (N, N, N), storage="f32", tau={2: tau}, external=bufs, stream=stream)
+
+    rho, u = inputs.tgv3d(N, U0)
+    d_rho = torch.from_numpy(rho.reshape(-1)).to("cuda")
+    d_u = torch.from_numpy(u.reshape(-1)).to("cuda")
+    ctx.init_fields_device(d_rho, d_u)
+    torch.cuda.synchronize()
+    del d_rho, d_u
+    mass0 = float(rho.sum())
+
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kernel_ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
+
+    g = ctx.reduce()
+    assert g["nonfinite"] == 0, "simulation diverged"
+    assert abs(g["mass"] - mass0) / mass0 < 1e-5, "mass not conserved"
+    ctx.destroy()
+    del bufs
+    torch.cuda.empty_cache()
+
+    copy_gbs = copy_bandwidth(torch)
+
+    value = nodes * args.steps / wall / 1e6
+    alg_bytes = 2 * Q * STORAGE_BYTES * nodes
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(alg_bytes)
+    out = {
+        "metric": "MLUPS of CM-MRT stream+collide, % HBM roofline; error vs FP64 oracle",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / max(args.steps, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D3Q27 CM-MRT 256^3 periodic 3D Taylor-Green vortex, u0=0.05, Re=1600, "
+                               "FP32 deviation storage",
+                   "lattice": "D3Q27", "grid": [N, N, N], "storage": "f32", "tau_shear": round(tau, 6),
+                   "tau_higher": 1.0, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": KERNEL, "kernel_ms": round(kernel_ms, 5),
+                     "bytes_per_node_update": 2 * Q * STORAGE_BYTES,
+                     "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(tau)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

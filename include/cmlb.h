@@ -1,0 +1,170 @@
+/*
+ * cmlb: central-moment multiple-relaxation-time lattice Boltzmann on MI355X.
+ *
+ * C ABI of the library that advances the fused pull-stream-and-collide update
+ * of X. Shan, "A central-moment multiple-relaxation-time collision model"
+ * (arXiv:1808.04406) on a periodic grid, on one AMD Instinct GPU (gfx950).
+ *
+ * The update (Sec. II.C, final equation) is f_i(x + xi_i, t + 1) = f^_i + Omega_i:
+ * every node gathers its populations, forms rho, u (and theta on the thermal
+ * lattice), relaxes each order n of central moments at its own rate omega_n
+ * = 1/tau_n (eq:omega), maps the result back to the absolute frame on the
+ * fixed velocities (eq:mrt, eq:fi) and stores the post-collision populations.
+ *
+ * Conventions shared by every call:
+ *  - Lattices (the quadrature of eq:quad, xi_i = r e_i):
+ *      CMLB_D2Q9   e in {-1,0,1}^2, r = sqrt(3), complete tensor-product basis;
+ *      CMLB_D3Q27  e in {-1,0,1}^3, r = sqrt(3), complete tensor-product basis;
+ *      CMLB_D2Q37  e in Z^2 with |e|^2 <= 10, ninth-degree rule (r ~ 1.19698),
+ *                  order-4 Hermite truncation N = M = 4 (Sec. II.B).
+ *    Population order: D2Q9/D3Q27 i = (ex+1) + 3(ey+1) + 9(ez+1); D2Q37
+ *    lexicographic in (ey, ex), both from -3 to 3.
+ *  - Host arrays of fields and populations are FP64, structure of arrays,
+ *    x fastest: fields [component][z][y][x], populations [i][z][y][x].
+ *    Velocities are in lattice units (cells per step); theta is the paper's
+ *    dimensionless temperature (1 is the lattice reference).
+ *  - The state is the post-collision population field; one step pulls
+ *    f_i(x - e_i) and collides (the paper's push update re-indexed).
+ *  - Every function returns CMLB_OK (0) or a negative error code; a failing
+ *    call leaves the context unchanged and cmlb_last_error() describes it.
+ *    No C++ exception crosses this interface.
+ *  - Ownership: the library never keeps a host pointer after a call returns.
+ *    It owns the device buffers it allocates; buffers passed to
+ *    cmlb_create_external stay owned by the caller and must outlive the
+ *    context.
+ */
+#ifndef CMLB_H
+#define CMLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMLB_OK 0
+#define CMLB_EINVAL (-1)    /* bad argument */
+#define CMLB_ENOMEM (-2)    /* device or host allocation failed */
+#define CMLB_EDEVICE (-3)   /* HIP runtime or kernel launch error */
+#define CMLB_ESTATE (-4)    /* call not valid in the current state */
+#define CMLB_EUNSTABLE (-5) /* non-finite populations found (divergence) */
+
+enum { CMLB_D2Q9 = 0, CMLB_D3Q27 = 1, CMLB_D2Q37 = 2 };
+
+/* Storage of the population field.  Every type stores the deviation
+ * g_i = s_i (f_i - w_i rho0); arithmetic is FP64 for CMLB_F64 and FP32 for
+ * the others.  s_i is a power of two (1 for F64/F32/BF16; for F16 chosen
+ * from w_i so that |f_i - w_i rho0| up to 8 w_i stays representable). */
+enum { CMLB_F64 = 0, CMLB_F32 = 1, CMLB_BF16 = 2, CMLB_F16 = 3 };
+
+/* Collision model.  CMLB_MODEL_CM is the paper's central-moment MRT
+ * (eq:omega, eq:mrt).  The two others are the comparison operators of
+ * eq:regnmrt: raw-moment MRT relaxes absolute-frame Hermite coefficients at
+ * per-order rates, regularised BGK (eq:lbgk-reg) relaxes every order at
+ * omega_2.  Raw MRT and regularised BGK are available on CMLB_D2Q37. */
+enum { CMLB_MODEL_CM = 0, CMLB_MODEL_RAW_MRT = 1, CMLB_MODEL_REG_BGK = 2 };
+
+typedef struct cmlb_params {
+    int32_t lattice;   /* CMLB_D2Q9, CMLB_D3Q27, CMLB_D2Q37 */
+    int32_t storage;   /* CMLB_F64, CMLB_F32, CMLB_BF16, CMLB_F16 */
+    int32_t model;     /* CMLB_MODEL_* */
+    int32_t thermal;   /* 1: theta follows from f (D2Q37 only); 0: theta frozen at theta0 */
+    int64_t nx, ny, nz;/* periodic grid; nz must be 1 for 2D lattices; D2Q37
+                          needs nx, ny >= 3 (its velocities reach 3 cells) */
+    double rho0;       /* reference density of the deviation storage (>0) */
+    double theta0;     /* frozen temperature of isothermal runs (>0) */
+    double tau[8];     /* tau[n]: relaxation time of central-moment order n
+                          (n >= 2; entries 0 and 1 ignored; 0 means 1.0) */
+    double scale[37];  /* storage scale s_i per population; 0 means automatic */
+    int32_t device;    /* HIP device ordinal */
+    int32_t reserved;  /* must be 0 */
+    void *hip_stream;  /* hipStream_t for all work, or NULL for a library stream */
+} cmlb_params;
+
+/* Global FP64 diagnostics of the current state (Sec. III.B's kinetic-energy
+ * history and the conservation checks).  momentum and energy are in lattice
+ * units: sum f e and sum f |e|^2 / 2; kinetic_energy = sum rho |u|^2 / 2;
+ * enstrophy = sum |curl u|^2 / 2 with second-order central differences
+ * (2D: the single vorticity component). */
+typedef struct cmlb_globals {
+    double mass;
+    double momentum[3];
+    double energy;
+    double kinetic_energy;
+    double enstrophy;
+    int64_t n_nonfinite;
+} cmlb_globals;
+
+typedef struct cmlb_ctx cmlb_ctx;
+
+/* Lattice table (eq:quad): D, Q, e[Q*3] (integers), w[Q], r.  Any output
+ * pointer may be NULL.  Host-only; needs no device. */
+int cmlb_lattice_info(int lattice, int *D, int *Q, int *e, double *w, double *r);
+
+/* Create a context: validates p, allocates two population buffers of
+ * Q * nx*ny*nz elements of the storage type on p->device.  The state is
+ * undefined until cmlb_init_fields or cmlb_set_populations.  On failure
+ * *out is NULL and cmlb_create_error() describes the reason. */
+int cmlb_create(const cmlb_params *p, cmlb_ctx **out);
+
+/* As cmlb_create, but the population buffers f_a and f_b are device memory
+ * owned by the caller (for example PyTorch tensors), each at least
+ * Q * nx*ny*nz elements of the storage type, 256-byte aligned, distinct. */
+int cmlb_create_external(const cmlb_params *p, void *f_a, void *f_b, cmlb_ctx **out);
+
+/* Reason for the last failed create on this thread. */
+const char *cmlb_create_error(void);
+
+/* Free the library-owned device memory and the context.  NULL is a no-op. */
+void cmlb_destroy(cmlb_ctx *ctx);
+
+/* Description of the last error on ctx ("" if none). */
+const char *cmlb_last_error(const cmlb_ctx *ctx);
+
+/* Replace tau_n for orders 2 .. 2+n-1 (tau_by_order[k] is tau of order k+2). */
+int cmlb_set_tau(cmlb_ctx *ctx, const double *tau_by_order, int n);
+
+/* Set the state to the discrete equilibrium of the given fields (host FP64,
+ * rho[node], u[D][node], theta[node] or NULL for theta0): the complete-basis
+ * equilibrium on D2Q9/D3Q27, the order-4 Hermite equilibrium on D2Q37
+ * (Sec. II.B, eq:maxwellian truncated). */
+int cmlb_init_fields(cmlb_ctx *ctx, const double *rho, const double *u, const double *theta);
+
+/* As cmlb_init_fields with the fields already in device memory. */
+int cmlb_init_fields_device(cmlb_ctx *ctx, const double *rho, const double *u, const double *theta);
+
+/* Enqueue n stream-and-collide steps on the context stream (asynchronous). */
+int cmlb_step(cmlb_ctx *ctx, int64_t n);
+
+/* Wait for all work enqueued on the context stream. */
+int cmlb_sync(cmlb_ctx *ctx);
+
+/* Read rho[node], u[D][node] (lattice units) and theta[node] of the state
+ * (host FP64; any pointer may be NULL).  Synchronises. */
+int cmlb_get_moments(cmlb_ctx *ctx, double *rho, double *u, double *theta);
+
+/* Read / write the full populations f_i (decoded, host FP64, [i][node]).
+ * Writing encodes to the storage type (round to nearest even). Synchronises. */
+int cmlb_get_populations(cmlb_ctx *ctx, double *f);
+int cmlb_set_populations(cmlb_ctx *ctx, const double *f);
+
+/* FP64 global diagnostics of the state (deterministic two-pass reduction).
+ * Returns CMLB_EUNSTABLE (with *out filled) if any population is not finite. */
+int cmlb_reduce(cmlb_ctx *ctx, cmlb_globals *out);
+
+/* Device pointer and byte size of the current population buffer, and the
+ * stream the library launches on (hipStream_t). */
+int cmlb_state(cmlb_ctx *ctx, void **f_cur, size_t *bytes, void **hip_stream);
+
+/* Number of steps taken since the last init or set. */
+int64_t cmlb_step_count(const cmlb_ctx *ctx);
+
+/* Storage scale s_i actually in use (Q values). */
+int cmlb_get_scale(const cmlb_ctx *ctx, double *scale);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMLB_H */

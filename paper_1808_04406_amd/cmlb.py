@@ -1,0 +1,237 @@
+"""Python binding of the cmlb C ABI (include/cmlb.h): argument marshalling only.
+
+Every step of the update runs in the HIP library ``libcmlb.so``; this module
+converts numpy arrays and torch streams/tensors to plain pointers and status
+codes to exceptions.  There is no fallback: if the library is missing the
+import of :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmlb.so")
+
+LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q37": 2}
+STORAGES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+MODELS = {"cm": 0, "raw_mrt": 1, "reg_bgk": 2}
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", EUNSTABLE: "EUNSTABLE"}
+
+
+class CmlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("thermal", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("rho0", ctypes.c_double), ("theta0", ctypes.c_double),
+                ("tau", ctypes.c_double * 8), ("scale", ctypes.c_double * 37),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+
+
+class Globals(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3), ("energy", ctypes.c_double),
+                ("kinetic_energy", ctypes.c_double), ("enstrophy", ctypes.c_double),
+                ("n_nonfinite", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcmlb.so (built by ``python -m paper_1808_04406_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1808_04406_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, c_int, c_i64, vp = ctypes.POINTER, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+        dp = P(ctypes.c_double)
+        L.cmlb_lattice_info.argtypes = [c_int, P(c_int), P(c_int), P(c_int), dp, dp]
+        L.cmlb_create.argtypes = [P(Params), P(vp)]
+        L.cmlb_create_external.argtypes = [P(Params), vp, vp, P(vp)]
+        L.cmlb_create_error.restype = ctypes.c_char_p
+        L.cmlb_destroy.argtypes = [vp]
+        L.cmlb_destroy.restype = None
+        L.cmlb_last_error.argtypes = [vp]
+        L.cmlb_last_error.restype = ctypes.c_char_p
+        L.cmlb_set_tau.argtypes = [vp, dp, c_int]
+        L.cmlb_init_fields.argtypes = [vp, dp, dp, dp]
+        L.cmlb_init_fields_device.argtypes = [vp, vp, vp, vp]
+        L.cmlb_step.argtypes = [vp, c_i64]
+        L.cmlb_sync.argtypes = [vp]
+        L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
+        L.cmlb_get_populations.argtypes = [vp, dp]
+        L.cmlb_set_populations.argtypes = [vp, dp]
+        L.cmlb_reduce.argtypes = [vp, P(Globals)]
+        L.cmlb_state.argtypes = [vp, P(vp), P(ctypes.c_size_t), P(vp)]
+        L.cmlb_step_count.argtypes = [vp]
+        L.cmlb_step_count.restype = c_i64
+        L.cmlb_get_scale.argtypes = [vp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lattice_info(kind: str) -> dict:
+    """cmlb_lattice_info: D, Q, e (Q,3), w (Q,), r."""
+    D, Q = ctypes.c_int(), ctypes.c_int()
+    e = np.zeros(37 * 3, np.int32)
+    w = np.zeros(37)
+    r = ctypes.c_double()
+    rc = lib().cmlb_lattice_info(LATTICES[kind], ctypes.byref(D), ctypes.byref(Q),
+                                 e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w), ctypes.byref(r))
+    if rc:
+        raise CmlbError(rc, "lattice_info failed")
+    q = Q.value
+    return dict(D=D.value, Q=q, e=e[:3 * q].reshape(q, 3).astype(np.int64), w=w[:q].copy(), r=r.value)
+
+
+def make_params(lattice, shape, storage="f32", model="cm", thermal=False, rho0=1.0, theta0=1.0,
+                tau=None, scale=None, device=0, stream=None) -> Params:
+    p = Params()
+    p.lattice = LATTICES[lattice]
+    p.storage = STORAGES[storage]
+    p.model = MODELS[model]
+    p.thermal = 1 if thermal else 0
+    if len(shape) == 2:
+        shape = (1,) + tuple(shape)
+    p.nz, p.ny, p.nx = (int(s) for s in shape)
+    p.rho0, p.theta0 = rho0, theta0
+    for n, t in (tau or {}).items():
+        p.tau[n] = t
+    if scale is not None:
+        for i, s in enumerate(scale):
+            p.scale[i] = s
+    p.device = device
+    p.reserved = 0
+    p.hip_stream = _stream_handle(stream)
+    return p
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class Context:
+    """One simulation context (cmlb_ctx*).  Methods mirror the C entry points."""
+
+    def __init__(self, lattice="D3Q27", shape=(32, 32, 32), storage="f32", model="cm", thermal=False,
+                 rho0=1.0, theta0=1.0, tau=None, scale=None, device=0, stream=None, external=None):
+        self.lattice, self.storage = lattice, storage
+        self.shape = tuple(shape)
+        self.info = lattice_info(lattice)
+        self.Q, self.D = self.info["Q"], self.info["D"]
+        self.nodes = int(np.prod(shape))
+        self.params = make_params(lattice, shape, storage, model, thermal, rho0, theta0, tau, scale,
+                                  device, stream)
+        self._external = external  # keep caller tensors alive
+        h = ctypes.c_void_p()
+        if external is None:
+            rc = lib().cmlb_create(ctypes.byref(self.params), ctypes.byref(h))
+        else:
+            fa, fb = (t.data_ptr() if hasattr(t, "data_ptr") else int(t) for t in external)
+            rc = lib().cmlb_create_external(ctypes.byref(self.params), fa, fb, ctypes.byref(h))
+        if rc:
+            raise CmlbError(rc, lib().cmlb_create_error().decode())
+        self.h = h
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc):
+        if rc:
+            raise CmlbError(rc, lib().cmlb_last_error(self.h).decode())
+
+    def _field(self, a, comps=1):
+        a = np.ascontiguousarray(a, np.float64)
+        if a.size != comps * self.nodes:
+            raise ValueError(f"expected {comps}x{self.nodes} values, got {a.size}")
+        return a
+
+    # -- entry points ------------------------------------------------------
+    def destroy(self):
+        if getattr(self, "h", None):
+            lib().cmlb_destroy(self.h)
+            self.h = None
+
+    close = destroy
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_tau(self, tau_by_order):
+        t = np.ascontiguousarray(tau_by_order, np.float64)
+        self._check(lib().cmlb_set_tau(self.h, _dp(t), len(t)))
+
+    def init_fields(self, rho, u, theta=None):
+        rho = self._field(rho)
+        u = self._field(u, self.D)
+        th = None if theta is None else self._field(theta)
+        self._check(lib().cmlb_init_fields(self.h, _dp(rho), _dp(u), _dp(th)))
+
+    def init_fields_device(self, rho, u, theta=None):
+        """Fields as float64 device tensors (torch) of nodes / D*nodes elements."""
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self._check(lib().cmlb_init_fields_device(self.h, ptr(rho), ptr(u), ptr(theta)))
+
+    def step(self, n=1):
+        self._check(lib().cmlb_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib().cmlb_sync(self.h))
+
+    def get_moments(self):
+        shape = self.shape
+        rho = np.zeros(shape)
+        u = np.zeros((self.D,) + shape)
+        th = np.zeros(shape)
+        self._check(lib().cmlb_get_moments(self.h, _dp(rho), _dp(u), _dp(th)))
+        return rho, u, th
+
+    def get_populations(self):
+        f = np.zeros((self.Q,) + self.shape)
+        self._check(lib().cmlb_get_populations(self.h, _dp(f)))
+        return f
+
+    def set_populations(self, f):
+        f = self._field(f, self.Q)
+        self._check(lib().cmlb_set_populations(self.h, _dp(f)))
+
+    def reduce(self, allow_unstable=False):
+        g = Globals()
+        rc = lib().cmlb_reduce(self.h, ctypes.byref(g))
+        if rc and not (allow_unstable and rc == EUNSTABLE):
+            self._check(rc)
+        return dict(mass=g.mass, momentum=np.array(list(g.momentum)), energy=g.energy,
+                    ke=g.kinetic_energy, enstrophy=g.enstrophy, nonfinite=g.n_nonfinite)
+
+    def state(self):
+        p, n, s = ctypes.c_void_p(), ctypes.c_size_t(), ctypes.c_void_p()
+        self._check(lib().cmlb_state(self.h, ctypes.byref(p), ctypes.byref(n), ctypes.byref(s)))
+        return p.value, n.value, s.value
+
+    def step_count(self):
+        return lib().cmlb_step_count(self.h)
+
+    def get_scale(self):
+        s = np.zeros(37)
+        self._check(lib().cmlb_get_scale(self.h, _dp(s)))
+        return s[:self.Q]

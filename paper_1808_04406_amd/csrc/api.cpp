@@ -1,0 +1,523 @@
+// C ABI of the cmlb library: context management, validation, lattice tables,
+// and the host side of every entry point declared in include/cmlb.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cmlb.h"
+#include "launch.hpp"
+
+using namespace cmlb;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HostLattice {
+    int D = 0, Q = 0;
+    int e[37][3] = {};
+    double w[37] = {};
+    double r = 0.0;
+    double wcls[8] = {};
+};
+
+// D2Q37 weights per |e|^2 class and the scale r.  The nine even-moment
+// conditions of a degree-9 rule, sum_i w_i xi_x^p xi_y^q = E[X^p] E[Y^q]
+// with xi = r e, are solved for the eight class weights and x = 1/r^2 by
+// Newton's method (the conditions are linear in w and polynomial in x).
+bool solve_d2q37(double (&wcls)[8], double& r) {
+    static const int mons[9][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}, {8, 0}, {6, 2}, {4, 4}};
+    auto gm = [](int p) { double m = 1.0; if (p % 2) return 0.0; for (int k = p - 1; k > 0; k -= 2) m *= k; return m; };
+    double S[9][8] = {};
+    for (int i = 0; i < 37; ++i) {
+        const int ex = kTab37.ex[i], ey = kTab37.ey[i], c = kTab37.cls[i];
+        for (int k = 0; k < 9; ++k) S[k][c] += std::pow((double)ex, mons[k][0]) * std::pow((double)ey, mons[k][1]);
+    }
+    double v[9];
+    for (int c = 0; c < 8; ++c) v[c] = 1.0 / 37.0;
+    v[8] = 0.5;
+    for (int it = 0; it < 100; ++it) {
+        double J[9][10];
+        double norm = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            const int h = (mons[k][0] + mons[k][1]) / 2;
+            const double g = gm(mons[k][0]) * gm(mons[k][1]);
+            double F = -g * std::pow(v[8], h);
+            for (int c = 0; c < 8; ++c) { F += S[k][c] * v[c]; J[k][c] = S[k][c]; }
+            J[k][8] = h ? -g * h * std::pow(v[8], h - 1) : 0.0;
+            J[k][9] = -F;
+            norm += F * F;
+        }
+        // Gaussian elimination with partial pivoting on the augmented system
+        for (int col = 0; col < 9; ++col) {
+            int piv = col;
+            for (int row = col + 1; row < 9; ++row)
+                if (std::fabs(J[row][col]) > std::fabs(J[piv][col])) piv = row;
+            if (J[piv][col] == 0.0) return false;
+            for (int k = 0; k < 10; ++k) std::swap(J[col][k], J[piv][k]);
+            for (int row = col + 1; row < 9; ++row) {
+                const double m = J[row][col] / J[col][col];
+                for (int k = col; k < 10; ++k) J[row][k] -= m * J[col][k];
+            }
+        }
+        double dv[9];
+        for (int row = 8; row >= 0; --row) {
+            double s = J[row][9];
+            for (int k = row + 1; k < 9; ++k) s -= J[row][k] * dv[k];
+            dv[row] = s / J[row][row];
+        }
+        for (int k = 0; k < 9; ++k) v[k] += dv[k];
+        if (norm < 1e-30 && it > 3) break;
+    }
+    for (int c = 0; c < 8; ++c) {
+        if (!(v[c] > 0.0)) return false;
+        wcls[c] = v[c];
+    }
+    if (!(v[8] > 0.0)) return false;
+    r = 1.0 / std::sqrt(v[8]);
+    return true;
+}
+
+bool host_lattice(int kind, HostLattice& L) {
+    if (kind == CMLB_D2Q9 || kind == CMLB_D3Q27) {
+        const int D = (kind == CMLB_D2Q9) ? 2 : 3;
+        static const double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+        L.D = D;
+        L.Q = (D == 2) ? 9 : 27;
+        L.r = std::sqrt(3.0);
+        for (int i = 0; i < L.Q; ++i) {
+            const int ix = i % 3, iy = (i / 3) % 3, iz = (D == 3) ? i / 9 : 1;
+            L.e[i][0] = ix - 1;
+            L.e[i][1] = iy - 1;
+            L.e[i][2] = (D == 3) ? iz - 1 : 0;
+            L.w[i] = w1[ix] * w1[iy] * (D == 3 ? w1[iz] : 1.0);
+        }
+        return true;
+    }
+    if (kind == CMLB_D2Q37) {
+        static bool done = false;
+        static double wc[8], r;
+        if (!done) {
+            if (!solve_d2q37(wc, r)) return false;
+            done = true;
+        }
+        L.D = 2;
+        L.Q = 37;
+        L.r = r;
+        for (int c = 0; c < 8; ++c) L.wcls[c] = wc[c];
+        for (int i = 0; i < 37; ++i) {
+            L.e[i][0] = kTab37.ex[i];
+            L.e[i][1] = kTab37.ey[i];
+            L.e[i][2] = 0;
+            L.w[i] = wc[kTab37.cls[i]];
+        }
+        return true;
+    }
+    return false;
+}
+
+size_t storage_bytes(int st) { return st == CMLB_F64 ? 8 : st == CMLB_F32 ? 4 : 2; }
+
+}  // namespace
+
+struct cmlb_ctx {
+    cmlb_params p{};
+    HostLattice L;
+    uint64_t nodes = 0;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool owns = true;
+    bool own_stream = false;
+    bool initialised = false;
+    hipStream_t stream = nullptr;
+    double omega[8] = {};
+    float s[37] = {}, inv_s[37] = {};
+    int64_t steps = 0;
+    std::string err;
+    // reduction scratch (allocated on first use)
+    double* red_u = nullptr;
+    double* red_p = nullptr;
+    double* red_out = nullptr;
+};
+
+namespace {
+
+int fail(cmlb_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(cmlb_ctx* c, hipError_t e, const char* where) {
+    return fail(c, CMLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+StepArgs base_args(const cmlb_ctx* c) {
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = make_grid((uint32_t)c->p.nx, (uint32_t)c->p.ny, (uint32_t)c->p.nz);
+    a.rho0 = c->p.rho0;
+    a.theta0 = c->p.theta0;
+    for (int n = 0; n < 8; ++n) a.omega[n] = c->omega[n];
+    for (int i = 0; i < 37; ++i) {
+        a.s[i] = c->s[i];
+        a.inv_s[i] = c->inv_s[i];
+    }
+    a.r = c->L.r;
+    for (int k = 0; k < 8; ++k) a.wcls[k] = c->L.wcls[k];
+    a.thermal = c->p.thermal;
+    return a;
+}
+
+void set_omegas(cmlb_ctx* c) {
+    for (int n = 0; n < 8; ++n) {
+        const double t = (n < 2) ? 1.0 : (c->p.tau[n] == 0.0 ? 1.0 : c->p.tau[n]);
+        c->omega[n] = (n < 2) ? 0.0 : 1.0 / t;
+    }
+    if (c->p.model == CMLB_MODEL_REG_BGK)
+        for (int n = 3; n < 8; ++n) c->omega[n] = c->omega[2];
+}
+
+std::string validate(const cmlb_params* p) {
+    if (!p) return "params is NULL";
+    if (p->lattice < CMLB_D2Q9 || p->lattice > CMLB_D2Q37) return "unknown lattice";
+    if (p->storage < CMLB_F64 || p->storage > CMLB_F16) return "unknown storage";
+    if (p->model < CMLB_MODEL_CM || p->model > CMLB_MODEL_REG_BGK) return "unknown collision model";
+    if (p->model != CMLB_MODEL_CM && p->lattice != CMLB_D2Q37)
+        return "raw-moment MRT and regularised BGK are implemented for D2Q37 only";
+    if (p->thermal && p->lattice != CMLB_D2Q37) return "thermal mode needs the D2Q37 lattice";
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid sizes must be >= 1";
+    if (p->lattice != CMLB_D3Q27 && p->nz != 1) return "2D lattices need nz == 1";
+    // the D2Q37 gather wraps shifts of up to 3 cells with a single correction
+    if (p->lattice == CMLB_D2Q37 && (p->nx < 3 || p->ny < 3)) return "D2Q37 needs nx, ny >= 3";
+    if (p->nx > (1 << 20) || p->ny > (1 << 20) || p->nz > (1 << 20)) return "grid size too large";
+    const int Q = (p->lattice == CMLB_D2Q9) ? 9 : (p->lattice == CMLB_D3Q27 ? 27 : 37);
+    const double nodes = (double)p->nx * (double)p->ny * (double)p->nz;
+    if (nodes * Q >= 4294967296.0 * 8) return "grid too large";
+    if ((uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz >= (1ull << 32)) return "more than 2^32 nodes";
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return "rho0 must be positive";
+    if (!(p->theta0 > 0.0) || !std::isfinite(p->theta0)) return "theta0 must be positive";
+    for (int n = 2; n < 8; ++n) {
+        const double t = p->tau[n];
+        if (t != 0.0 && !(t > 0.0 && std::isfinite(t))) return "tau must be positive (0 = default 1.0)";
+    }
+    for (int i = 0; i < Q; ++i) {
+        const double s = p->scale[i];
+        if (s != 0.0 && !(s > 0.0 && std::isfinite(s))) return "scale must be positive (0 = automatic)";
+    }
+    if (p->reserved != 0) return "reserved must be 0";
+    return "";
+}
+
+int create_impl(const cmlb_params* p, void* fa, void* fb, cmlb_ctx** out) {
+    if (!out) { g_create_error = "out is NULL"; return CMLB_EINVAL; }
+    *out = nullptr;
+    std::string why = validate(p);
+    if (!why.empty()) { g_create_error = why; return CMLB_EINVAL; }
+    cmlb_ctx* c = new (std::nothrow) cmlb_ctx();
+    if (!c) { g_create_error = "host allocation failed"; return CMLB_ENOMEM; }
+    c->p = *p;
+    if (!host_lattice(p->lattice, c->L)) {
+        delete c;
+        g_create_error = "lattice table generation failed";
+        return CMLB_EINVAL;
+    }
+    c->nodes = (uint64_t)p->nx * p->ny * p->nz;
+    set_omegas(c);
+    for (int i = 0; i < c->L.Q; ++i) {
+        double s = p->scale[i];
+        if (s == 0.0) {
+            s = 1.0;
+            if (p->storage == CMLB_F16) {
+                // largest power of two with 16 w_i rho0 s_i <= 65504 / 2
+                s = std::exp2(std::floor(std::log2(32752.0 / (16.0 * c->L.w[i] * p->rho0))));
+            }
+        }
+        c->s[i] = (float)s;
+        c->inv_s[i] = (float)(1.0 / s);
+    }
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) { g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e); delete c; return CMLB_EDEVICE; }
+    if (p->hip_stream) {
+        c->stream = (hipStream_t)p->hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e); delete c; return CMLB_EDEVICE; }
+        c->own_stream = true;
+    }
+    const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(p->storage);
+    if (fa || fb) {
+        if (!fa || !fb || fa == fb || ((uintptr_t)fa % 256) || ((uintptr_t)fb % 256)) {
+            g_create_error = "external buffers must be two distinct non-NULL 256-byte aligned pointers";
+            cmlb_destroy(c);
+            return CMLB_EINVAL;
+        }
+        c->f[0] = fa;
+        c->f[1] = fb;
+        c->owns = false;
+    } else {
+        for (int k = 0; k < 2; ++k) {
+            e = hipMalloc(&c->f[k], bytes);
+            if (e != hipSuccess) {
+                g_create_error = std::string("hipMalloc population buffer: ") + hipGetErrorString(e);
+                (void)hipGetLastError();
+                cmlb_destroy(c);
+                return CMLB_ENOMEM;
+            }
+        }
+    }
+    *out = c;
+    return CMLB_OK;
+}
+
+// Device staging for host FP64 arrays.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+}  // namespace
+
+extern "C" {
+
+int cmlb_lattice_info(int lattice, int* D, int* Q, int* e, double* w, double* r) {
+    HostLattice L;
+    if (!host_lattice(lattice, L)) return CMLB_EINVAL;
+    if (D) *D = L.D;
+    if (Q) *Q = L.Q;
+    if (r) *r = L.r;
+    for (int i = 0; i < L.Q; ++i) {
+        if (w) w[i] = L.w[i];
+        if (e)
+            for (int d = 0; d < 3; ++d) e[3 * i + d] = L.e[i][d];
+    }
+    return CMLB_OK;
+}
+
+int cmlb_create(const cmlb_params* p, cmlb_ctx** out) { return create_impl(p, nullptr, nullptr, out); }
+
+int cmlb_create_external(const cmlb_params* p, void* f_a, void* f_b, cmlb_ctx** out) {
+    if (!f_a || !f_b) {
+        g_create_error = "external buffers must not be NULL";
+        if (out) *out = nullptr;
+        return CMLB_EINVAL;
+    }
+    return create_impl(p, f_a, f_b, out);
+}
+
+const char* cmlb_create_error(void) { return g_create_error.c_str(); }
+
+void cmlb_destroy(cmlb_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->p.device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->owns)
+        for (int k = 0; k < 2; ++k)
+            if (c->f[k]) (void)hipFree(c->f[k]);
+    if (c->red_u) (void)hipFree(c->red_u);
+    if (c->red_p) (void)hipFree(c->red_p);
+    if (c->red_out) (void)hipFree(c->red_out);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* cmlb_last_error(const cmlb_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+int cmlb_set_tau(cmlb_ctx* c, const double* tau, int n) {
+    if (!c) return CMLB_EINVAL;
+    if (!tau || n < 1 || n > 6) return fail(c, CMLB_EINVAL, "tau array must hold 1..6 orders (2..7)");
+    for (int k = 0; k < n; ++k)
+        if (!(tau[k] > 0.0) || !std::isfinite(tau[k])) return fail(c, CMLB_EINVAL, "tau must be positive and finite");
+    for (int k = 0; k < n; ++k) c->p.tau[k + 2] = tau[k];
+    set_omegas(c);
+    return CMLB_OK;
+}
+
+static int init_device_fields(cmlb_ctx* c, const double* rho, const double* u, const double* theta) {
+    StepArgs a = base_args(c);
+    a.dst = c->f[c->cur];
+    FieldArgs fa{};
+    fa.rho = rho;
+    fa.u = u;
+    fa.theta = theta;
+    if (launch_init(c->p.lattice, c->p.storage, a, fa, c->stream)) return fail(c, CMLB_EINVAL, "unsupported configuration");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel launch");
+    c->initialised = true;
+    c->steps = 0;
+    return CMLB_OK;
+}
+
+int cmlb_init_fields_device(cmlb_ctx* c, const double* rho, const double* u, const double* theta) {
+    if (!c) return CMLB_EINVAL;
+    if (!rho || !u) return fail(c, CMLB_EINVAL, "rho and u are required");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    return init_device_fields(c, rho, u, theta);
+}
+
+int cmlb_init_fields(cmlb_ctx* c, const double* rho, const double* u, const double* theta) {
+    if (!c) return CMLB_EINVAL;
+    if (!rho || !u) return fail(c, CMLB_EINVAL, "rho and u are required");
+    for (uint64_t n = 0; n < c->nodes; ++n)
+        if (!(rho[n] > 0.0) || !std::isfinite(rho[n])) return fail(c, CMLB_EINVAL, "rho must be positive and finite");
+    if (theta)
+        for (uint64_t n = 0; n < c->nodes; ++n)
+            if (!(theta[n] > 0.0) || !std::isfinite(theta[n])) return fail(c, CMLB_EINVAL, "theta must be positive and finite");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    const int D = c->L.D;
+    const size_t fb = c->nodes * sizeof(double);
+    DevBuf buf;
+    hipError_t e = hipMalloc(&buf.p, fb * (D + 2));
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(c, CMLB_ENOMEM, "staging allocation failed"); }
+    double* d_rho = (double*)buf.p;
+    double* d_u = d_rho + c->nodes;
+    double* d_th = d_u + (size_t)D * c->nodes;
+    if ((e = hipMemcpyAsync(d_rho, rho, fb, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return hip_fail(c, e, "copy rho");
+    if ((e = hipMemcpyAsync(d_u, u, fb * D, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return hip_fail(c, e, "copy u");
+    if (theta && (e = hipMemcpyAsync(d_th, theta, fb, hipMemcpyHostToDevice, c->stream)) != hipSuccess) return hip_fail(c, e, "copy theta");
+    int rc = init_device_fields(c, d_rho, d_u, theta ? d_th : nullptr);
+    if (rc) return rc;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "init");
+    return CMLB_OK;
+}
+
+int cmlb_step(cmlb_ctx* c, int64_t n) {
+    if (!c) return CMLB_EINVAL;
+    if (n < 0) return fail(c, CMLB_EINVAL, "negative step count");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    StepArgs a = base_args(c);
+    for (int64_t k = 0; k < n; ++k) {
+        a.src = c->f[c->cur];
+        a.dst = c->f[1 - c->cur];
+        if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream))
+            return fail(c, CMLB_EINVAL, "unsupported configuration");
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+        c->cur = 1 - c->cur;
+        c->steps++;
+    }
+    return CMLB_OK;
+}
+
+int cmlb_sync(cmlb_ctx* c) {
+    if (!c) return CMLB_EINVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sync");
+    return CMLB_OK;
+}
+
+int cmlb_get_moments(cmlb_ctx* c, double* rho, double* u, double* theta) {
+    if (!c) return CMLB_EINVAL;
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    const int D = c->L.D;
+    const size_t fb = c->nodes * sizeof(double);
+    DevBuf buf;
+    hipError_t e = hipMalloc(&buf.p, fb * (D + 2));
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(c, CMLB_ENOMEM, "staging allocation failed"); }
+    StepArgs a = base_args(c);
+    a.src = c->f[c->cur];
+    FieldArgs fa{};
+    fa.out_rho = (double*)buf.p;
+    fa.out_u = fa.out_rho + c->nodes;
+    fa.out_theta = fa.out_u + (size_t)D * c->nodes;
+    launch_moments(c->p.lattice, c->p.storage, a, fa, c->stream);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "moments kernel launch");
+    if (rho && (e = hipMemcpyAsync(rho, fa.out_rho, fb, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy rho");
+    if (u && (e = hipMemcpyAsync(u, fa.out_u, fb * D, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy u");
+    if (theta && (e = hipMemcpyAsync(theta, fa.out_theta, fb, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy theta");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "moments");
+    return CMLB_OK;
+}
+
+static int codec(cmlb_ctx* c, double* f, bool decode) {
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    const size_t bytes = c->nodes * c->L.Q * sizeof(double);
+    DevBuf buf;
+    hipError_t e = hipMalloc(&buf.p, bytes);
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(c, CMLB_ENOMEM, "staging allocation failed"); }
+    StepArgs a = base_args(c);
+    if (!decode && (e = hipMemcpyAsync(buf.p, f, bytes, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy populations");
+    launch_codec(c->p.lattice, c->p.storage, decode, c->f[c->cur], (double*)buf.p, a, c->L.w, c->stream);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "codec kernel launch");
+    if (decode && (e = hipMemcpyAsync(f, buf.p, bytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy populations");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "codec");
+    return CMLB_OK;
+}
+
+int cmlb_get_populations(cmlb_ctx* c, double* f) {
+    if (!c) return CMLB_EINVAL;
+    if (!f) return fail(c, CMLB_EINVAL, "f is NULL");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    return codec(c, f, true);
+}
+
+int cmlb_set_populations(cmlb_ctx* c, const double* f) {
+    if (!c) return CMLB_EINVAL;
+    if (!f) return fail(c, CMLB_EINVAL, "f is NULL");
+    int rc = codec(c, const_cast<double*>(f), false);
+    if (rc == CMLB_OK) {
+        c->initialised = true;
+        c->steps = 0;
+    }
+    return rc;
+}
+
+int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
+    if (!c) return CMLB_EINVAL;
+    if (!out) return fail(c, CMLB_EINVAL, "out is NULL");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    hipError_t e;
+    const int nb = reduce_blocks(c->nodes);
+    if (!c->red_u) {
+        if ((e = hipMalloc(&c->red_u, c->nodes * 3 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_u = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+        if ((e = hipMalloc(&c->red_p, (size_t)nb * 16 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_p = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+        if ((e = hipMalloc(&c->red_out, 8 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_out = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+    }
+    StepArgs a = base_args(c);
+    a.src = c->f[c->cur];
+    launch_reduce(c->p.lattice, c->p.storage, a, c->red_u, c->red_p, c->red_p + (size_t)nb * 8, c->red_out, c->stream);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+    double v[8];
+    if ((e = hipMemcpyAsync(v, c->red_out, sizeof(v), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "reduce");
+    double we2 = 0.0;
+    for (int i = 0; i < c->L.Q; ++i)
+        we2 += c->L.w[i] * (c->L.e[i][0] * c->L.e[i][0] + c->L.e[i][1] * c->L.e[i][1] + c->L.e[i][2] * c->L.e[i][2]);
+    out->mass = c->p.rho0 * (double)c->nodes + v[0];
+    out->momentum[0] = v[1];
+    out->momentum[1] = v[2];
+    out->momentum[2] = v[3];
+    out->energy = 0.5 * (v[4] + c->p.rho0 * we2 * (double)c->nodes);
+    out->kinetic_energy = v[5];
+    out->enstrophy = v[6];
+    out->n_nonfinite = (int64_t)v[7];
+    if (out->n_nonfinite > 0) return fail(c, CMLB_EUNSTABLE, "non-finite populations in the state");
+    return CMLB_OK;
+}
+
+int cmlb_state(cmlb_ctx* c, void** f_cur, size_t* bytes, void** stream) {
+    if (!c) return CMLB_EINVAL;
+    if (f_cur) *f_cur = c->f[c->cur];
+    if (bytes) *bytes = (size_t)c->nodes * c->L.Q * storage_bytes(c->p.storage);
+    if (stream) *stream = (void*)c->stream;
+    return CMLB_OK;
+}
+
+int64_t cmlb_step_count(const cmlb_ctx* c) { return c ? c->steps : -1; }
+
+int cmlb_get_scale(const cmlb_ctx* c, double* scale) {
+    if (!c || !scale) return CMLB_EINVAL;
+    for (int i = 0; i < c->L.Q; ++i) scale[i] = c->s[i];
+    return CMLB_OK;
+}
+
+}  // extern "C"

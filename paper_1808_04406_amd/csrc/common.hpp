@@ -1,0 +1,167 @@
+// Shared device-side definitions of the cmlb HIP library: storage codecs,
+// compile-time lattice tables, kernel argument blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+namespace cmlb {
+
+enum Lattice { kD2Q9 = 0, kD3Q27 = 1, kD2Q37 = 2 };
+enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
+enum Model { kCM = 0, kRawMRT = 1, kRegBGK = 2 };
+
+// ---------------------------------------------------------------------------
+// Compile-time loops: the body receives std::integral_constant<int, I>, so
+// every lattice index used inside is a constant expression and the population
+// arrays stay in registers.
+// ---------------------------------------------------------------------------
+template <int I, int N, class F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lattice velocity tables.
+// D2Q9 / D3Q27: e in {-1,0,1}^D, index i = (ex+1) + 3(ey+1) + 9(ez+1).
+// D2Q37: e in Z^2 with |e|^2 <= 10, ordered lexicographically in (ey, ex);
+// the ordering is centrally symmetric, so -e_i is population 36 - i and the
+// rest population is 18.  cls(i) numbers the weight classes by |e|^2.
+// ---------------------------------------------------------------------------
+struct TabD37 {
+    int ex[37], ey[37], cls[37];
+};
+
+constexpr int d37_norm_class(int n2) {
+    // |e|^2 takes the values 0, 1, 2, 4, 5, 8, 9, 10
+    return n2 == 0 ? 0 : n2 == 1 ? 1 : n2 == 2 ? 2 : n2 == 4 ? 3 : n2 == 5 ? 4 : n2 == 8 ? 5 : n2 == 9 ? 6 : 7;
+}
+
+constexpr TabD37 make_tab_d37() {
+    TabD37 t{};
+    int k = 0;
+    for (int ey = -3; ey <= 3; ++ey)
+        for (int ex = -3; ex <= 3; ++ex)
+            if (ex * ex + ey * ey <= 10) {
+                t.ex[k] = ex;
+                t.ey[k] = ey;
+                t.cls[k] = d37_norm_class(ex * ex + ey * ey);
+                ++k;
+            }
+    return t;
+}
+
+inline constexpr TabD37 kTab37 = make_tab_d37();
+static_assert(kTab37.ex[36] == 1 && kTab37.ey[36] == 3, "D2Q37 table");
+static_assert(kTab37.ex[18] == 0 && kTab37.ey[18] == 0, "D2Q37 rest population");
+
+template <int D>
+struct TP {
+    static constexpr int Q = (D == 2) ? 9 : 27;
+    static constexpr int ex(int i) { return i % 3 - 1; }
+    static constexpr int ey(int i) { return (i / 3) % 3 - 1; }
+    static constexpr int ez(int i) { return D == 3 ? i / 9 - 1 : 0; }
+};
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  The stored value is g = s (f - w rho0); decode returns the
+// deviation in the arithmetic type R.  16-bit encodes round to nearest even.
+// Stores are non-temporal: the output is not read again within a step.
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Store;
+
+template <>
+struct Store<kF64> {
+    using T = double;
+    using R = double;
+    static constexpr bool kScaled = false;
+    __device__ static R load(const T* p) { return *p; }
+    __device__ static void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __host__ __device__ static double to_double(T v) { return v; }
+    __host__ __device__ static T from_double(double v) { return v; }
+};
+
+template <>
+struct Store<kF32> {
+    using T = float;
+    using R = float;
+    static constexpr bool kScaled = false;
+    __device__ static R load(const T* p) { return *p; }
+    __device__ static void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __host__ __device__ static double to_double(T v) { return v; }
+    __host__ __device__ static T from_double(double v) { return (float)v; }
+};
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float v) {
+    uint32_t b = __builtin_bit_cast(uint32_t, v);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);  // quiet NaN
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+template <>
+struct Store<kBF16> {
+    using T = uint16_t;
+    using R = float;
+    static constexpr bool kScaled = true;
+    __device__ static R load(const T* p) { return bf16_to_f32(*p); }
+    __device__ static void store(T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
+    __host__ __device__ static double to_double(T v) { return bf16_to_f32(v); }
+    __host__ __device__ static T from_double(double v) { return f32_to_bf16_rne((float)v); }
+};
+
+template <>
+struct Store<kF16> {
+    using T = uint16_t;
+    using R = float;
+    static constexpr bool kScaled = true;
+    __device__ static R load(const T* p) { return (float)__builtin_bit_cast(_Float16, *p); }
+    __device__ static void store(T* p, R v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (_Float16)v), p);
+    }
+    __device__ static double to_double(T v) { return (double)__builtin_bit_cast(_Float16, v); }
+    __device__ static T from_double(double v) { return __builtin_bit_cast(uint16_t, (_Float16)(float)v); }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks (passed by value).
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    uint32_t nx, ny, nz;
+    uint32_t nchunks;   // x chunks of blockDim.x per row
+    uint64_t plane;     // nx * ny * nz
+};
+
+struct StepArgs {
+    const void* src;
+    void* dst;
+    GridArgs g;
+    double rho0;
+    double theta0;      // frozen temperature (isothermal)
+    double omega[8];    // omega[n] = 1 / tau_n
+    float s[37];        // storage scale per population
+    float inv_s[37];
+    double r;           // D2Q37 abscissa scale
+    double wcls[8];     // D2Q37 weight per |e|^2 class
+    int thermal;
+};
+
+struct FieldArgs {
+    const double* rho;
+    const double* u;      // [D][node], lattice units
+    const double* theta;  // may be null
+    double* out_rho;
+    double* out_u;
+    double* out_theta;
+};
+
+}  // namespace cmlb

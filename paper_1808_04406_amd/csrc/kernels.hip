@@ -1,0 +1,522 @@
+// HIP kernels of the cmlb library (gfx950) and their host launchers.
+//
+//  k_step_tp / k_step_d37   fused pull-stream + collide (the hot path)
+//  k_init_*                 state <- discrete equilibrium of given fields
+//  k_moments                rho, u, theta readout (FP64)
+//  k_decode / k_encode      full FP64 populations <-> storage
+//  k_reduce_*               deterministic FP64 global diagnostics
+//
+// Layout: populations are structure-of-arrays F[i][z][y][x], x fastest, in
+// the storage type.  The step kernel runs one thread per node; a block covers
+// one contiguous x-segment of a row, so the y/z neighbour rows of every
+// population are block-uniform addresses and each wavefront reads and writes
+// 27 (37) contiguous runs.  Two buffers alternate (pull from one, write the
+// other), so reads and writes never alias.
+#include "launch.hpp"
+
+#include "collide_d2q37.hpp"
+#include "collide_tp.hpp"
+
+namespace cmlb {
+
+__device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+
+// source coordinate v - e (periodic), |e| <= 3, for the D2Q37 gather
+__device__ __forceinline__ uint32_t wrap_sub(uint32_t v, int e, uint32_t n) {
+    int s = (int)v - e;
+    s += (s < 0) ? (int)n : 0;
+    s -= (s >= (int)n) ? (int)n : 0;
+    return (uint32_t)s;
+}
+
+// ---------------------------------------------------------------------------
+// Hot path: D2Q9 / D3Q27 stream + collide
+// ---------------------------------------------------------------------------
+template <int D, int ST>
+__global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
+    using S = Store<ST>;
+    using R = typename S::R;
+    using T = typename S::T;
+    constexpr int Q = TP<D>::Q;
+    const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const uint32_t chunk = blockIdx.x % a.g.nchunks;
+    const uint32_t row = blockIdx.x / a.g.nchunks;
+    const uint32_t x = chunk * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const uint32_t y = row % ny, z = row / ny;
+    const T* __restrict__ src = static_cast<const T*>(a.src);
+    T* __restrict__ dst = static_cast<T*>(a.dst);
+    const uint32_t xsrc[3] = {wrap_inc(x, nx), x, wrap_dec(x, nx)};  // x - e for e = -1, 0, +1
+    const uint32_t ysrc[3] = {wrap_inc(y, ny), y, wrap_dec(y, ny)};
+    const uint32_t zsrc[3] = {D == 3 ? wrap_inc(z, nz) : 0u, z, D == 3 ? wrap_dec(z, nz) : 0u};
+
+    R h[Q];
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = TP<D>::ex(i), ey = TP<D>::ey(i), ez = TP<D>::ez(i);
+        const T* rowp = src + (uint64_t)i * a.g.plane + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * nx;
+        R v = S::load(rowp + xsrc[ex + 1]);
+        if constexpr (S::kScaled) v *= R(a.inv_s[i]);
+        h[i] = v;
+    });
+
+    R om[8];
+    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
+    tp_collide<D, R>(h, R(a.rho0), om);
+
+    const uint64_t node = ((uint64_t)z * ny + y) * nx + x;
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        R v = h[i];
+        if constexpr (S::kScaled) v *= R(a.s[i]);
+        S::store(dst + (uint64_t)i * a.g.plane + node, v);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Hot path: D2Q37 stream + collide (order-4 Hermite truncation)
+// ---------------------------------------------------------------------------
+template <int ST, int MODEL>
+__global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
+    using S = Store<ST>;
+    using R = typename S::R;
+    using T = typename S::T;
+    const uint32_t nx = a.g.nx, ny = a.g.ny;
+    const uint32_t chunk = blockIdx.x % a.g.nchunks;
+    const uint32_t y = blockIdx.x / a.g.nchunks;
+    const uint32_t x = chunk * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const T* __restrict__ src = static_cast<const T*>(a.src);
+    T* __restrict__ dst = static_cast<T*>(a.dst);
+
+    R h[37];
+    static_for<0, 37>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
+        const uint32_t ys = wrap_sub(y, ey, ny);
+        const uint32_t xs = wrap_sub(x, ex, nx);
+        const T* rowp = src + (uint64_t)i * a.g.plane + (uint64_t)ys * nx;
+        R v = S::load(rowp + xs);
+        if constexpr (S::kScaled) v *= R(a.inv_s[i]);
+        h[i] = v;
+    });
+
+    R om[8];
+    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
+    R wc[8];
+    static_for<0, 8>([&](auto N) { wc[decltype(N)::value] = R(a.wcls[decltype(N)::value]); });
+    d37_collide<MODEL, R>(h, R(a.rho0), om, R(a.r), wc, a.thermal != 0, R(a.theta0));
+
+    const uint64_t node = (uint64_t)y * nx + x;
+    static_for<0, 37>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        R v = h[i];
+        if constexpr (S::kScaled) v *= R(a.s[i]);
+        S::store(dst + (uint64_t)i * a.g.plane + node, v);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation from fields (FP64 arithmetic, then encode)
+// ---------------------------------------------------------------------------
+template <int D, int ST>
+__global__ __launch_bounds__(256) void k_init_tp(StepArgs a, FieldArgs fa) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    constexpr int Q = TP<D>::Q;
+    T* dst = static_cast<T*>(a.dst);
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        double u[3] = {fa.u[n], fa.u[a.g.plane + n], D == 3 ? fa.u[2 * a.g.plane + n] : 0.0};
+        double h[Q];
+        tp_equilibrium<D, double>(h, fa.rho[n] - a.rho0, a.rho0, u);
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            dst[(uint64_t)i * a.g.plane + n] = S::from_double(h[i] * (double)a.s[i]);
+        });
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_init_d37(StepArgs a, FieldArgs fa) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    T* dst = static_cast<T*>(a.dst);
+    double wc[8];
+    for (int k = 0; k < 8; ++k) wc[k] = a.wcls[k];
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        const double th = fa.theta ? fa.theta[n] : a.theta0;
+        double h[37];
+        d37_equilibrium<double>(h, fa.rho[n] - a.rho0, a.rho0, a.r * fa.u[n], a.r * fa.u[a.g.plane + n],
+                                th - 1.0, a.r, wc);
+        static_for<0, 37>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            dst[(uint64_t)i * a.g.plane + n] = S::from_double(h[i] * (double)a.s[i]);
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Readout, codecs
+// ---------------------------------------------------------------------------
+template <int LAT>
+struct LatInfo;
+template <>
+struct LatInfo<kD2Q9> {
+    static constexpr int D = 2, Q = 9;
+    static constexpr int ex(int i) { return TP<2>::ex(i); }
+    static constexpr int ey(int i) { return TP<2>::ey(i); }
+    static constexpr int ez(int) { return 0; }
+};
+template <>
+struct LatInfo<kD3Q27> {
+    static constexpr int D = 3, Q = 27;
+    static constexpr int ex(int i) { return TP<3>::ex(i); }
+    static constexpr int ey(int i) { return TP<3>::ey(i); }
+    static constexpr int ez(int i) { return TP<3>::ez(i); }
+};
+template <>
+struct LatInfo<kD2Q37> {
+    static constexpr int D = 2, Q = 37;
+    static constexpr int ex(int i) { return kTab37.ex[i]; }
+    static constexpr int ey(int i) { return kTab37.ey[i]; }
+    static constexpr int ez(int) { return 0; }
+};
+
+// Sums of one node's deviation populations (FP64): sum h, sum h e, sum h |e|^2.
+template <int LAT, int ST>
+__device__ __forceinline__ void node_sums(const typename Store<ST>::T* src, uint64_t plane, uint64_t n,
+                                          const float* inv_s, double& s0, double (&j)[3], double& e2,
+                                          int& nonfinite) {
+    using S = Store<ST>;
+    using L = LatInfo<LAT>;
+    s0 = 0.0;
+    j[0] = j[1] = j[2] = 0.0;
+    e2 = 0.0;
+    nonfinite = 0;
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        double v = S::to_double(src[(uint64_t)i * plane + n]);
+        if constexpr (S::kScaled) v *= (double)inv_s[i];
+        nonfinite += (v - v != 0.0) ? 1 : 0;
+        s0 += v;
+        j[0] += L::ex(i) * v;
+        j[1] += L::ey(i) * v;
+        j[2] += L::ez(i) * v;
+        e2 += (L::ex(i) * L::ex(i) + L::ey(i) * L::ey(i) + L::ez(i) * L::ez(i)) * v;
+    });
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_moments(StepArgs a, FieldArgs fa) {
+    using L = LatInfo<LAT>;
+    using T = typename Store<ST>::T;
+    const T* src = static_cast<const T*>(a.src);
+    const double r2 = a.r * a.r;
+    // sum_i w_i |e_i|^2 = D / r^2 (second moment of the quadrature)
+    const double w_e2 = L::D / r2;
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        double s0, j[3], e2;
+        int nf;
+        node_sums<LAT, ST>(src, a.g.plane, n, a.inv_s, s0, j, e2, nf);
+        const double rho = a.rho0 + s0;
+        const double ux = j[0] / rho, uy = j[1] / rho, uz = j[2] / rho;
+        if (fa.out_rho) fa.out_rho[n] = rho;
+        if (fa.out_u) {
+            fa.out_u[n] = ux;
+            fa.out_u[a.g.plane + n] = uy;
+            if (L::D == 3) fa.out_u[2 * a.g.plane + n] = uz;
+        }
+        if (fa.out_theta) {
+            // rho (|u|^2 + D theta) = sum f |xi|^2, xi = r e
+            const double uu = ux * ux + uy * uy + uz * uz;
+            fa.out_theta[n] = r2 * ((e2 + a.rho0 * w_e2) / rho - uu) / L::D;
+        }
+    }
+}
+
+struct CodecArgs {
+    void* stor;
+    double* full;       // [Q][node]
+    uint64_t plane;
+    double rho0;
+    double w[37];
+    float s[37];
+    float inv_s[37];
+};
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_decode(CodecArgs c) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    const T* src = static_cast<const T*>(c.stor);
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < c.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        static_for<0, LatInfo<LAT>::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            double v = S::to_double(src[(uint64_t)i * c.plane + n]);
+            if constexpr (S::kScaled) v *= (double)c.inv_s[i];
+            c.full[(uint64_t)i * c.plane + n] = v + c.w[i] * c.rho0;
+        });
+    }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_encode(CodecArgs c) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    T* dst = static_cast<T*>(c.stor);
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < c.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        static_for<0, LatInfo<LAT>::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double v = (c.full[(uint64_t)i * c.plane + n] - c.w[i] * c.rho0) * (double)c.s[i];
+            dst[(uint64_t)i * c.plane + n] = S::from_double(v);
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions
+// ---------------------------------------------------------------------------
+constexpr int kRedVals = 8;  // drho, jx, jy, jz, e2, ke, enstrophy, nonfinite
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block sum of kRedVals values; thread 0 writes the block's partial row.
+__device__ __forceinline__ void block_partials(double (&v)[kRedVals], double* partials) {
+    __shared__ double lds[4][kRedVals];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < kRedVals; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < kRedVals; ++k) lds[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < kRedVals) {
+        double s = 0.0;
+        const int nw = blockDim.x >> 6;
+        for (int w = 0; w < nw; ++w) s += lds[w][threadIdx.x];
+        partials[(uint64_t)blockIdx.x * kRedVals + threadIdx.x] = s;
+    }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, double* partials) {
+    using T = typename Store<ST>::T;
+    const T* src = static_cast<const T*>(a.src);
+    double acc[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        double s0, j[3], e2;
+        int nf;
+        node_sums<LAT, ST>(src, a.g.plane, n, a.inv_s, s0, j, e2, nf);
+        const double rho = a.rho0 + s0;
+        const double ux = j[0] / rho, uy = j[1] / rho, uz = j[2] / rho;
+        acc[0] += s0;
+        acc[1] += j[0];
+        acc[2] += j[1];
+        acc[3] += j[2];
+        acc[4] += e2;
+        acc[5] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+        acc[7] += nf;
+        uf[n] = ux;
+        uf[a.g.plane + n] = uy;
+        uf[2 * a.g.plane + n] = uz;
+    }
+    block_partials(acc, partials);
+}
+
+// Enstrophy 1/2 |curl u|^2 with second-order central differences (periodic).
+__global__ __launch_bounds__(256) void k_reduce_vort(GridArgs g, int D, const double* uf, double* partials) {
+    double acc[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint64_t P = g.plane;
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < P;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = n % g.nx, y = (n / g.nx) % g.ny, z = n / ((uint64_t)g.nx * g.ny);
+        auto at = [&](int c, uint32_t xx, uint32_t yy, uint32_t zz) {
+            return uf[(uint64_t)c * P + ((uint64_t)zz * g.ny + yy) * g.nx + xx];
+        };
+        const uint32_t xp = x + 1 == g.nx ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
+        const uint32_t yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+        // d/dx of component c
+        const double dvy_dx = 0.5 * (at(1, xp, y, z) - at(1, xm, y, z));
+        const double dvx_dy = 0.5 * (at(0, x, yp, z) - at(0, x, ym, z));
+        double w2 = (dvy_dx - dvx_dy) * (dvy_dx - dvx_dy);
+        if (D == 3) {
+            const uint32_t zp = z + 1 == g.nz ? 0 : z + 1, zm = z == 0 ? g.nz - 1 : z - 1;
+            const double dvz_dy = 0.5 * (at(2, x, yp, z) - at(2, x, ym, z));
+            const double dvy_dz = 0.5 * (at(1, x, y, zp) - at(1, x, y, zm));
+            const double dvx_dz = 0.5 * (at(0, x, y, zp) - at(0, x, y, zm));
+            const double dvz_dx = 0.5 * (at(2, xp, y, z) - at(2, xm, y, z));
+            w2 += (dvz_dy - dvy_dz) * (dvz_dy - dvy_dz) + (dvx_dz - dvz_dx) * (dvx_dz - dvz_dx);
+        }
+        acc[6] += 0.5 * w2;
+    }
+    block_partials(acc, partials);
+}
+
+// Sum the partial rows of both passes in a fixed order.
+__global__ __launch_bounds__(64) void k_reduce_final(const double* p1, const double* p2, int nblocks, double* out) {
+    const int k = threadIdx.x;
+    if (k >= kRedVals) return;
+    const double* p = (k == 6) ? p2 : p1;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += p[(uint64_t)b * kRedVals + k];
+    out[k] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static void step_shape(const GridArgs& g, dim3& grid, dim3& block, uint32_t rows) {
+    uint32_t bs = g.nx >= 256 ? 256u : ((g.nx + 63u) / 64u) * 64u;
+    block = dim3(bs);
+    grid = dim3(g.nchunks * rows);
+}
+
+GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz) {
+    GridArgs g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    uint32_t bs = nx >= 256 ? 256u : ((nx + 63u) / 64u) * 64u;
+    g.nchunks = (nx + bs - 1) / bs;
+    g.plane = (uint64_t)nx * ny * nz;
+    return g;
+}
+
+static dim3 flat_grid(uint64_t n) {
+    uint64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return dim3((uint32_t)b);
+}
+
+template <int D, int ST>
+static void launch_tp(const StepArgs& a, hipStream_t s) {
+    dim3 grid, block;
+    step_shape(a.g, grid, block, a.g.ny * a.g.nz);
+    hipLaunchKernelGGL((k_step_tp<D, ST>), grid, block, 0, s, a);
+}
+
+template <int ST, int MODEL>
+static void launch_d37(const StepArgs& a, hipStream_t s) {
+    dim3 grid, block;
+    step_shape(a.g, grid, block, a.g.ny);
+    hipLaunchKernelGGL((k_step_d37<ST, MODEL>), grid, block, 0, s, a);
+}
+
+int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s) {
+#define CMLB_TP(D)                                                   \
+    switch (storage) {                                               \
+        case kF64: launch_tp<D, kF64>(a, s); return 0;               \
+        case kF32: launch_tp<D, kF32>(a, s); return 0;               \
+        case kBF16: launch_tp<D, kBF16>(a, s); return 0;             \
+        case kF16: launch_tp<D, kF16>(a, s); return 0;               \
+    }                                                                \
+    return -1;
+    if (lattice == kD2Q9) { CMLB_TP(2) }
+    if (lattice == kD3Q27) { CMLB_TP(3) }
+#undef CMLB_TP
+    if (lattice == kD2Q37) {
+        const bool raw = (model == kRawMRT);
+        switch (storage) {
+            case kF64: raw ? launch_d37<kF64, kRawMRT>(a, s) : launch_d37<kF64, kCM>(a, s); return 0;
+            case kF32: raw ? launch_d37<kF32, kRawMRT>(a, s) : launch_d37<kF32, kCM>(a, s); return 0;
+            case kBF16: raw ? launch_d37<kBF16, kRawMRT>(a, s) : launch_d37<kBF16, kCM>(a, s); return 0;
+            case kF16: raw ? launch_d37<kF16, kRawMRT>(a, s) : launch_d37<kF16, kCM>(a, s); return 0;
+        }
+    }
+    return -1;
+}
+
+template <int ST>
+static int launch_init_st(int lattice, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
+    dim3 grid = flat_grid(a.g.plane), block(256);
+    if (lattice == kD2Q9) hipLaunchKernelGGL((k_init_tp<2, ST>), grid, block, 0, s, a, f);
+    else if (lattice == kD3Q27) hipLaunchKernelGGL((k_init_tp<3, ST>), grid, block, 0, s, a, f);
+    else if (lattice == kD2Q37) hipLaunchKernelGGL((k_init_d37<ST>), grid, block, 0, s, a, f);
+    else return -1;
+    return 0;
+}
+
+int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
+    switch (storage) {
+        case kF64: return launch_init_st<kF64>(lattice, a, f, s);
+        case kF32: return launch_init_st<kF32>(lattice, a, f, s);
+        case kBF16: return launch_init_st<kBF16>(lattice, a, f, s);
+        case kF16: return launch_init_st<kF16>(lattice, a, f, s);
+    }
+    return -1;
+}
+
+#define CMLB_DISPATCH(LAUNCH)                                                     \
+    switch (lattice * 4 + storage) {                                              \
+        case kD2Q9 * 4 + kF64: LAUNCH(kD2Q9, kF64); break;                        \
+        case kD2Q9 * 4 + kF32: LAUNCH(kD2Q9, kF32); break;                        \
+        case kD2Q9 * 4 + kBF16: LAUNCH(kD2Q9, kBF16); break;                      \
+        case kD2Q9 * 4 + kF16: LAUNCH(kD2Q9, kF16); break;                        \
+        case kD3Q27 * 4 + kF64: LAUNCH(kD3Q27, kF64); break;                      \
+        case kD3Q27 * 4 + kF32: LAUNCH(kD3Q27, kF32); break;                      \
+        case kD3Q27 * 4 + kBF16: LAUNCH(kD3Q27, kBF16); break;                    \
+        case kD3Q27 * 4 + kF16: LAUNCH(kD3Q27, kF16); break;                      \
+        case kD2Q37 * 4 + kF64: LAUNCH(kD2Q37, kF64); break;                      \
+        case kD2Q37 * 4 + kF32: LAUNCH(kD2Q37, kF32); break;                      \
+        case kD2Q37 * 4 + kBF16: LAUNCH(kD2Q37, kBF16); break;                    \
+        case kD2Q37 * 4 + kF16: LAUNCH(kD2Q37, kF16); break;                      \
+        default: return -1;                                                       \
+    }
+
+int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
+    dim3 grid = flat_grid(a.g.plane), block(256);
+#define L_MOM(L, S) hipLaunchKernelGGL((k_moments<L, S>), grid, block, 0, s, a, f)
+    CMLB_DISPATCH(L_MOM)
+#undef L_MOM
+    return 0;
+}
+
+int launch_codec(int lattice, int storage, bool decode, void* stor, double* full, const StepArgs& a,
+                 const double* w, hipStream_t s) {
+    CodecArgs c;
+    c.stor = stor;
+    c.full = full;
+    c.plane = a.g.plane;
+    c.rho0 = a.rho0;
+    for (int i = 0; i < 37; ++i) {
+        c.w[i] = w[i];
+        c.s[i] = a.s[i];
+        c.inv_s[i] = a.inv_s[i];
+    }
+    dim3 grid = flat_grid(a.g.plane), block(256);
+#define L_DEC(L, S) hipLaunchKernelGGL((k_decode<L, S>), grid, block, 0, s, c)
+#define L_ENC(L, S) hipLaunchKernelGGL((k_encode<L, S>), grid, block, 0, s, c)
+    if (decode) {
+        CMLB_DISPATCH(L_DEC)
+    } else {
+        CMLB_DISPATCH(L_ENC)
+    }
+#undef L_DEC
+#undef L_ENC
+    return 0;
+}
+
+int reduce_blocks(uint64_t plane) { return (int)flat_grid(plane).x; }
+
+int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,
+                  hipStream_t s) {
+    dim3 grid = flat_grid(a.g.plane), block(256);
+#define L_RED(L, S) hipLaunchKernelGGL((k_reduce_nodes<L, S>), grid, block, 0, s, a, uf, p1)
+    CMLB_DISPATCH(L_RED)
+#undef L_RED
+    const int D = (lattice == kD3Q27) ? 3 : 2;
+    hipLaunchKernelGGL(k_reduce_vort, grid, block, 0, s, a.g, D, uf, p2);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, p1, p2, (int)grid.x, out);
+    return 0;
+}
+
+}  // namespace cmlb

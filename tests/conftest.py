@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def cm():
+    """The cmlb binding; builds libcmlb.so only if it is absent."""
+    from paper_1808_04406_amd import cmlb
+    if not os.path.exists(cmlb.LIB_PATH):
+        from paper_1808_04406_amd import build
+        build.build()
+    cmlb.lib()
+    return cmlb

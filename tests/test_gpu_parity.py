@@ -1,0 +1,307 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded and synthetic; both sides receive the same FP64 fields or
+populations.  For 16-bit storage the test quantises the FP64 input itself
+(numpy round-to-nearest-even through FP32, as the documented codec does), so
+that the oracle sees exactly the stored state; the remaining difference is
+FP32 arithmetic plus the rounding of the output.
+
+Tolerances (absolute, on populations f_i, relative to the largest deviation
+|f_i - w_i rho0| of the state, written per storage in TOL):
+  f64: 1e-13 (a few FP64 rounding steps of O(1) quantities, x10 margin);
+  f32: 2e-6  (about 30 FP32 roundings of the deviation scale);
+  f16: 2^-10 (one output ulp of an 11-bit significand, x2) plus f32 term;
+  bf16: 2^-7 (one output ulp of an 8-bit significand, x2) plus f32 term.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1808_04406_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-13, "f32": 2e-6, "f16": 2.0 ** -10 + 2e-6, "bf16": 2.0 ** -7 + 2e-6}
+
+
+def quantise(x, storage):
+    """Round FP64 values the way the storage codec does: FP64 -> FP32 -> 16-bit RNE."""
+    if storage == "f64":
+        return x.copy()
+    f = x.astype(np.float32)
+    if storage == "f32":
+        return f.astype(np.float64)
+    if storage == "f16":
+        return f.astype(np.float16).astype(np.float64)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) & 0xFFFF
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def f16_scales(w, rho0=1.0):
+    """Power-of-two scales for FP16 storage: largest s with 16 w rho0 s <= 32752."""
+    return np.exp2(np.floor(np.log2(32752.0 / (16.0 * w * rho0))))
+
+
+def random_state(orc, kind, shape, seed, thermal=False, eps=0.03):
+    cfg = orc.Cfg(lattice=kind, thermal=thermal)
+    rho, u, th = inputs.random_fields(shape, seed, drho=0.05, umax=0.06, dtheta=0.05 if thermal else 0.0)
+    S = orc.init_equilibrium(cfg, rho, u, th if thermal else None)
+    return S * inputs.perturbation(S.shape, seed + 1, eps)
+
+
+def taus(kind, seed):
+    rng = np.random.default_rng(seed)
+    hi = 5 if kind == "D2Q37" else 7
+    return {n: float(rng.uniform(0.52, 1.6)) for n in range(2, hi)}
+
+
+def one_step_case(cm, orc, kind, storage, shape, seed, thermal=False, model="cm"):
+    L = orc.lattice(kind)
+    w = L["w"]
+    S = random_state(orc, kind, shape, seed, thermal)
+    tau = taus(kind, seed + 7)
+    scale = f16_scales(w) if storage == "f16" else np.ones(L["Q"])
+    bshape = (L["Q"],) + (1,) * len(shape)
+    dev = (S - w.reshape(bshape)) * scale.reshape(bshape)
+    Sq = quantise(dev, storage) / scale.reshape(bshape) + w.reshape(bshape)
+    ctx = cm.Context(kind, shape, storage=storage, model=model, thermal=thermal, tau=tau,
+                     scale=scale if storage == "f16" else None)
+    try:
+        ctx.set_populations(S)
+        ctx.step(1)
+        got = ctx.get_populations()
+    finally:
+        ctx.destroy()
+    ref = Sq.copy()
+    orc.run(orc.Cfg(lattice=kind, tau=tau, thermal=thermal, model=model), ref, 1)
+    dev_scale = np.abs(ref - w.reshape(bshape)).max()
+    err = np.abs(got - ref).max()
+    return err, dev_scale
+
+
+CASES = [
+    ("D3Q27", (5, 7, 37)),      # ragged x inside one 64-lane block
+    ("D3Q27", (3, 4, 300)),     # two x chunks of 256 with a tail
+    ("D3Q27", (2, 3, 1)),       # nx = 1: x neighbours are the node itself
+    ("D2Q9", (19, 70)),
+    ("D2Q37", (13, 41)),
+    ("D2Q37", (5, 260)),
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("kind,shape", CASES)
+def test_one_step_parity(cm, orc, kind, shape, storage):
+    err, scale = one_step_case(cm, orc, kind, storage, shape, seed=100 + len(shape) * 7 + shape[-1])
+    print(f"{kind} {shape} {storage}: max|df| = {err:.3e} (deviation scale {scale:.3e})")
+    assert err <= TOL[storage] * scale
+
+
+@pytest.mark.parametrize("model", ["cm", "raw_mrt", "reg_bgk"])
+@pytest.mark.parametrize("thermal", [True, False])
+def test_one_step_parity_d2q37_models(cm, orc, model, thermal):
+    for storage in ("f64", "f32"):
+        err, scale = one_step_case(cm, orc, "D2Q37", storage, (11, 67), seed=300, thermal=thermal, model=model)
+        print(f"D2Q37 {model} thermal={thermal} {storage}: {err:.3e} / {scale:.3e}")
+        assert err <= TOL[storage] * scale
+
+
+def test_tgv_fp64_multistep(cm, orc):
+    """D3Q27 TGV 24^3, tau = 0.6, 60 steps in FP64: max|du| <= 1e-12."""
+    n, steps = 24, 60
+    tau = {2: 0.6}
+    rho, u = inputs.tgv3d(n, 0.05)
+    ctx = cm.Context("D3Q27", (n, n, n), storage="f64", tau=tau)
+    ctx.init_fields(rho, u)
+    ctx.step(steps)
+    g_rho, g_u, _ = ctx.get_moments()
+    ctx.destroy()
+    cfg = orc.Cfg(lattice="D3Q27", tau=tau)
+    S = orc.init_equilibrium(cfg, rho, u)
+    orc.run(cfg, S, steps)
+    o_rho, o_u, _ = orc.moments("D3Q27", S)
+    du = np.abs(g_u - o_u).max()
+    print(f"FP64 TGV 24^3 x {steps}: max|du| = {du:.3e}, max|drho| = {np.abs(g_rho - o_rho).max():.3e}")
+    assert du <= 1e-12
+    assert np.abs(g_rho - o_rho).max() <= 1e-12
+
+
+@pytest.mark.parametrize("storage,tol_u", [("f32", 2e-6), ("f16", 2e-4), ("bf16", 3e-3)])
+def test_tgv_reduced_precision_multistep(cm, orc, storage, tol_u):
+    """D3Q27 TGV 32^3, tau = 0.55, 200 steps: error of u against the FP64
+    oracle stays within the stated bound for each storage type."""
+    n, steps = 32, 200
+    tau = {2: 0.55}
+    rho, u = inputs.tgv3d(n, 0.05)
+    ctx = cm.Context("D3Q27", (n, n, n), storage=storage, tau=tau)
+    ctx.init_fields(rho, u)
+    ctx.step(steps)
+    _, g_u, _ = ctx.get_moments()
+    ctx.destroy()
+    cfg = orc.Cfg(lattice="D3Q27", tau=tau)
+    S = orc.init_equilibrium(cfg, rho, u)
+    orc.run(cfg, S, steps)
+    _, o_u, _ = orc.moments("D3Q27", S)
+    du = np.abs(g_u - o_u).max()
+    print(f"{storage} TGV 32^3 x {steps}: max|du| = {du:.3e} (u0 = 0.05)")
+    assert du <= tol_u
+
+
+def test_d2q37_thermal_waves_multistep(cm, orc):
+    """D2Q37 thermal, shear + thermal waves with a background flow, FP64 and FP32."""
+    shape, steps = (24, 30), 40
+    L = orc.lattice("D2Q37")
+    tau = {2: 0.6, 3: 0.64, 4: 1.0}
+    rho, u, th = inputs.waves2d(30, 24, shear_amp=0.01, thermal_amp=0.01, background=(0.0, 0.1))
+    cfg = orc.Cfg(lattice="D2Q37", tau=tau, thermal=True)
+    S = orc.init_equilibrium(cfg, rho, u, th)
+    orc.run(cfg, S, steps)
+    o_rho, o_u, o_th = orc.moments("D2Q37", S)
+    for storage, tol in (("f64", 1e-12), ("f32", 2e-6)):
+        ctx = cm.Context("D2Q37", shape, storage=storage, thermal=True, tau=tau)
+        ctx.init_fields(rho, u, th)
+        ctx.step(steps)
+        g_rho, g_u, g_th = ctx.get_moments()
+        ctx.destroy()
+        err = max(np.abs(g_u - o_u).max(), np.abs(g_th - o_th).max(), np.abs(g_rho - o_rho).max())
+        print(f"D2Q37 waves {storage}: max err {err:.3e}")
+        assert err <= tol
+
+
+def test_full_size_sampled_d3q27_256(cm, orc):
+    """The benchmark workload (D3Q27 256^3 FP32 TGV, Re = 1600): one step in the
+    benchmark's launch configuration, checked at sampled nodes against the
+    oracle's pull + collide of the same initial fields."""
+    n, u0 = 256, 0.05
+    nu = u0 * (n / (2 * math.pi)) / 1600.0
+    tau = {2: 0.5 + 3.0 * nu}
+    rho, u = inputs.tgv3d(n, u0)
+    ctx = cm.Context("D3Q27", (n, n, n), storage="f32", tau=tau)
+    ctx.init_fields(rho, u)
+    ctx.step(1)
+    got = ctx.get_populations()
+    g = ctx.reduce()
+    ctx.destroy()
+    rng = np.random.default_rng(5)
+    nodes = np.concatenate([rng.choice(n ** 3, 300, replace=False),
+                            [0, n - 1, n * n - 1, n ** 3 - 1, n ** 3 - n]])  # faces and corners
+    L = orc.lattice("D3Q27")
+    cfg = orc.Cfg(lattice="D3Q27", tau=tau)
+    fin = np.zeros((len(nodes), 27))
+    for k, idx in enumerate(nodes):
+        x, y, z = idx % n, (idx // n) % n, idx // (n * n)
+        for i, e in enumerate(L["e"]):
+            xs, ys, zs = (x - e[0]) % n, (y - e[1]) % n, (z - e[2]) % n
+            fin[k, i] = orc.equilibrium("D3Q27", rho[zs, ys, xs], u[:, zs, ys, xs], 1.0)[i]
+    # the GPU state was encoded to FP32 at initialisation
+    fin = quantise(fin - L["w"], "f32") + L["w"]
+    ref = orc.collide(cfg, fin)
+    gs = got.reshape(27, -1)[:, nodes].T
+    err = np.abs(gs - ref).max()
+    scale = np.abs(ref - L["w"]).max()
+    print(f"256^3 sampled: max|df| = {err:.3e} (deviation scale {scale:.3e})")
+    assert err <= TOL["f32"] * scale
+    mass0 = rho.sum()
+    assert abs(g["mass"] - mass0) / mass0 < 1e-7
+
+
+def test_determinism(cm):
+    n = 32
+    rho, u = inputs.tgv3d(n, 0.05)
+    outs = []
+    for _ in range(2):
+        ctx = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.52})
+        ctx.init_fields(rho, u)
+        ctx.step(25)
+        outs.append(ctx.get_populations())
+        outs.append(ctx.reduce())
+        ctx.destroy()
+    assert np.array_equal(outs[0], outs[2])
+    assert outs[1]["enstrophy"] == outs[3]["enstrophy"] and outs[1]["ke"] == outs[3]["ke"]
+
+
+@pytest.mark.parametrize("kind,shape,thermal", [("D3Q27", (9, 10, 11), False), ("D2Q37", (12, 13), True),
+                                                ("D2Q9", (20, 17), False)])
+def test_moments_and_reductions(cm, orc, kind, shape, thermal):
+    from oracle.analysis import globals_of_state
+    S = random_state(orc, kind, shape, 44, thermal)
+    ctx = cm.Context(kind, shape, storage="f64", thermal=thermal)
+    ctx.set_populations(S)
+    g_rho, g_u, g_th = ctx.get_moments()
+    g = ctx.reduce()
+    ctx.destroy()
+    o_rho, o_u, o_th = orc.moments(kind, S)
+    assert np.abs(g_rho - o_rho).max() < 1e-14
+    assert np.abs(g_u - o_u).max() < 1e-14
+    assert np.abs(g_th - o_th).max() < 1e-13
+    ref = globals_of_state(kind, S)
+    for key in ("mass", "energy", "ke", "enstrophy"):
+        assert g[key] == pytest.approx(ref[key], rel=1e-12, abs=1e-15), key
+    assert np.allclose(g["momentum"][:len(ref["momentum"])], ref["momentum"], rtol=1e-12, atol=1e-13)
+    assert g["nonfinite"] == 0
+
+
+def test_nonfinite_detected(cm, orc):
+    S = random_state(orc, "D3Q27", (4, 5, 6), 45)
+    S[3, 1, 2, 3] = np.nan
+    ctx = cm.Context("D3Q27", (4, 5, 6), storage="f32")
+    ctx.set_populations(S)
+    with pytest.raises(cm.CmlbError) as ei:
+        ctx.reduce()
+    assert ei.value.code == cm.EUNSTABLE
+    assert ctx.reduce(allow_unstable=True)["nonfinite"] == 1
+    ctx.destroy()
+
+
+def test_error_paths(cm):
+    ctx = cm.Context("D3Q27", (4, 4, 4))
+    with pytest.raises(cm.CmlbError) as ei:
+        ctx.step(1)
+    assert ei.value.code == cm.ESTATE
+    with pytest.raises(cm.CmlbError) as ei:
+        ctx.get_moments()
+    assert ei.value.code == cm.ESTATE
+    with pytest.raises(cm.CmlbError) as ei:
+        ctx.set_tau([-1.0])
+    assert ei.value.code == cm.EINVAL
+    with pytest.raises(cm.CmlbError):
+        ctx.init_fields(np.zeros((4, 4, 4)), np.zeros((3, 4, 4, 4)))   # rho must be positive
+    ctx.init_fields(np.ones((4, 4, 4)), np.zeros((3, 4, 4, 4)))
+    ctx.step(0)
+    assert ctx.step_count() == 0
+    ctx.destroy()
+
+
+def test_external_buffers_match_internal(cm):
+    import torch
+    n = 16
+    rho, u = inputs.tgv3d(n, 0.05)
+    nbytes = 27 * n ** 3 * 4
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    a = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.7}, external=bufs, stream=stream)
+    b = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.7})
+    for c in (a, b):
+        c.init_fields(rho, u)
+        c.step(7)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    ptr, size, s = a.state()
+    assert ptr in (bufs[0].data_ptr(), bufs[1].data_ptr()) and size == nbytes
+    assert s == stream.cuda_stream
+    a.destroy()
+    b.destroy()
+
+
+def test_set_tau_changes_rates(cm, orc):
+    S = random_state(orc, "D3Q27", (4, 5, 6), 46)
+    ctx = cm.Context("D3Q27", (4, 5, 6), storage="f64", tau={2: 0.9})
+    ctx.set_tau([0.7, 0.8, 0.9, 1.1, 1.3])
+    ctx.set_populations(S)
+    ctx.step(1)
+    got = ctx.get_populations()
+    ctx.destroy()
+    ref = S.copy()
+    orc.run(orc.Cfg(lattice="D3Q27", tau={2: 0.7, 3: 0.8, 4: 0.9, 5: 1.1, 6: 1.3}), ref, 1)
+    assert np.abs(got - ref).max() < 1e-14
