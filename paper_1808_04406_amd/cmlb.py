@@ -51,6 +51,12 @@ def lib():
     """Load libcmlb.so (built by ``python -m paper_1808_04406_amd.build``)."""
     global _lib
     if _lib is None:
+        try:
+            # libcmlb needs libamdhip64.so.7; if torch is present its copy is
+            # loaded first so that one HIP runtime serves both
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1808_04406_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
@@ -122,11 +128,16 @@ def make_params(lattice, shape, storage="f32", model="cm", thermal=False, rho0=1
 
 
 def _stream_handle(stream):
+    """hipStream_t of a torch stream (or a raw handle).  The legacy default
+    stream (handle 0) cannot be named through the C ABI, where NULL asks for
+    a library-owned stream that does not order with it; it is refused."""
     if stream is None:
         return None
-    if isinstance(stream, int):
-        return stream
-    return int(stream.cuda_stream)  # torch.cuda.Stream
+    h = stream if isinstance(stream, int) else int(stream.cuda_stream)
+    if h == 0:
+        raise ValueError("pass a non-default stream (e.g. torch.cuda.Stream()); the default stream "
+                         "does not order with the library's own stream")
+    return h
 
 
 class Context:

@@ -280,7 +280,8 @@ def test_external_buffers_match_internal(cm):
     rho, u = inputs.tgv3d(n, 0.05)
     nbytes = 27 * n ** 3 * 4
     bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
     a = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.7}, external=bufs, stream=stream)
     b = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.7})
     for c in (a, b):
@@ -290,8 +291,31 @@ def test_external_buffers_match_internal(cm):
     ptr, size, s = a.state()
     assert ptr in (bufs[0].data_ptr(), bufs[1].data_ptr()) and size == nbytes
     assert s == stream.cuda_stream
+    with pytest.raises(ValueError):
+        cm.Context("D3Q27", (n, n, n), stream=torch.cuda.default_stream())
     a.destroy()
     b.destroy()
+
+
+def test_device_fields_on_torch_stream(cm, orc):
+    """Fields handed over as device tensors on the caller's stream."""
+    import torch
+    n = 12
+    rho, u = inputs.tgv3d(n, 0.05)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        d_rho = torch.from_numpy(rho.reshape(-1)).to("cuda")
+        d_u = torch.from_numpy(u.reshape(-1)).to("cuda")
+        ctx = cm.Context("D3Q27", (n, n, n), storage="f64", tau={2: 0.8}, stream=stream)
+        ctx.init_fields_device(d_rho, d_u)
+        ctx.step(3)
+        _, g_u, _ = ctx.get_moments()
+        ctx.destroy()
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.8})
+    S = orc.init_equilibrium(cfg, rho, u)
+    orc.run(cfg, S, 3)
+    _, o_u, _ = orc.moments("D3Q27", S)
+    assert np.abs(g_u - o_u).max() < 1e-13
 
 
 def test_set_tau_changes_rates(cm, orc):
