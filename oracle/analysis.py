@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import lattice
+from . import collide, equilibrium, lattice
 
 
 def nu_lattice(kind: str, tau2: float, theta: float = 1.0) -> float:
@@ -93,3 +93,32 @@ def globals_of_state(kind: str, S: np.ndarray) -> dict:
         ens = 0.5 * (wx ** 2 + wy ** 2 + wz ** 2).sum()
     return dict(mass=rho.sum(), momentum=mom.sum(1), energy=energy, ke=ke,
                 enstrophy=ens, nonfinite=nonfinite)
+
+
+def collision_jacobian(cfg, u_lat, theta=1.0, h=1e-6):
+    """d f* / d f of the oracle collision at the equilibrium of (rho = 1, u),
+    by central differences (linearised operator of Sec. II.C)."""
+    L = lattice(cfg.lattice)
+    Q = L["Q"]
+    f0 = equilibrium(cfg.lattice, 1.0, u_lat, theta)
+    plus = collide(cfg, f0[None] + h * np.eye(Q))
+    minus = collide(cfg, f0[None] - h * np.eye(Q))
+    return ((plus - minus) / (2 * h)).T
+
+
+def spectral_radius(cfg, u_lat, theta=1.0, nk=9):
+    """Largest |eigenvalue| of the linearised stream-and-collide update
+    A(k) = diag(exp(-i k.e_i)) J over a grid of wave vectors k in [0, pi]^D
+    (von Neumann analysis); > 1 means a growing mode."""
+    L = lattice(cfg.lattice)
+    D = L["D"]
+    e = L["e"][:, :D]
+    J = collision_jacobian(cfg, u_lat, theta)
+    ks = np.linspace(0.0, np.pi, nk)
+    best, arg = 0.0, None
+    for k in np.stack(np.meshgrid(*[ks] * D, indexing="ij"), -1).reshape(-1, D):
+        S = np.exp(-1j * (e @ k))
+        r = np.abs(np.linalg.eigvals(S[:, None] * J)).max()
+        if r > best:
+            best, arg = r, k
+    return best, arg

@@ -92,11 +92,12 @@ __device__ __forceinline__ Tri<R> d37_shift(const Tri<R>& in, R t) {
             constexpr int k = decltype(K)::value, l = decltype(L)::value;
             if constexpr (k + l <= 4) {
                 constexpr int n = AXIS == 0 ? k : l;
-                R acc = AXIS == 0 ? in.v[k][l] : in.v[k][l];
+                R acc = in.v[k][l];
                 static_for<0, n>([&](auto A) {
                     constexpr int a = decltype(A)::value;
+                    constexpr int c = binom4(n, a);
                     const R src = AXIS == 0 ? in.v[a][l] : in.v[k][a];
-                    acc += R(binom4(n, a)) * tp[n - a] * src;
+                    acc += R(c) * tp[n - a] * src;
                 });
                 out.v[k][l] = acc;
             }
@@ -104,8 +105,6 @@ __device__ __forceinline__ Tri<R> d37_shift(const Tri<R>& in, R t) {
     });
     return out;
 }
-
-struct D37Macro {};
 
 template <class R>
 struct D37State {
@@ -118,7 +117,7 @@ __device__ __forceinline__ D37State<R> d37_state(const Tri<R>& m, R rho0, bool t
     D37State<R> st;
     st.drho = m.v[0][0];
     st.rho = rho0 + st.drho;
-    const R inv = R(1) / st.rho;
+    const R inv = recip<R>(st.rho);
     st.ux = m.v[1][0] * inv;
     st.uy = m.v[0][1] * inv;
     if (thermal) {
@@ -155,7 +154,8 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
                 R acc = R(0);
                 static_for<0, k + 1>([&](auto A) {
                     constexpr int aa = decltype(A)::value;
-                    if constexpr (he_coef(k, aa) != 0) acc += R(he_coef(k, aa)) * m.v[aa][l];
+                    constexpr int c = he_coef(k, aa);
+                    if constexpr (c != 0) acc += R(c) * m.v[aa][l];
                 });
                 t.v[k][l] = acc;
             }
@@ -168,9 +168,11 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
                 R acc = R(0);
                 static_for<0, l + 1>([&](auto B) {
                     constexpr int b = decltype(B)::value;
-                    if constexpr (he_coef(l, b) != 0) acc += R(he_coef(l, b)) * t.v[k][b];
+                    constexpr int c = he_coef(l, b);
+                    if constexpr (c != 0) acc += R(c) * t.v[k][b];
                 });
-                a.v[k][l] = acc * R(1.0 / (fact_c(k) * fact_c(l)));
+                constexpr int kl = fact_c(k) * fact_c(l);
+                a.v[k][l] = acc * R(1.0 / kl);
             }
         });
     });
@@ -182,7 +184,8 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
                 R acc = R(0);
                 static_for<aa, 5 - l>([&](auto K) {
                     constexpr int k = decltype(K)::value;
-                    if constexpr (he_coef(k, aa) != 0) acc += R(he_coef(k, aa)) * a.v[k][l];
+                    constexpr int c = he_coef(k, aa);
+                    if constexpr (c != 0) acc += R(c) * a.v[k][l];
                 });
                 c.v[aa][l] = acc;
             }
@@ -196,7 +199,8 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
                 R acc = R(0);
                 static_for<b, 5 - aa>([&](auto L) {
                     constexpr int l = decltype(L)::value;
-                    if constexpr (he_coef(l, b) != 0) acc += R(he_coef(l, b)) * c.v[aa][l];
+                    constexpr int cc = he_coef(l, b);
+                    if constexpr (cc != 0) acc += R(cc) * c.v[aa][l];
                 });
                 C.v[aa][b] = acc * rp[aa + b];
             }
@@ -268,7 +272,8 @@ __device__ __forceinline__ void d37_collide(R (&h)[37], R rho0, const R* om, R r
                     R acc = R(0);
                     static_for<0, k + 1>([&](auto A) {
                         constexpr int aa = decltype(A)::value;
-                        if constexpr (he_coef(k, aa) != 0) acc += R(he_coef(k, aa)) * M.v[aa][l];
+                        constexpr int c = he_coef(k, aa);
+                        if constexpr (c != 0) acc += R(c) * M.v[aa][l];
                     });
                     t.v[k][l] = acc;
                 }
@@ -281,7 +286,8 @@ __device__ __forceinline__ void d37_collide(R (&h)[37], R rho0, const R* om, R r
                     R acc = R(0);
                     static_for<0, l + 1>([&](auto B) {
                         constexpr int b = decltype(B)::value;
-                        if constexpr (he_coef(l, b) != 0) acc += R(he_coef(l, b)) * t.v[k][b];
+                        constexpr int c = he_coef(l, b);
+                        if constexpr (c != 0) acc += R(c) * t.v[k][b];
                     });
                     a.v[k][l] = acc;
                     if constexpr (k + l >= 2) {
@@ -303,7 +309,8 @@ __device__ __forceinline__ void d37_collide(R (&h)[37], R rho0, const R* om, R r
                     R acc = R(0);
                     static_for<0, aa + 1>([&](auto K) {
                         constexpr int k = decltype(K)::value;
-                        if constexpr (mono[aa][k] != 0) acc += R(mono[aa][k]) * a.v[k][l];
+                        constexpr int c = mono[aa][k];
+                        if constexpr (c != 0) acc += R(c) * a.v[k][l];
                     });
                     t2.v[aa][l] = acc;
                 }
@@ -316,7 +323,8 @@ __device__ __forceinline__ void d37_collide(R (&h)[37], R rho0, const R* om, R r
                     R acc = R(0);
                     static_for<0, b + 1>([&](auto L) {
                         constexpr int l = decltype(L)::value;
-                        if constexpr (mono[b][l] != 0) acc += R(mono[b][l]) * t2.v[aa][l];
+                        constexpr int c = mono[b][l];
+                        if constexpr (c != 0) acc += R(c) * t2.v[aa][l];
                     });
                     mstar.v[aa][b] = acc;
                 }

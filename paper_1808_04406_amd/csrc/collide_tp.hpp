@@ -9,8 +9,9 @@
 // c_s^2 = theta / r^2 = 1/3 (the complete-basis Maxwellian).
 //
 // The transform factorises into D sweeps of the 3-point map
-// (f_-, f_0, f_+) -> (kappa_0, kappa_1, kappa_2) along each axis; its inverse
-// is analytic.  All arithmetic is on deviations h_i = f_i - w_i rho0: the
+// (f_-, f_0, f_+) -> (kappa_0, kappa_1, kappa_2) along each axis, done as raw
+// moments first (whose lowest orders are rho and rho u) and then a per-axis
+// binomial shift to the central frame; the inverse is analytic.  All arithmetic is on deviations h_i = f_i - w_i rho0: the
 // transforms are linear, and the deviation equilibrium
 // kappa'_eq = rho prod m - rho0 prod(m + d), d = (0, -u, u^2) (the central
 // moments of w about u) is formed by a recursion over the axes that never
@@ -27,33 +28,10 @@ struct TPMacro {
     R u[3];  // lattice units
 };
 
-// rho - rho0 and u from the deviation populations (Sec. II.A moments).
+// In place: populations (slot digit e+1 along each axis) -> raw moments
+// (slot digit = order along each axis), i.e. the sums sum_e e^p f_e.
 template <int D, class R>
-__device__ __forceinline__ TPMacro<D, R> tp_macro(const R (&h)[TP<D>::Q], R rho0) {
-    R s = R(0), j[3] = {R(0), R(0), R(0)};
-    static_for<0, TP<D>::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        s += h[i];
-        if constexpr (TP<D>::ex(i) == 1) j[0] += h[i];
-        if constexpr (TP<D>::ex(i) == -1) j[0] -= h[i];
-        if constexpr (TP<D>::ey(i) == 1) j[1] += h[i];
-        if constexpr (TP<D>::ey(i) == -1) j[1] -= h[i];
-        if constexpr (TP<D>::ez(i) == 1) j[2] += h[i];
-        if constexpr (TP<D>::ez(i) == -1) j[2] -= h[i];
-    });
-    TPMacro<D, R> m;
-    m.drho = s;
-    const R inv = R(1) / (rho0 + s);
-    m.u[0] = j[0] * inv;
-    m.u[1] = j[1] * inv;
-    m.u[2] = (D == 3) ? j[2] * inv : R(0);
-    return m;
-}
-
-// In place: populations (slot digit e+1 along each axis) -> central moments
-// (slot digit = order along each axis).
-template <int D, class R>
-__device__ __forceinline__ void tp_forward(R (&h)[TP<D>::Q], const R (&u)[3]) {
+__device__ __forceinline__ void tp_raw(R (&h)[TP<D>::Q]) {
     static_for<0, D>([&](auto Dd) {
         constexpr int d = decltype(Dd)::value;
         constexpr int s = (d == 0) ? 1 : (d == 1 ? 3 : 9);
@@ -61,19 +39,46 @@ __device__ __forceinline__ void tp_forward(R (&h)[TP<D>::Q], const R (&u)[3]) {
             constexpr int base = decltype(B)::value;
             if constexpr ((base / s) % 3 == 0) {
                 const R hm = h[base], h0 = h[base + s], hp = h[base + 2 * s];
-                const R sum = hm + hp, dif = hp - hm;
-                const R k0 = sum + h0;
-                const R k1 = dif - u[d] * k0;
-                const R k2 = sum - u[d] * (dif + k1);
-                h[base] = k0;
-                h[base + s] = k1;
-                h[base + 2 * s] = k2;
+                const R sum = hm + hp;
+                h[base] = sum + h0;        // e^0
+                h[base + s] = hp - hm;     // e^1
+                h[base + 2 * s] = sum;     // e^2
             }
         });
     });
 }
 
-// In place: central moments -> populations (inverse of tp_forward).
+// In place: raw moments -> central moments (binomial shift along each axis).
+template <int D, class R>
+__device__ __forceinline__ void tp_raw_to_central(R (&k)[TP<D>::Q], const R (&u)[3]) {
+    static_for<0, D>([&](auto Dd) {
+        constexpr int d = decltype(Dd)::value;
+        constexpr int s = (d == 0) ? 1 : (d == 1 ? 3 : 9);
+        static_for<0, TP<D>::Q>([&](auto B) {
+            constexpr int base = decltype(B)::value;
+            if constexpr ((base / s) % 3 == 0) {
+                const R m0 = k[base], m1 = k[base + s], m2 = k[base + 2 * s];
+                const R c1 = m1 - u[d] * m0;
+                k[base + s] = c1;
+                k[base + 2 * s] = m2 - u[d] * (m1 + c1);   // m2 - 2 u m1 + u^2 m0
+            }
+        });
+    });
+}
+
+// rho - rho0 and u from the raw moments of the deviations (Sec. II.A moments).
+template <int D, class R>
+__device__ __forceinline__ TPMacro<D, R> tp_macro_raw(const R (&m)[TP<D>::Q], R rho0) {
+    TPMacro<D, R> r;
+    r.drho = m[0];
+    const R inv = recip<R>(rho0 + m[0]);
+    r.u[0] = m[1] * inv;
+    r.u[1] = m[3] * inv;
+    r.u[2] = (D == 3) ? m[9] * inv : R(0);
+    return r;
+}
+
+// In place: central moments -> populations (inverse of the two maps above).
 template <int D, class R>
 __device__ __forceinline__ void tp_inverse(R (&h)[TP<D>::Q], const R (&u)[3]) {
     static_for<0, D>([&](auto Dd) {
@@ -85,9 +90,10 @@ __device__ __forceinline__ void tp_inverse(R (&h)[TP<D>::Q], const R (&u)[3]) {
                 const R k0 = h[base], k1 = h[base + s], k2 = h[base + 2 * s];
                 const R m1 = k1 + u[d] * k0;          // raw first moment
                 const R m2 = k2 + u[d] * (k1 + m1);   // raw second moment
+                const R hm1 = R(0.5) * m1;
                 h[base + s] = k0 - m2;                // e = 0
-                h[base + 2 * s] = R(0.5) * (m2 + m1); // e = +1
-                h[base] = R(0.5) * (m2 - m1);         // e = -1
+                h[base + 2 * s] = R(0.5) * m2 + hm1;  // e = +1
+                h[base] = R(0.5) * m2 - hm1;          // e = -1
             }
         });
     });
@@ -135,8 +141,9 @@ __device__ __forceinline__ void tp_relax(R (&k)[TP<D>::Q], R drho, R rho0, const
 // Full collision of one node on deviation populations (in place).
 template <int D, class R>
 __device__ __forceinline__ void tp_collide(R (&h)[TP<D>::Q], R rho0, const R* om) {
-    const TPMacro<D, R> m = tp_macro<D, R>(h, rho0);
-    tp_forward<D, R>(h, m.u);
+    tp_raw<D, R>(h);
+    const TPMacro<D, R> m = tp_macro_raw<D, R>(h, rho0);
+    tp_raw_to_central<D, R>(h, m.u);
     tp_relax<D, R>(h, m.drho, rho0, m.u, om);
     tp_inverse<D, R>(h, m.u);
 }

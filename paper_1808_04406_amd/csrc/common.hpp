@@ -25,6 +25,13 @@ __host__ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// Reciprocal: the hardware approximation (1 ulp) in FP32, exact division in FP64.
+template <class R>
+__device__ __forceinline__ R recip(R x) {
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(x);
+    else return R(1) / x;
+}
+
 // ---------------------------------------------------------------------------
 // Lattice velocity tables.
 // D2Q9 / D3Q27: e in {-1,0,1}^D, index i = (ex+1) + 3(ey+1) + 9(ez+1).

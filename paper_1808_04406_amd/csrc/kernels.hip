@@ -45,9 +45,13 @@ __global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
     const uint32_t x = chunk * blockDim.x + threadIdx.x;
     if (x >= nx) return;
     const uint32_t y = row % ny, z = row / ny;
-    const T* __restrict__ src = static_cast<const T*>(a.src);
-    T* __restrict__ dst = static_cast<T*>(a.dst);
-    const uint32_t xsrc[3] = {wrap_inc(x, nx), x, wrap_dec(x, nx)};  // x - e for e = -1, 0, +1
+    // Row bases are block-uniform (scalar registers); lanes add a 32-bit byte
+    // offset, which maps onto the saddr + voffset form of global loads/stores.
+    const char* __restrict__ src = static_cast<const char*>(a.src);
+    char* __restrict__ dst = static_cast<char*>(a.dst);
+    const uint64_t plane_bytes = a.g.plane * sizeof(T);
+    const uint32_t xoff[3] = {wrap_inc(x, nx) * (uint32_t)sizeof(T), x * (uint32_t)sizeof(T),
+                              wrap_dec(x, nx) * (uint32_t)sizeof(T)};  // x - e for e = -1, 0, +1
     const uint32_t ysrc[3] = {wrap_inc(y, ny), y, wrap_dec(y, ny)};
     const uint32_t zsrc[3] = {D == 3 ? wrap_inc(z, nz) : 0u, z, D == 3 ? wrap_dec(z, nz) : 0u};
 
@@ -55,8 +59,8 @@ __global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = TP<D>::ex(i), ey = TP<D>::ey(i), ez = TP<D>::ez(i);
-        const T* rowp = src + (uint64_t)i * a.g.plane + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * nx;
-        R v = S::load(rowp + xsrc[ex + 1]);
+        const char* rowp = src + i * plane_bytes + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * nx * sizeof(T);
+        R v = S::load(reinterpret_cast<const T*>(rowp + xoff[ex + 1]));
         if constexpr (S::kScaled) v *= R(a.inv_s[i]);
         h[i] = v;
     });
@@ -65,12 +69,12 @@ __global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
     static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
     tp_collide<D, R>(h, R(a.rho0), om);
 
-    const uint64_t node = ((uint64_t)z * ny + y) * nx + x;
+    char* outrow = dst + ((uint64_t)z * ny + y) * nx * sizeof(T);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         R v = h[i];
         if constexpr (S::kScaled) v *= R(a.s[i]);
-        S::store(dst + (uint64_t)i * a.g.plane + node, v);
+        S::store(reinterpret_cast<T*>(outrow + i * plane_bytes + xoff[1]), v);
     });
 }
 
@@ -87,17 +91,18 @@ __global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
     const uint32_t y = blockIdx.x / a.g.nchunks;
     const uint32_t x = chunk * blockDim.x + threadIdx.x;
     if (x >= nx) return;
-    const T* __restrict__ src = static_cast<const T*>(a.src);
-    T* __restrict__ dst = static_cast<T*>(a.dst);
+    const char* __restrict__ src = static_cast<const char*>(a.src);
+    char* __restrict__ dst = static_cast<char*>(a.dst);
+    const uint64_t plane_bytes = a.g.plane * sizeof(T);
 
     R h[37];
     static_for<0, 37>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
-        const uint32_t ys = wrap_sub(y, ey, ny);
-        const uint32_t xs = wrap_sub(x, ex, nx);
-        const T* rowp = src + (uint64_t)i * a.g.plane + (uint64_t)ys * nx;
-        R v = S::load(rowp + xs);
+        const uint32_t ys = wrap_sub(y, ey, ny);                       // block-uniform
+        const uint32_t xo = wrap_sub(x, ex, nx) * (uint32_t)sizeof(T);  // lane byte offset
+        const char* rowp = src + i * plane_bytes + (uint64_t)ys * nx * sizeof(T);
+        R v = S::load(reinterpret_cast<const T*>(rowp + xo));
         if constexpr (S::kScaled) v *= R(a.inv_s[i]);
         h[i] = v;
     });
@@ -108,12 +113,13 @@ __global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
     static_for<0, 8>([&](auto N) { wc[decltype(N)::value] = R(a.wcls[decltype(N)::value]); });
     d37_collide<MODEL, R>(h, R(a.rho0), om, R(a.r), wc, a.thermal != 0, R(a.theta0));
 
-    const uint64_t node = (uint64_t)y * nx + x;
+    char* outrow = dst + (uint64_t)y * nx * sizeof(T);
+    const uint32_t xo = x * (uint32_t)sizeof(T);
     static_for<0, 37>([&](auto I) {
         constexpr int i = decltype(I)::value;
         R v = h[i];
         if constexpr (S::kScaled) v *= R(a.s[i]);
-        S::store(dst + (uint64_t)i * a.g.plane + node, v);
+        S::store(reinterpret_cast<T*>(outrow + i * plane_bytes + xo), v);
     });
 }
 

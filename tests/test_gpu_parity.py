@@ -329,3 +329,22 @@ def test_set_tau_changes_rates(cm, orc):
     ref = S.copy()
     orc.run(orc.Cfg(lattice="D3Q27", tau={2: 0.7, 3: 0.8, 4: 0.9, 5: 1.1, 6: 1.3}), ref, 1)
     assert np.abs(got - ref).max() < 1e-14
+
+
+def test_tgv_long_run_stable_rates(cm):
+    """64^3 Taylor-Green vortex at tau_2 = 0.50095 (Re = 1600 at this size) with
+    the benchmark's rate set (odd orders at 1, even orders at omega_2) stays
+    finite for 600 steps and loses kinetic energy monotonically."""
+    n = 64
+    tau = 0.5 + 3.0 * 0.05 * (n / (2 * math.pi)) / 1600.0
+    rho, u = inputs.tgv3d(n, 0.05)
+    ctx = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: tau, 3: 1.0, 4: tau, 5: 1.0, 6: tau})
+    ctx.init_fields(rho, u)
+    ke = [ctx.reduce()["ke"]]
+    for _ in range(6):
+        ctx.step(100)
+        g = ctx.reduce()
+        assert g["nonfinite"] == 0
+        ke.append(g["ke"])
+    ctx.destroy()
+    assert all(b < a for a, b in zip(ke, ke[1:]))
