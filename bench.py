@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="tgv256_f32", choices=sorted(WORKLOADS),
+                    help="default: the D3Q27 256^3 FP32 Taylor-Green benchmark; others report the precision "
+                         "form and the thermal lattice with the same JSON fields")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -134,25 +137,60 @@ def main():
     stream = torch.cuda.Stream()  # default priority; all work of the run is ordered on it
     with torch.cuda.stream(stream):
         out = run(torch, cmlb, inputs, stream, args)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "tgv256_f32":
         out["cpu_baseline"] = cpu_baseline(out["config"]["tau_shear"])
     print(json.dumps(out), flush=True)
 
 
-def run(torch, cmlb, inputs, stream, args):
-    tau = tau_shear()
-    nodes = N ** 3
-    nbytes = Q * nodes * STORAGE_BYTES
-    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
-    ctx = cmlb.Context("D3Q27", (N, N, N), storage="f32", tau=rates(tau), external=bufs, stream=stream)
+WORKLOADS = {
+    # name: (lattice, grid, storage, description)
+    "tgv256_f32": ("D3Q27", (256, 256, 256), "f32", "D3Q27 CM-MRT 256^3 periodic 3D Taylor-Green vortex, u0=0.05, "
+                   "Re=1600, FP32 deviation storage"),
+    "tgv512_f32": ("D3Q27", (512, 512, 512), "f32", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, FP32 storage"),
+    "tgv512_f16": ("D3Q27", (512, 512, 512), "f16", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, FP16 scaled storage"),
+    "tgv512_bf16": ("D3Q27", (512, 512, 512), "bf16", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, BF16 storage"),
+    "tgv512_f64": ("D3Q27", (512, 512, 512), "f64", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, FP64 storage"),
+    "waves1024_f32": ("D2Q37", (1024, 1024), "f32", "D2Q37 thermal CM-MRT 1024^2, shear + thermal waves "
+                      "(amplitude 0.01), tau_2=0.6, Pr=0.71, background 0.1, FP32 storage"),
+    "waves2048_f32": ("D2Q37", (2048, 2048), "f32", "D2Q37 thermal CM-MRT 2048^2, shear + thermal waves "
+                      "(amplitude 0.01), tau_2=0.6, Pr=0.71, background 0.1, FP32 storage"),
+}
+QS = {"D3Q27": 27, "D2Q37": 37}
+SBYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
-    rho, u = inputs.tgv3d(N, U0)
-    d_rho = torch.from_numpy(rho.reshape(-1)).to("cuda")
-    d_u = torch.from_numpy(u.reshape(-1)).to("cuda")
-    ctx.init_fields_device(d_rho, d_u)
+
+def setup_workload(name, torch, cmlb, inputs, stream):
+    """Context, external buffers and device fields of a workload."""
+    lattice, shape, storage, desc = WORKLOADS[name]
+    q, sb = QS[lattice], SBYTES[storage]
+    nodes = 1
+    for s_ in shape:
+        nodes *= s_
+    bufs = [torch.empty(q * nodes * sb, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    theta = None
+    if lattice == "D3Q27":
+        n = shape[0]
+        re = RE if n == 256 else 1.0e5
+        tau = tau_shear(n, U0, re)
+        taus = rates(tau)
+        ctx = cmlb.Context("D3Q27", shape, storage=storage, tau=taus, external=bufs, stream=stream)
+        rho, u = inputs.tgv3d(n, U0)
+    else:
+        n = shape[0]
+        tau2, pr = 0.6, 0.71
+        taus = {2: tau2, 3: 0.5 + (tau2 - 0.5) / pr, 4: tau2}
+        ctx = cmlb.Context("D2Q37", shape, storage=storage, thermal=True, tau=taus, external=bufs, stream=stream)
+        rho, u, theta = inputs.waves2d(n, n, shear_amp=0.01, thermal_amp=0.01, k=(1, 0), background=(0.0, 0.1))
+    d = [torch.from_numpy(a.reshape(-1)).to("cuda") for a in (rho, u)]
+    d_th = None if theta is None else torch.from_numpy(theta.reshape(-1)).to("cuda")
+    ctx.init_fields_device(d[0], d[1], d_th)
     torch.cuda.synchronize()
-    del d_rho, d_u
-    mass0 = float(rho.sum())
+    return ctx, bufs, float(rho.sum()), taus, desc, nodes, q, sb
+
+
+def run(torch, cmlb, inputs, stream, args):
+    ctx, bufs, mass0, taus, desc, nodes, q, sb = setup_workload(args.workload, torch, cmlb, inputs, stream)
+    lattice, shape, storage, _ = WORKLOADS[args.workload]
 
     ctx.step(args.warmup)
     torch.cuda.synchronize()
@@ -179,9 +217,11 @@ def run(torch, cmlb, inputs, stream, args):
     copy_gbs = copy_bandwidth(torch)
 
     value = nodes * args.steps / wall / 1e6
-    alg_bytes = 2 * Q * STORAGE_BYTES * nodes
+    per_node = 2 * q * sb
+    alg_bytes = per_node * nodes
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(alg_bytes)
+    traffic = measured_traffic(alg_bytes) if args.workload == "tgv256_f32" else None
+    kernel = KERNEL if lattice == "D3Q27" else "k_step_d37<%s, kCM>" % storage
     out = {
         "metric": "MLUPS of CM-MRT stream+collide, % HBM roofline; error vs FP64 oracle",
         "value": round(value, 1),
@@ -193,16 +233,15 @@ def run(torch, cmlb, inputs, stream, args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": storage,
         "data": "synthetic",
-        "config": {"workload": "D3Q27 CM-MRT 256^3 periodic 3D Taylor-Green vortex, u0=0.05, Re=1600, "
-                               "FP32 deviation storage",
-                   "lattice": "D3Q27", "grid": [N, N, N], "storage": "f32", "tau_shear": tau,
-                   "tau_by_order": {str(k): v for k, v in rates(tau).items()}, "parallelism": "single GPU"},
+        "config": {"workload": desc, "lattice": lattice, "grid": list(shape), "storage": storage,
+                   "tau_shear": taus[2], "tau_by_order": {str(k): v for k, v in taus.items()},
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": KERNEL, "kernel_ms": round(kernel_ms, 5),
-                     "bytes_per_node_update": 2 * Q * STORAGE_BYTES,
+                     "kernel": kernel, "kernel_ms": round(kernel_ms, 5),
+                     "bytes_per_node_update": per_node,
                      "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     return out
