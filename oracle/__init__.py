@@ -59,6 +59,11 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int64), d, ctypes.c_int]
         L.orc_init_equilibrium.argtypes = [ctypes.POINTER(_Cfg), l, l, l, d, d, d, d, ctypes.c_int]
         L.orc_moments.argtypes = [ctypes.c_int, l, d, d, d, d]
+        L.orc_mlp_forward.argtypes = [d, ctypes.c_int, d, d]
+        L.orc_closure_inputs.argtypes = [ctypes.c_int, d, d, d]
+        L.orc_collide_closure.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, d]
+        L.orc_closure_loss_grad.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, d, d]
+        L.orc_gather_nodes.argtypes = [ctypes.c_int, l, l, l, d, l, ctypes.POINTER(ctypes.c_int64), d]
         _lib = L
     return _lib
 
@@ -245,3 +250,65 @@ def moments(kind: str, S: np.ndarray):
     th = np.zeros(shape)
     lib().orc_moments(KINDS[kind], n, _p(S), _p(rho), _p(u), _p(th))
     return rho, u, th
+
+
+# ---------------------------------------------------------------------------
+# Learned closure (D3Q27): a per-node MLP sets the rates of orders 3..6
+# ---------------------------------------------------------------------------
+MLP_NPARAM = 2084
+
+
+def mlp_rates(params, x):
+    """omega_3..omega_6 = 0.5 + 1.45 sigmoid(MLP(x)) for inputs x[n, 27]."""
+    params = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
+    out = np.zeros((x.shape[0], 4))
+    lib().orc_mlp_forward(_p(params), x.shape[0], _p(x), _p(out))
+    return out
+
+
+def closure_inputs(f, norm):
+    """Network inputs (kappa_p - kappa_eq,p) / (rho sigma_p) of D3Q27 states f[n, 27]."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    norm = np.ascontiguousarray(norm, np.float64)
+    x = np.zeros_like(f)
+    lib().orc_closure_inputs(f.shape[0], _p(f), _p(norm), _p(x))
+    return x
+
+
+def collide_closure(cfg: Cfg, f, params, norm):
+    """D3Q27 collision with network rates; returns (f*[n, 27], omega[n, 4])."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    out = np.zeros_like(f)
+    om = np.zeros((f.shape[0], 4))
+    rc = lib().orc_collide_closure(ctypes.byref(cfg.c()), f.shape[0], _p(f),
+                                   _p(np.ascontiguousarray(params, np.float64)),
+                                   _p(np.ascontiguousarray(norm, np.float64)), _p(out), _p(om))
+    if rc:
+        raise RuntimeError("closure collision needs a D3Q27 CM configuration")
+    return out, om
+
+
+def closure_loss_grad(cfg: Cfg, f, fbar, params, norm):
+    """Mean over nodes of sum_i (f*_i - fbar_i)^2 / w_i and its gradient."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    fbar = np.ascontiguousarray(np.atleast_2d(fbar), np.float64)
+    loss = ctypes.c_double()
+    grad = np.zeros(MLP_NPARAM)
+    rc = lib().orc_closure_loss_grad(ctypes.byref(cfg.c()), f.shape[0], _p(f), _p(fbar),
+                                     _p(np.ascontiguousarray(params, np.float64)),
+                                     _p(np.ascontiguousarray(norm, np.float64)), ctypes.byref(loss), _p(grad))
+    if rc:
+        raise RuntimeError("closure loss needs a D3Q27 CM configuration")
+    return loss.value, grad
+
+
+def gather_nodes(kind: str, S: np.ndarray, nodes) -> np.ndarray:
+    """Pulled populations S_i(x - e_i) at flat node indices; returns [n, Q]."""
+    S = np.ascontiguousarray(S, np.float64)
+    Q, nz, ny, nx = _dims(S)
+    nodes = np.ascontiguousarray(nodes, np.int64)
+    out = np.zeros((len(nodes), Q))
+    lib().orc_gather_nodes(KINDS[kind], nx, ny, nz, _p(S), len(nodes),
+                           nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out))
+    return out

@@ -20,8 +20,9 @@
  *
  * Parity: every function below is pinned by the CPU test suite against
  * closed forms, library quadrature, brute force or the paper's printed
- * constants, except the storage codecs (none here) and the learned-closure
- * network, whose pin is a finite-difference gradient check.
+ * constants; the learned-closure network (not in the paper) is pinned by an
+ * independent FP64 implementation of its layers and by finite differences
+ * of its training objective.
  */
 #include <math.h>
 #include <stdint.h>
@@ -933,6 +934,209 @@ int orc_moments(int kind, long n_nodes, const double *S, double *rho, double *u,
         rho[n] = r_;
         for (int d = 0; d < L->D; ++d) u[d * n_nodes + n] = ux[d] / L->r;
         if (theta) theta[n] = th;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Learned closure (D3Q27): a per-node MLP sets omega_3..omega_6             */
+/* ------------------------------------------------------------------------- */
+/* Not part of the paper; the rates it sets are the paper's omega_n of
+ * eq:omega for n >= 3.  Network: x (27) -> GELU(W1 x + b1) (32) ->
+ * GELU(W2 h1 + b2) (32) -> z = W3 h2 + b3 (4), omega_{n} = 0.5 + 1.45
+ * sigmoid(z_{n-3}).  GELU is the exact erf form.  Parameters are packed as
+ * W1[32][27], b1[32], W2[32][32], b2[32], W3[4][32], b3[4] (2084 values,
+ * row-major [out][in]).  Inputs are the non-equilibrium central moments
+ * x_p = (kappa_p - kappa_eq,p) / (rho sigma_p), p = px + 3 py + 9 pz,
+ * kappa_p = sum_i f_i prod_d (e_{i,d} - u_d)^{p_d} (lattice units) and
+ * kappa_eq,p = rho prod_d m(p_d), m = (1, 0, 1/3). */
+
+#define MLP_NIN 27
+#define MLP_NH 32
+#define MLP_NOUT 4
+#define MLP_NPARAM (MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NOUT * MLP_NH + MLP_NOUT)
+
+static double gelu(double a) { return 0.5 * a * (1.0 + erf(a / sqrt(2.0))); }
+static double gelu_grad(double a)
+{
+    const double pi = 3.14159265358979323846;
+    return 0.5 * (1.0 + erf(a / sqrt(2.0))) + a * exp(-0.5 * a * a) / sqrt(2.0 * pi);
+}
+static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+typedef struct { double a1[MLP_NH], h1[MLP_NH], a2[MLP_NH], h2[MLP_NH], z[MLP_NOUT]; } mlp_trace;
+
+static void mlp_forward(const double *P, const double *x, mlp_trace *t)
+{
+    const double *W1 = P, *b1 = W1 + MLP_NH * MLP_NIN, *W2 = b1 + MLP_NH, *b2 = W2 + MLP_NH * MLP_NH;
+    const double *W3 = b2 + MLP_NH, *b3 = W3 + MLP_NOUT * MLP_NH;
+    for (int j = 0; j < MLP_NH; ++j) {
+        double s = b1[j];
+        for (int k = 0; k < MLP_NIN; ++k) s += W1[j * MLP_NIN + k] * x[k];
+        t->a1[j] = s;
+        t->h1[j] = gelu(s);
+    }
+    for (int j = 0; j < MLP_NH; ++j) {
+        double s = b2[j];
+        for (int k = 0; k < MLP_NH; ++k) s += W2[j * MLP_NH + k] * t->h1[k];
+        t->a2[j] = s;
+        t->h2[j] = gelu(s);
+    }
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        double s = b3[j];
+        for (int k = 0; k < MLP_NH; ++k) s += W3[j * MLP_NH + k] * t->h2[k];
+        t->z[j] = s;
+    }
+}
+
+static double rate_from_logit(double z) { return 0.5 + 1.45 * sigmoid(z); }
+
+int orc_mlp_nparam(void) { return MLP_NPARAM; }
+
+int orc_mlp_forward(const double *params, int n, const double *x, double *omega)
+{
+    for (int k = 0; k < n; ++k) {
+        mlp_trace t;
+        mlp_forward(params, x + (size_t)k * MLP_NIN, &t);
+        for (int j = 0; j < MLP_NOUT; ++j) omega[(size_t)k * MLP_NOUT + j] = rate_from_logit(t.z[j]);
+    }
+    return 0;
+}
+
+/* Network inputs of one D3Q27 node (central moments by their definition). */
+static void closure_inputs(const orc_lattice *L, const double *f, const double *norm, double *x)
+{
+    double rho = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < 27; ++i) {
+        rho += f[i];
+        for (int d = 0; d < 3; ++d) j[d] += f[i] * L->e[i][d];
+    }
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    for (int p = 0; p < 27; ++p) {
+        int pd[3];
+        tp_index(3, p, pd);
+        double kap = 0.0, keq = rho;
+        for (int i = 0; i < 27; ++i) {
+            double m = 1.0;
+            for (int d = 0; d < 3; ++d) m *= pow(L->e[i][d] - u[d], pd[d]);
+            kap += m * f[i];
+        }
+        for (int d = 0; d < 3; ++d) keq *= (pd[d] == 0) ? 1.0 : (pd[d] == 1 ? 0.0 : 1.0 / 3.0);
+        x[p] = (kap - keq) / (rho * norm[p]);
+    }
+}
+
+int orc_closure_inputs(int n, const double *f, const double *norm, double *x)
+{
+    const orc_lattice *L = lattice(ORC_D3Q27);
+    for (int k = 0; k < n; ++k) closure_inputs(L, f + (size_t)k * 27, norm, x + (size_t)k * 27);
+    return 0;
+}
+
+/* Collision with the network's rates for orders 3..6 (omega_2 from cfg). */
+int orc_collide_closure(const orc_cfg *cfg, int n, const double *f, const double *params, const double *norm,
+                        double *out, double *omega_out)
+{
+    const orc_lattice *L = lattice(ORC_D3Q27);
+    if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM) return -1;
+    for (int k = 0; k < n; ++k) {
+        double x[27];
+        mlp_trace t;
+        closure_inputs(L, f + (size_t)k * 27, norm, x);
+        mlp_forward(params, x, &t);
+        orc_cfg c = *cfg;
+        for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t.z[j]);
+        if (omega_out)
+            for (int j = 0; j < MLP_NOUT; ++j) omega_out[(size_t)k * MLP_NOUT + j] = c.omega[3 + j];
+        collide_tp(L, &c, f + (size_t)k * 27, out + (size_t)k * 27);
+    }
+    return 0;
+}
+
+/* Training objective and its gradient.  For pulled pre-collision states f
+ * and targets fbar (n nodes each, [node][i]):
+ *   L = (1/n) sum_nodes sum_i (f*_i - fbar_i)^2 / w_i,
+ * f* the collision with the network's rates.  f* is affine in each omega_m
+ * (kappa* = kappa + omega_{|p|} (kappa_eq - kappa)), so the derivative of f*
+ * with respect to omega_m is the
+ * difference of two collisions with omega_m = 1 and omega_m = 0; the rest is
+ * the chain rule through the sigmoid map and the two GELU layers. */
+int orc_closure_loss_grad(const orc_cfg *cfg, int n, const double *f, const double *fbar, const double *params,
+                          const double *norm, double *loss_out, double *grad)
+{
+    const orc_lattice *L = lattice(ORC_D3Q27);
+    if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM || n < 1) return -1;
+    const double *W2 = params + MLP_NH * MLP_NIN + MLP_NH;
+    const double *W3 = W2 + MLP_NH * MLP_NH + MLP_NH;
+    memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    double loss = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double *fk = f + (size_t)k * 27, *tk = fbar + (size_t)k * 27;
+        double x[27], fs[27], r[27];
+        mlp_trace t;
+        closure_inputs(L, fk, norm, x);
+        mlp_forward(params, x, &t);
+        orc_cfg c = *cfg;
+        for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t.z[j]);
+        collide_tp(L, &c, fk, fs);
+        for (int i = 0; i < 27; ++i) {
+            double e = fs[i] - tk[i];
+            loss += e * e / L->w[i] / n;
+            r[i] = 2.0 * e / L->w[i] / n;
+        }
+        double dz[MLP_NOUT];
+        for (int j = 0; j < MLP_NOUT; ++j) {
+            orc_cfg c1 = c, c0 = c;
+            c1.omega[3 + j] = 1.0;
+            c0.omega[3 + j] = 0.0;
+            double g1[27], g0[27], dw = 0.0;
+            collide_tp(L, &c1, fk, g1);
+            collide_tp(L, &c0, fk, g0);
+            for (int i = 0; i < 27; ++i) dw += r[i] * (g1[i] - g0[i]);
+            double s = sigmoid(t.z[j]);
+            dz[j] = dw * 1.45 * s * (1.0 - s);
+        }
+        double *gW1 = grad, *gb1 = gW1 + MLP_NH * MLP_NIN, *gW2 = gb1 + MLP_NH, *gb2 = gW2 + MLP_NH * MLP_NH;
+        double *gW3 = gb2 + MLP_NH, *gb3 = gW3 + MLP_NOUT * MLP_NH;
+        double da2[MLP_NH], da1[MLP_NH];
+        for (int j = 0; j < MLP_NOUT; ++j) {
+            gb3[j] += dz[j];
+            for (int m = 0; m < MLP_NH; ++m) gW3[j * MLP_NH + m] += dz[j] * t.h2[m];
+        }
+        for (int m = 0; m < MLP_NH; ++m) {
+            double dh = 0.0;
+            for (int j = 0; j < MLP_NOUT; ++j) dh += W3[j * MLP_NH + m] * dz[j];
+            da2[m] = dh * gelu_grad(t.a2[m]);
+        }
+        for (int j = 0; j < MLP_NH; ++j) {
+            gb2[j] += da2[j];
+            for (int m = 0; m < MLP_NH; ++m) gW2[j * MLP_NH + m] += da2[j] * t.h1[m];
+        }
+        for (int m = 0; m < MLP_NH; ++m) {
+            double dh = 0.0;
+            for (int j = 0; j < MLP_NH; ++j) dh += W2[j * MLP_NH + m] * da2[j];
+            da1[m] = dh * gelu_grad(t.a1[m]);
+        }
+        for (int j = 0; j < MLP_NH; ++j) {
+            gb1[j] += da1[j];
+            for (int m = 0; m < MLP_NIN; ++m) gW1[j * MLP_NIN + m] += da1[j] * x[m];
+        }
+    }
+    *loss_out = loss;
+    return 0;
+}
+
+/* Pulled (pre-collision) populations of the listed nodes: out[k*Q + i] =
+ * S_i(x_k - e_i) on the periodic grid. */
+int orc_gather_nodes(int kind, long nx, long ny, long nz, const double *S, long n_nodes, const int64_t *nodes,
+                     double *out)
+{
+    const orc_lattice *L = lattice(kind);
+    if (!L) return -1;
+    for (long k = 0; k < n_nodes; ++k) {
+        long idx = (long)nodes[k];
+        long x = idx % nx, y = (idx / nx) % ny, z = idx / (nx * ny);
+        gather(L, nx, ny, nz, S, x, y, z, out + (size_t)k * L->Q);
     }
     return 0;
 }
