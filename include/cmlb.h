@@ -163,6 +163,57 @@ int64_t cmlb_step_count(const cmlb_ctx *ctx);
 /* Storage scale s_i actually in use (Q values). */
 int cmlb_get_scale(const cmlb_ctx *ctx, double *scale);
 
+/* Copy the current population buffer to / from device memory in the
+ * context's own layout and storage type (Q * nx*ny*nz elements).  Loading
+ * marks the state initialised and resets the step count. */
+int cmlb_store_state_device(cmlb_ctx *ctx, void *dst);
+int cmlb_load_state_device(cmlb_ctx *ctx, const void *src);
+
+/* Box filter for coarse-graining (D3Q27 contexts): the populations of
+ * factor^3 blocks of nodes are averaged (a linear filter, so mass and
+ * momentum are kept) and written to dst as FP32 deviations f_i - w_i rho0
+ * on the (nx/factor, ny/factor, nz/factor) grid, layout [i][z][y][x].
+ * nx, ny, nz must be multiples of factor. */
+int cmlb_box_filter(cmlb_ctx *ctx, int factor, void *dst);
+
+/* ---- Learned closure (D3Q27 contexts with FP32 storage) ----------------
+ * Not part of the paper: a per-node network sets the rates omega_3..omega_6
+ * of eq:omega.  Inputs: x_p = (kappa_p - kappa_eq,p) / (rho sigma_p) for the
+ * 27 central moments p = px + 3 py + 9 pz (lattice units); network
+ * 27 -> GELU 32 -> GELU 32 -> 4, omega_{3+j} = 0.5 + 1.45 sigmoid(z_j).
+ * Parameters: 2084 FP32 values W1[32][27], b1[32], W2[32][32], b2[32],
+ * W3[4][32], b3[4] (row-major [out][in]); the step evaluates the network
+ * with BF16 weights and activations and FP32 accumulation (matrix cores). */
+#define CMLB_CLOSURE_NPARAM 2084
+
+/* Load FP32 parameters (kept as the FP32 master copy) and the 27 input
+ * scales sigma_p (> 0); resets the optimiser state.  Host arrays. */
+int cmlb_closure_load(cmlb_ctx *ctx, const float *params, const float *sigma);
+
+/* Use (1) or stop using (0) the network rates in cmlb_step. */
+int cmlb_closure_enable(cmlb_ctx *ctx, int on);
+
+/* Current FP32 master parameters (host array of 2084). */
+int cmlb_closure_get(cmlb_ctx *ctx, float *params);
+
+/* A training batch: n_pairs consecutive (state, target) pairs in device
+ * memory, each Q * nx*ny*nz FP32 deviations in the context's layout.  The
+ * state is pulled (streamed) and collided with the network's rates; the
+ * objective is the mean over all nodes of sum_i (f*_i - fbar_i)^2 / w_i
+ * against the target.  nx must be a multiple of 64. */
+typedef struct cmlb_batch {
+    const void *state;
+    const void *target;
+    int64_t n_pairs;
+} cmlb_batch;
+
+/* Objective and its gradient (host outputs; grad may be NULL). */
+int cmlb_closure_objective(cmlb_ctx *ctx, const cmlb_batch *batch, float *objective, float *grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on
+ * the batch objective; *objective receives its value before the update. */
+int cmlb_closure_train_step(cmlb_ctx *ctx, const cmlb_batch *batch, float lr, float *objective);
+
 #ifdef __cplusplus
 }
 #endif

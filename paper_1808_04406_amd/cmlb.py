@@ -44,6 +44,12 @@ class Globals(ctypes.Structure):
                 ("n_nonfinite", ctypes.c_int64)]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_void_p), ("target", ctypes.c_void_p), ("n_pairs", ctypes.c_int64)]
+
+
+CLOSURE_NPARAM = 2084
+
 _lib = None
 
 
@@ -83,6 +89,15 @@ def lib():
         L.cmlb_step_count.argtypes = [vp]
         L.cmlb_step_count.restype = c_i64
         L.cmlb_get_scale.argtypes = [vp, dp]
+        fp = P(ctypes.c_float)
+        L.cmlb_store_state_device.argtypes = [vp, vp]
+        L.cmlb_load_state_device.argtypes = [vp, vp]
+        L.cmlb_box_filter.argtypes = [vp, c_int, vp]
+        L.cmlb_closure_load.argtypes = [vp, fp, fp]
+        L.cmlb_closure_enable.argtypes = [vp, c_int]
+        L.cmlb_closure_get.argtypes = [vp, fp]
+        L.cmlb_closure_objective.argtypes = [vp, P(Batch), fp, fp]
+        L.cmlb_closure_train_step.argtypes = [vp, P(Batch), ctypes.c_float, fp]
         _lib = L
     return _lib
 
@@ -246,3 +261,51 @@ class Context:
         s = np.zeros(37)
         self._check(lib().cmlb_get_scale(self.h, _dp(s)))
         return s[:self.Q]
+
+    # -- device-side state transfer and coarse-graining ---------------------
+    def store_state_device(self, dst):
+        """Copy the current populations into a device tensor (storage layout)."""
+        self._check(lib().cmlb_store_state_device(self.h, dst.data_ptr()))
+
+    def load_state_device(self, src):
+        self._check(lib().cmlb_load_state_device(self.h, src.data_ptr()))
+
+    def box_filter(self, factor, dst):
+        """Mean over factor^3 blocks into an FP32 device tensor (coarse layout)."""
+        self._check(lib().cmlb_box_filter(self.h, int(factor), dst.data_ptr()))
+
+    # -- learned closure -----------------------------------------------------
+    def closure_load(self, params, sigma):
+        p = np.ascontiguousarray(params, np.float32)
+        s = np.ascontiguousarray(sigma, np.float32)
+        if p.size != CLOSURE_NPARAM or s.size != 27:
+            raise ValueError("closure needs 2084 parameters and 27 scales")
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(lib().cmlb_closure_load(self.h, p.ctypes.data_as(fp), s.ctypes.data_as(fp)))
+
+    def closure_enable(self, on=True):
+        self._check(lib().cmlb_closure_enable(self.h, 1 if on else 0))
+
+    def closure_get(self):
+        p = np.zeros(CLOSURE_NPARAM, np.float32)
+        self._check(lib().cmlb_closure_get(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    @staticmethod
+    def _batch(state, target, n_pairs):
+        return Batch(state.data_ptr(), target.data_ptr(), int(n_pairs))
+
+    def closure_objective(self, state, target, n_pairs=1, grad=True):
+        fp = ctypes.POINTER(ctypes.c_float)
+        b = self._batch(state, target, n_pairs)
+        obj = ctypes.c_float()
+        g = np.zeros(CLOSURE_NPARAM, np.float32) if grad else None
+        self._check(lib().cmlb_closure_objective(self.h, ctypes.byref(b), ctypes.byref(obj),
+                                                 None if g is None else g.ctypes.data_as(fp)))
+        return (obj.value, g) if grad else obj.value
+
+    def closure_train_step(self, state, target, lr, n_pairs=1):
+        b = self._batch(state, target, n_pairs)
+        obj = ctypes.c_float()
+        self._check(lib().cmlb_closure_train_step(self.h, ctypes.byref(b), float(lr), ctypes.byref(obj)))
+        return obj.value

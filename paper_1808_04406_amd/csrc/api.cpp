@@ -143,6 +143,15 @@ struct cmlb_ctx {
     double* red_u = nullptr;
     double* red_p = nullptr;
     double* red_out = nullptr;
+    // learned closure
+    bool closure_loaded = false;
+    bool closure_on = false;
+    float* cl_params = nullptr;   // FP32 master weights, Adam moments m1, m2 (3 x 2084), sigma (27)
+    void* cl_net = nullptr;       // packed network
+    float* cl_partials = nullptr; // per-block partial gradients
+    float* cl_grad = nullptr;     // reduced gradient + objective
+    int cl_blocks = 0;
+    int cl_step = 0;
 };
 
 namespace {
@@ -321,6 +330,10 @@ void cmlb_destroy(cmlb_ctx* c) {
     if (c->red_u) (void)hipFree(c->red_u);
     if (c->red_p) (void)hipFree(c->red_p);
     if (c->red_out) (void)hipFree(c->red_out);
+    if (c->cl_params) (void)hipFree(c->cl_params);
+    if (c->cl_net) (void)hipFree(c->cl_net);
+    if (c->cl_partials) (void)hipFree(c->cl_partials);
+    if (c->cl_grad) (void)hipFree(c->cl_grad);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -394,7 +407,8 @@ int cmlb_step(cmlb_ctx* c, int64_t n) {
     for (int64_t k = 0; k < n; ++k) {
         a.src = c->f[c->cur];
         a.dst = c->f[1 - c->cur];
-        if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream))
+        if (c->closure_on) launch_step_closure(a, c->cl_net, c->stream);
+        else if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream))
             return fail(c, CMLB_EINVAL, "unsupported configuration");
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
@@ -513,6 +527,162 @@ int cmlb_state(cmlb_ctx* c, void** f_cur, size_t* bytes, void** stream) {
 }
 
 int64_t cmlb_step_count(const cmlb_ctx* c) { return c ? c->steps : -1; }
+
+int cmlb_store_state_device(cmlb_ctx* c, void* dst) {
+    if (!c) return CMLB_EINVAL;
+    if (!dst) return fail(c, CMLB_EINVAL, "dst is NULL");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(c->p.storage);
+    hipError_t e = hipMemcpyAsync(dst, c->f[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "store state");
+    return CMLB_OK;
+}
+
+int cmlb_load_state_device(cmlb_ctx* c, const void* src) {
+    if (!c) return CMLB_EINVAL;
+    if (!src) return fail(c, CMLB_EINVAL, "src is NULL");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(c->p.storage);
+    hipError_t e = hipMemcpyAsync(c->f[c->cur], src, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load state");
+    c->initialised = true;
+    c->steps = 0;
+    return CMLB_OK;
+}
+
+int cmlb_box_filter(cmlb_ctx* c, int factor, void* dst) {
+    if (!c) return CMLB_EINVAL;
+    if (!dst) return fail(c, CMLB_EINVAL, "dst is NULL");
+    if (c->p.lattice != CMLB_D3Q27) return fail(c, CMLB_EINVAL, "box filter is for D3Q27 contexts");
+    if (factor < 1 || c->p.nx % factor || c->p.ny % factor || c->p.nz % factor)
+        return fail(c, CMLB_EINVAL, "grid sizes must be multiples of the filter factor");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    StepArgs a = base_args(c);
+    a.src = c->f[c->cur];
+    launch_box_filter(c->p.storage, a, factor, static_cast<float*>(dst), c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "box filter launch");
+    return CMLB_OK;
+}
+
+static int closure_ready(cmlb_ctx* c, bool need_loaded) {
+    if (c->p.lattice != CMLB_D3Q27 || c->p.storage != CMLB_F32 || c->p.model != CMLB_MODEL_CM)
+        return fail(c, CMLB_EINVAL, "the learned closure needs a D3Q27 CM context with FP32 storage");
+    if (need_loaded && !c->closure_loaded) return fail(c, CMLB_ESTATE, "no closure loaded");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    return CMLB_OK;
+}
+
+int cmlb_closure_load(cmlb_ctx* c, const float* params, const float* sigma) {
+    if (!c) return CMLB_EINVAL;
+    if (!params || !sigma) return fail(c, CMLB_EINVAL, "params and sigma are required");
+    int rc = closure_ready(c, false);
+    if (rc) return rc;
+    for (int k = 0; k < CMLB_CLOSURE_NPARAM; ++k)
+        if (!std::isfinite(params[k])) return fail(c, CMLB_EINVAL, "parameters must be finite");
+    for (int k = 0; k < 27; ++k)
+        if (!(sigma[k] > 0.0f) || !std::isfinite(sigma[k])) return fail(c, CMLB_EINVAL, "sigma must be positive");
+    hipError_t e;
+    if (!c->cl_params) {
+        if ((e = hipMalloc(&c->cl_params, (3 * CMLB_CLOSURE_NPARAM + 32) * sizeof(float))) != hipSuccess ||
+            (e = hipMalloc(&c->cl_net, closure_net_bytes())) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, CMLB_ENOMEM, "closure allocation failed");
+        }
+    }
+    float* P = c->cl_params;
+    float* sig = P + 3 * CMLB_CLOSURE_NPARAM;
+    if ((e = hipMemcpyAsync(P, params, CMLB_CLOSURE_NPARAM * sizeof(float), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy params");
+    if ((e = hipMemsetAsync(P + CMLB_CLOSURE_NPARAM, 0, 2 * CMLB_CLOSURE_NPARAM * sizeof(float), c->stream)) != hipSuccess)
+        return hip_fail(c, e, "clear optimiser state");
+    if ((e = hipMemcpyAsync(sig, sigma, 27 * sizeof(float), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy sigma");
+    launch_closure_pack(P, sig, c->cl_net, c->stream);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "pack launch");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "closure load");
+    c->closure_loaded = true;
+    c->cl_step = 0;
+    return CMLB_OK;
+}
+
+int cmlb_closure_enable(cmlb_ctx* c, int on) {
+    if (!c) return CMLB_EINVAL;
+    if (on) {
+        int rc = closure_ready(c, true);
+        if (rc) return rc;
+    }
+    c->closure_on = on != 0;
+    return CMLB_OK;
+}
+
+int cmlb_closure_get(cmlb_ctx* c, float* params) {
+    if (!c) return CMLB_EINVAL;
+    if (!params) return fail(c, CMLB_EINVAL, "params is NULL");
+    int rc = closure_ready(c, true);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(params, c->cl_params, CMLB_CLOSURE_NPARAM * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "copy params");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "closure get");
+    return CMLB_OK;
+}
+
+static int closure_gradient(cmlb_ctx* c, const cmlb_batch* b) {
+    if (!b || !b->state || !b->target || b->n_pairs < 1) return fail(c, CMLB_EINVAL, "bad batch");
+    if (c->p.nx % 64) return fail(c, CMLB_EINVAL, "closure training needs nx to be a multiple of 64");
+    hipError_t e;
+    if (!c->cl_partials) {
+        c->cl_blocks = 1024;
+        if ((e = hipMalloc(&c->cl_partials, (size_t)c->cl_blocks * closure_partial_stride() * sizeof(float))) != hipSuccess ||
+            (e = hipMalloc(&c->cl_grad, closure_partial_stride() * sizeof(float))) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, CMLB_ENOMEM, "closure training scratch");
+        }
+    }
+    StepArgs a = base_args(c);
+    launch_closure_train(static_cast<const float*>(b->state), static_cast<const float*>(b->target), b->n_pairs, a.g,
+                         (float)c->p.rho0, (float)c->omega[2], c->cl_net, c->cl_partials, c->cl_blocks, c->cl_grad,
+                         c->stream);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "closure training launch");
+    return CMLB_OK;
+}
+
+int cmlb_closure_objective(cmlb_ctx* c, const cmlb_batch* b, float* objective, float* grad) {
+    if (!c) return CMLB_EINVAL;
+    if (!objective) return fail(c, CMLB_EINVAL, "objective is NULL");
+    int rc = closure_ready(c, true);
+    if (rc) return rc;
+    if ((rc = closure_gradient(c, b))) return rc;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(objective, c->cl_grad + CMLB_CLOSURE_NPARAM, sizeof(float), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy objective");
+    if (grad && (e = hipMemcpyAsync(grad, c->cl_grad, CMLB_CLOSURE_NPARAM * sizeof(float), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy gradient");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "closure objective");
+    return CMLB_OK;
+}
+
+int cmlb_closure_train_step(cmlb_ctx* c, const cmlb_batch* b, float lr, float* objective) {
+    if (!c) return CMLB_EINVAL;
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(c, CMLB_EINVAL, "lr must be positive");
+    int rc = closure_ready(c, true);
+    if (rc) return rc;
+    if ((rc = closure_gradient(c, b))) return rc;
+    float* P = c->cl_params;
+    c->cl_step++;
+    launch_closure_adam(P, P + CMLB_CLOSURE_NPARAM, P + 2 * CMLB_CLOSURE_NPARAM, c->cl_grad, lr, c->cl_step, c->stream);
+    launch_closure_pack(P, P + 3 * CMLB_CLOSURE_NPARAM, c->cl_net, c->stream);
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "adam launch");
+    if (objective) {
+        if ((e = hipMemcpyAsync(objective, c->cl_grad + CMLB_CLOSURE_NPARAM, sizeof(float), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+            return hip_fail(c, e, "copy objective");
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "train step");
+    }
+    return CMLB_OK;
+}
 
 int cmlb_get_scale(const cmlb_ctx* c, double* scale) {
     if (!c || !scale) return CMLB_EINVAL;

@@ -377,6 +377,36 @@ __global__ __launch_bounds__(64) void k_reduce_final(const double* p1, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Box filter (coarse-graining) of a D3Q27 state: the mean of the deviations
+// over factor^3 blocks, written as FP32 deviations on the coarse grid.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(256) void k_box_filter(StepArgs a, int factor, float* __restrict__ dst) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    const T* src = static_cast<const T*>(a.src);
+    const uint32_t cx = a.g.nx / factor, cy = a.g.ny / factor, cz = a.g.nz / factor;
+    const uint64_t cplane = (uint64_t)cx * cy * cz;
+    const double inv = 1.0 / ((double)factor * factor * factor);
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < cplane * 27;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = c / cplane;
+        const uint64_t cn = c % cplane;
+        const uint32_t X = cn % cx, Y = (cn / cx) % cy, Z = cn / ((uint64_t)cx * cy);
+        double sum = 0.0;
+        for (int dz = 0; dz < factor; ++dz)
+            for (int dy = 0; dy < factor; ++dy) {
+                const uint64_t rowb = (uint64_t)i * a.g.plane +
+                                      (((uint64_t)(Z * factor + dz) * a.g.ny + (Y * factor + dy)) * a.g.nx) + X * factor;
+                for (int dx = 0; dx < factor; ++dx) sum += S::to_double(src[rowb + dx]);
+            }
+        double v = sum * inv;
+        if constexpr (S::kScaled) v *= (double)a.inv_s[i];
+        dst[c] = (float)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 static void step_shape(const GridArgs& g, dim3& grid, dim3& block, uint32_t rows) {
@@ -512,6 +542,18 @@ int launch_codec(int lattice, int storage, bool decode, void* stor, double* full
 }
 
 int reduce_blocks(uint64_t plane) { return (int)flat_grid(plane).x; }
+
+int launch_box_filter(int storage, const StepArgs& a, int factor, float* dst, hipStream_t s) {
+    const uint64_t coarse = (uint64_t)(a.g.nx / factor) * (a.g.ny / factor) * (a.g.nz / factor) * 27;
+    dim3 grid = flat_grid(coarse), block(256);
+    switch (storage) {
+        case kF64: hipLaunchKernelGGL((k_box_filter<kF64>), grid, block, 0, s, a, factor, dst); return 0;
+        case kF32: hipLaunchKernelGGL((k_box_filter<kF32>), grid, block, 0, s, a, factor, dst); return 0;
+        case kBF16: hipLaunchKernelGGL((k_box_filter<kBF16>), grid, block, 0, s, a, factor, dst); return 0;
+        case kF16: hipLaunchKernelGGL((k_box_filter<kF16>), grid, block, 0, s, a, factor, dst); return 0;
+    }
+    return -1;
+}
 
 int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,
                   hipStream_t s) {

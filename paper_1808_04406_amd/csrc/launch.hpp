@@ -20,4 +20,16 @@ int reduce_blocks(uint64_t plane);
 int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,
                   hipStream_t s);
 
+// Learned closure (kernels_closure.hip).
+size_t closure_net_bytes();
+int closure_partial_stride();
+void launch_closure_pack(const float* params, const float* norm, void* net, hipStream_t s);
+void launch_step_closure(const StepArgs& a, const void* net, hipStream_t s);
+void launch_closure_train(const float* state, const float* target, int64_t n_pairs, const GridArgs& g, float rho0,
+                          float omega2, const void* net, float* partials, int nblocks, float* grad, hipStream_t s);
+void launch_closure_adam(float* params, float* m1, float* m2, const float* grad, float lr, int step, hipStream_t s);
+
+// Box filter of a D3Q27 state to FP32 deviations on the coarse grid.
+int launch_box_filter(int storage, const StepArgs& a, int factor, float* dst, hipStream_t s);
+
 }  // namespace cmlb
