@@ -150,6 +150,10 @@ WORKLOADS = {
     "tgv512_f16": ("D3Q27", (512, 512, 512), "f16", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, FP16 scaled storage"),
     "tgv512_bf16": ("D3Q27", (512, 512, 512), "bf16", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, BF16 storage"),
     "tgv512_f64": ("D3Q27", (512, 512, 512), "f64", "D3Q27 CM-MRT 512^3 TGV, u0=0.05, Re=1e5, FP64 storage"),
+    "tgv128_f32": ("D3Q27", (128, 128, 128), "f32", "D3Q27 CM-MRT 128^3 TGV, u0=0.05, Re=1e5, FP32 storage"),
+    "tgv128_closure_f32": ("D3Q27", (128, 128, 128), "f32", "D3Q27 CM-MRT 128^3 TGV, u0=0.05, Re=1e5, FP32 "
+                           "storage, learned closure (per-node 27-32-32-4 MLP on the matrix cores) setting the "
+                           "rates of orders 3..6"),
     "waves1024_f32": ("D2Q37", (1024, 1024), "f32", "D2Q37 thermal CM-MRT 1024^2, shear + thermal waves "
                       "(amplitude 0.01), tau_2=0.6, Pr=0.71, background 0.1, FP32 storage"),
     "waves2048_f32": ("D2Q37", (2048, 2048), "f32", "D2Q37 thermal CM-MRT 2048^2, shear + thermal waves "
@@ -174,6 +178,11 @@ def setup_workload(name, torch, cmlb, inputs, stream):
         tau = tau_shear(n, U0, re)
         taus = rates(tau)
         ctx = cmlb.Context("D3Q27", shape, storage=storage, tau=taus, external=bufs, stream=stream)
+        if name.endswith("closure_f32"):
+            import numpy as np
+            params = 0.3 * np.random.default_rng(0).normal(size=cmlb.CLOSURE_NPARAM)
+            ctx.closure_load(params, np.full(27, 0.01))
+            ctx.closure_enable(True)
         rho, u = inputs.tgv3d(n, U0)
     else:
         n = shape[0]
@@ -222,6 +231,8 @@ def run(torch, cmlb, inputs, stream, args):
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic(alg_bytes) if args.workload == "tgv256_f32" else None
     kernel = KERNEL if lattice == "D3Q27" else "k_step_d37<%s, kCM>" % storage
+    if args.workload.endswith("closure_f32"):
+        kernel = "k_step_closure"
     out = {
         "metric": "MLUPS of CM-MRT stream+collide, % HBM roofline; error vs FP64 oracle",
         "value": round(value, 1),

@@ -76,23 +76,38 @@ def waves2d(nx: int, ny: int, shear_amp: float = 0.0, thermal_amp: float = 0.0,
 def random_multimode(n: int, seed: int, kmax: int = 4, umax: float = 0.05, dim: int = 3):
     """Random-phase solenoidal velocity field on an n^dim periodic grid.
 
-    Modes with 1 <= |k| <= kmax get Gaussian complex amplitudes from
-    ``numpy.random.default_rng(seed)``, are projected onto the plane normal
-    to k, and the field is scaled so that max |u| = umax.  rho = 1.
+    Every integer mode k with 1 <= |k| <= kmax gets a complex Gaussian
+    amplitude vector from ``numpy.random.default_rng(seed)`` (drawn on the
+    (2 kmax + 1)^dim mode box, so the field does not depend on n), projected
+    onto the plane normal to k; u is the real part of the mode sum, scaled so
+    that max |u| = umax.  The sum is evaluated exactly by separable
+    transforms (small DFTs along x and y, one matrix product along z).
+    rho = 1.
     """
     rng = np.random.default_rng(seed)
-    shape = (n,) * dim
-    ks = np.meshgrid(*[np.fft.fftfreq(n, 1.0 / n)] * dim, indexing="ij")
-    kk = np.stack(list(reversed(ks)))  # component d along axis (x fastest)
+    m = 2 * kmax + 1
+    ks = np.arange(-kmax, kmax + 1)
+    kk = np.stack(np.meshgrid(*[ks] * dim, indexing="ij"))[::-1]  # kk[d] along axis d (x first)
     kmag = np.sqrt((kk ** 2).sum(0))
     mask = (kmag >= 1) & (kmag <= kmax)
-    amp = (rng.normal(size=(dim,) + shape) + 1j * rng.normal(size=(dim,) + shape)) * mask
+    amp = (rng.normal(size=(dim,) + (m,) * dim) + 1j * rng.normal(size=(dim,) + (m,) * dim)) * mask
     with np.errstate(invalid="ignore", divide="ignore"):
         kdotA = (kk * amp).sum(0) / np.where(kmag > 0, kmag ** 2, 1.0)
     amp = amp - kk * kdotA
-    u = np.real(np.fft.ifftn(amp, axes=tuple(range(1, dim + 1))))
+    pos = np.arange(n)
+    E = np.exp(2j * np.pi * np.outer(ks, pos) / n)           # [mode, position]
+    u = np.empty((dim,) + (n,) * dim)
+    for d in range(dim):
+        a = amp[d]                                            # axes (kz,) ky, kx
+        if dim == 3:
+            b = np.einsum("zyk,kx->zyx", a, E)                # along x
+            c = np.einsum("zkx,ky->zyx", b, E)                # along y: [kz, y, x]
+            u[d] = (E.T @ c.reshape(m, n * n)).real.reshape(n, n, n)
+        else:
+            b = np.einsum("yk,kx->yx", a, E)
+            u[d] = (E.T @ b).real
     u *= umax / np.sqrt((u ** 2).sum(0)).max()
-    return np.ones(shape), u
+    return np.ones((n,) * dim), u
 
 
 def random_fields(shape, seed: int, drho: float = 0.05, umax: float = 0.05, dtheta: float = 0.0):
