@@ -182,6 +182,7 @@ def setup_workload(name, torch, cmlb, inputs, stream):
             import numpy as np
             params = 0.3 * np.random.default_rng(0).normal(size=cmlb.CLOSURE_NPARAM)
             ctx.closure_load(params, np.full(27, 0.01))
+            ctx.closure_tie_even(True)   # orders 4, 6 at omega_2: stable as tau_2 -> 1/2
             ctx.closure_enable(True)
         rho, u = inputs.tgv3d(n, U0)
     else:

@@ -193,6 +193,14 @@ int cmlb_closure_load(cmlb_ctx *ctx, const float *params, const float *sigma);
 /* Use (1) or stop using (0) the network rates in cmlb_step. */
 int cmlb_closure_enable(cmlb_ctx *ctx, int on);
 
+/* With on = 1, orders 4 and 6 relax at omega_2 instead of the network's
+ * rates (its outputs 1 and 3 are then unused and get no gradient).  A
+ * central monomial of order 4 or 6 carries second-order Hermite content, and
+ * rates differing from omega_2 make the linearised update grow as
+ * tau_2 -> 1/2; the network's range [0.5, 1.95] cannot reach omega_2 there.
+ * Default 0.  Needs a loaded closure; kept across cmlb_closure_load. */
+int cmlb_closure_tie_even(cmlb_ctx *ctx, int on);
+
 /* Current FP32 master parameters (host array of 2084). */
 int cmlb_closure_get(cmlb_ctx *ctx, float *params);
 

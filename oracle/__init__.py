@@ -61,8 +61,8 @@ def lib():
         L.orc_moments.argtypes = [ctypes.c_int, l, d, d, d, d]
         L.orc_mlp_forward.argtypes = [d, ctypes.c_int, d, d]
         L.orc_closure_inputs.argtypes = [ctypes.c_int, d, d, d]
-        L.orc_collide_closure.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, d]
-        L.orc_closure_loss_grad.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, d, d]
+        L.orc_collide_closure.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, ctypes.c_int, d, d]
+        L.orc_closure_loss_grad.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, ctypes.c_int, d, d]
         L.orc_gather_nodes.argtypes = [ctypes.c_int, l, l, l, d, l, ctypes.POINTER(ctypes.c_int64), d]
         _lib = L
     return _lib
@@ -276,20 +276,22 @@ def closure_inputs(f, norm):
     return x
 
 
-def collide_closure(cfg: Cfg, f, params, norm):
-    """D3Q27 collision with network rates; returns (f*[n, 27], omega[n, 4])."""
+def collide_closure(cfg: Cfg, f, params, norm, tie_even=False):
+    """D3Q27 collision with network rates; returns (f*[n, 27], omega[n, 4]).
+    tie_even: orders 4 and 6 relax at omega_2 instead of the network's rate."""
     f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
     out = np.zeros_like(f)
     om = np.zeros((f.shape[0], 4))
     rc = lib().orc_collide_closure(ctypes.byref(cfg.c()), f.shape[0], _p(f),
                                    _p(np.ascontiguousarray(params, np.float64)),
-                                   _p(np.ascontiguousarray(norm, np.float64)), _p(out), _p(om))
+                                   _p(np.ascontiguousarray(norm, np.float64)), 1 if tie_even else 0,
+                                   _p(out), _p(om))
     if rc:
         raise RuntimeError("closure collision needs a D3Q27 CM configuration")
     return out, om
 
 
-def closure_loss_grad(cfg: Cfg, f, fbar, params, norm):
+def closure_loss_grad(cfg: Cfg, f, fbar, params, norm, tie_even=False):
     """Mean over nodes of sum_i (f*_i - fbar_i)^2 / w_i and its gradient."""
     f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
     fbar = np.ascontiguousarray(np.atleast_2d(fbar), np.float64)
@@ -297,7 +299,8 @@ def closure_loss_grad(cfg: Cfg, f, fbar, params, norm):
     grad = np.zeros(MLP_NPARAM)
     rc = lib().orc_closure_loss_grad(ctypes.byref(cfg.c()), f.shape[0], _p(f), _p(fbar),
                                      _p(np.ascontiguousarray(params, np.float64)),
-                                     _p(np.ascontiguousarray(norm, np.float64)), ctypes.byref(loss), _p(grad))
+                                     _p(np.ascontiguousarray(norm, np.float64)), 1 if tie_even else 0,
+                                     ctypes.byref(loss), _p(grad))
     if rc:
         raise RuntimeError("closure loss needs a D3Q27 CM configuration")
     return loss.value, grad

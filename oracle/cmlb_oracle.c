@@ -1033,9 +1033,11 @@ int orc_closure_inputs(int n, const double *f, const double *norm, double *x)
     return 0;
 }
 
-/* Collision with the network's rates for orders 3..6 (omega_2 from cfg). */
+/* Collision with the network's rates for orders 3..6 (omega_2 from cfg).
+ * With tie_even, orders 4 and 6 relax at omega_2 instead (the network's
+ * outputs for them are unused). */
 int orc_collide_closure(const orc_cfg *cfg, int n, const double *f, const double *params, const double *norm,
-                        double *out, double *omega_out)
+                        int tie_even, double *out, double *omega_out)
 {
     const orc_lattice *L = lattice(ORC_D3Q27);
     if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM) return -1;
@@ -1046,6 +1048,7 @@ int orc_collide_closure(const orc_cfg *cfg, int n, const double *f, const double
         mlp_forward(params, x, &t);
         orc_cfg c = *cfg;
         for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t.z[j]);
+        if (tie_even) c.omega[4] = c.omega[6] = cfg->omega[2];
         if (omega_out)
             for (int j = 0; j < MLP_NOUT; ++j) omega_out[(size_t)k * MLP_NOUT + j] = c.omega[3 + j];
         collide_tp(L, &c, f + (size_t)k * 27, out + (size_t)k * 27);
@@ -1062,7 +1065,7 @@ int orc_collide_closure(const orc_cfg *cfg, int n, const double *f, const double
  * difference of two collisions with omega_m = 1 and omega_m = 0; the rest is
  * the chain rule through the sigmoid map and the two GELU layers. */
 int orc_closure_loss_grad(const orc_cfg *cfg, int n, const double *f, const double *fbar, const double *params,
-                          const double *norm, double *loss_out, double *grad)
+                          const double *norm, int tie_even, double *loss_out, double *grad)
 {
     const orc_lattice *L = lattice(ORC_D3Q27);
     if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM || n < 1) return -1;
@@ -1078,6 +1081,7 @@ int orc_closure_loss_grad(const orc_cfg *cfg, int n, const double *f, const doub
         mlp_forward(params, x, &t);
         orc_cfg c = *cfg;
         for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t.z[j]);
+        if (tie_even) c.omega[4] = c.omega[6] = cfg->omega[2];
         collide_tp(L, &c, fk, fs);
         for (int i = 0; i < 27; ++i) {
             double e = fs[i] - tk[i];
@@ -1086,6 +1090,7 @@ int orc_closure_loss_grad(const orc_cfg *cfg, int n, const double *f, const doub
         }
         double dz[MLP_NOUT];
         for (int j = 0; j < MLP_NOUT; ++j) {
+            if (tie_even && (j == 1 || j == 3)) { dz[j] = 0.0; continue; }
             orc_cfg c1 = c, c0 = c;
             c1.omega[3 + j] = 1.0;
             c0.omega[3 + j] = 0.0;

@@ -95,6 +95,7 @@ def lib():
         L.cmlb_box_filter.argtypes = [vp, c_int, vp]
         L.cmlb_closure_load.argtypes = [vp, fp, fp]
         L.cmlb_closure_enable.argtypes = [vp, c_int]
+        L.cmlb_closure_tie_even.argtypes = [vp, c_int]
         L.cmlb_closure_get.argtypes = [vp, fp]
         L.cmlb_closure_objective.argtypes = [vp, P(Batch), fp, fp]
         L.cmlb_closure_train_step.argtypes = [vp, P(Batch), ctypes.c_float, fp]
@@ -285,6 +286,9 @@ class Context:
 
     def closure_enable(self, on=True):
         self._check(lib().cmlb_closure_enable(self.h, 1 if on else 0))
+
+    def closure_tie_even(self, on=True):
+        self._check(lib().cmlb_closure_tie_even(self.h, 1 if on else 0))
 
     def closure_get(self):
         p = np.zeros(CLOSURE_NPARAM, np.float32)

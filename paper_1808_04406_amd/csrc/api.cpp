@@ -152,6 +152,7 @@ struct cmlb_ctx {
     float* cl_grad = nullptr;     // reduced gradient + objective
     int cl_blocks = 0;
     int cl_step = 0;
+    int cl_tie_even = 0;
 };
 
 namespace {
@@ -600,7 +601,7 @@ int cmlb_closure_load(cmlb_ctx* c, const float* params, const float* sigma) {
         return hip_fail(c, e, "clear optimiser state");
     if ((e = hipMemcpyAsync(sig, sigma, 27 * sizeof(float), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
         return hip_fail(c, e, "copy sigma");
-    launch_closure_pack(P, sig, c->cl_net, c->stream);
+    launch_closure_pack(P, sig, c->cl_tie_even, c->cl_net, c->stream);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "pack launch");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "closure load");
     c->closure_loaded = true;
@@ -615,6 +616,19 @@ int cmlb_closure_enable(cmlb_ctx* c, int on) {
         if (rc) return rc;
     }
     c->closure_on = on != 0;
+    return CMLB_OK;
+}
+
+int cmlb_closure_tie_even(cmlb_ctx* c, int on) {
+    if (!c) return CMLB_EINVAL;
+    int rc = closure_ready(c, true);
+    if (rc) return rc;
+    c->cl_tie_even = on != 0;
+    float* P = c->cl_params;
+    launch_closure_pack(P, P + 3 * CMLB_CLOSURE_NPARAM, c->cl_tie_even, c->cl_net, c->stream);
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "pack launch");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "tie even");
     return CMLB_OK;
 }
 
@@ -673,7 +687,7 @@ int cmlb_closure_train_step(cmlb_ctx* c, const cmlb_batch* b, float lr, float* o
     float* P = c->cl_params;
     c->cl_step++;
     launch_closure_adam(P, P + CMLB_CLOSURE_NPARAM, P + 2 * CMLB_CLOSURE_NPARAM, c->cl_grad, lr, c->cl_step, c->stream);
-    launch_closure_pack(P, P + 3 * CMLB_CLOSURE_NPARAM, c->cl_net, c->stream);
+    launch_closure_pack(P, P + 3 * CMLB_CLOSURE_NPARAM, c->cl_tie_even, c->cl_net, c->stream);
     hipError_t e;
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "adam launch");
     if (objective) {

@@ -39,6 +39,7 @@ struct ClosureNet {
     float inv_norm[kNIn];
     float w2f[kNH][kNH];   // BF16-rounded weights as FP32, for the backward pass
     float w3f[kNOut][kNH];
+    int tie_even;          // orders 4 and 6 relax at omega_2 (network outputs 1 and 3 unused)
 };
 
 // K order of layers 2 and 3 (see the header comment).

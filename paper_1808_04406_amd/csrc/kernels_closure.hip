@@ -10,8 +10,9 @@ namespace cmlb {
 // FP32 parameters -> packed BF16 MFMA fragments (one block of 256 threads)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_closure_pack(const float* __restrict__ P, const float* __restrict__ norm,
-                                                      ClosureNet* __restrict__ net) {
+                                                      int tie_even, ClosureNet* __restrict__ net) {
     const int t = threadIdx.x;
+    if (t == 0) net->tie_even = tie_even;
     auto bf = [](float v) { return (__bf16)v; };
     if (t < 128) {  // layer-1 and layer-2 fragments: (mt, lane)
         const int mt = t >> 6, lane = t & 63, g = lane >> 4, r = lane & 15;
@@ -56,6 +57,7 @@ __device__ __forceinline__ void closure_rates(const ClosureNet* net, const float
     mlp_forward_wave<KEEP>(net, x, xs, z, tr);
 #pragma unroll
     for (int j = 0; j < kNOut; ++j) om[3 + j] = 0.5f + 1.45f * sigmoid_f(z[j]);
+    if (net->tie_even) om[4] = om[6] = om[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -214,10 +216,11 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
                 constexpr int order = p % 3 + (p / 3) % 3 + p / 9;
                 if constexpr (order >= 3) dom[order] -= h[p] * neq[p];
             });
+            const bool tied = net->tie_even != 0;
 #pragma unroll
             for (int j = 0; j < kNOut; ++j) {
                 const float s = sigmoid_f(zz[j]);
-                DZ[lane][j] = dom[3 + j] * 1.45f * s * (1.0f - s);
+                DZ[lane][j] = (tied && (j & 1)) ? 0.0f : dom[3 + j] * 1.45f * s * (1.0f - s);
             }
         }
         __syncthreads();
@@ -309,8 +312,8 @@ __global__ __launch_bounds__(256) void k_closure_adam(float* __restrict__ P, flo
 size_t closure_net_bytes() { return sizeof(ClosureNet); }
 int closure_partial_stride() { return kPartialStride; }
 
-void launch_closure_pack(const float* P, const float* norm, void* net, hipStream_t s) {
-    hipLaunchKernelGGL(k_closure_pack, dim3(1), dim3(256), 0, s, P, norm, static_cast<ClosureNet*>(net));
+void launch_closure_pack(const float* P, const float* norm, int tie_even, void* net, hipStream_t s) {
+    hipLaunchKernelGGL(k_closure_pack, dim3(1), dim3(256), 0, s, P, norm, tie_even, static_cast<ClosureNet*>(net));
 }
 
 void launch_step_closure(const StepArgs& a, const void* net, hipStream_t s) {

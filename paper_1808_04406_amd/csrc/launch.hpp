@@ -23,7 +23,7 @@ int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, doubl
 // Learned closure (kernels_closure.hip).
 size_t closure_net_bytes();
 int closure_partial_stride();
-void launch_closure_pack(const float* params, const float* norm, void* net, hipStream_t s);
+void launch_closure_pack(const float* params, const float* norm, int tie_even, void* net, hipStream_t s);
 void launch_step_closure(const StepArgs& a, const void* net, hipStream_t s);
 void launch_closure_train(const float* state, const float* target, int64_t n_pairs, const GridArgs& g, float rho0,
                           float omega2, const void* net, float* partials, int nblocks, float* grad, hipStream_t s);

@@ -189,7 +189,7 @@ def _input_scales(state, n, samples=20000, seed=0):
 
 
 def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=400, pairs_per_seed=3, gap=400,
-            train_steps=400, lr=2e-3, tgv_coarse_steps=1250, every=50, stream=None):
+            train_steps=600, lr=2e-3, tgv_coarse_steps=1250, every=50, stream=None):
     """Learned closure: data from fine random multi-mode runs at Re = 1e5
     (acoustic scaling, coarse time step = factor fine steps), box-filtered;
     training on the GPU; gain on held-out seeds against fixed rates; TGV
@@ -231,23 +231,25 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
     test = [p for s_ in held_out for p in data[s_]]
     sigma = _input_scales(train[0][0].cpu().numpy(), nc)
     res["sigma"] = sigma.tolist()
-    # 2. training
+    # 2. training (orders 4 and 6 tied to omega_2, the network sets orders 3 and 5)
     ctx = cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)
     fixed1 = _constant_net([1.0, 1.0, 1.0, 1.0])
-    clamp = _constant_net([1.0, 1.94, 1.0, 1.94])
+    odd1 = _constant_net([1.0, 1.0, 1.0, 1.0], seed=1, scale=0.1)
 
-    def objective(params, pairs):
+    def objective(params, pairs, tie):
         ctx.closure_load(params, sigma)
+        ctx.closure_tie_even(tie)
         return float(np.mean([ctx.closure_objective(a, b, grad=False) for a, b in pairs]))
 
-    res["objective_fixed_rate1_test"] = objective(fixed1, test)
-    res["objective_fixed_even_1.94_test"] = objective(clamp, test)
-    ctx.closure_load(_constant_net([1.0, 1.0, 1.0, 1.0], seed=1, scale=0.1), sigma)
+    res["objective_fixed_rate1_test"] = objective(fixed1, test, False)
+    res["objective_stable_fixed_test"] = objective(odd1, test, True)
+    ctx.closure_load(odd1, sigma)
+    ctx.closure_tie_even(True)
     hist = []
     t1 = time.perf_counter()
     for it in range(train_steps):
         a, b = train[it % len(train)]
-        hist.append(ctx.closure_train_step(a, b, lr))
+        hist.append(ctx.closure_train_step(a, b, lr * (1.0 - it / train_steps)))
         if it % 50 == 0:
             print(f"train step {it}: objective {hist[-1]:.4e}", flush=True)
     torch.cuda.synchronize()
@@ -255,12 +257,13 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
     res["train_history"] = hist
     learned = ctx.closure_get().astype(np.float64)
     res["params"] = learned.tolist()
-    res["objective_learned_train"] = objective(learned, train)
-    res["objective_learned_test"] = objective(learned, test)
+    res["objective_learned_train"] = objective(learned, train, True)
+    res["objective_learned_test"] = objective(learned, test, True)
+    res["objective_stable_fixed_train"] = objective(odd1, train, True)
     res["gain_vs_rate1"] = res["objective_fixed_rate1_test"] / res["objective_learned_test"]
-    res["gain_vs_even_1.94"] = res["objective_fixed_even_1.94_test"] / res["objective_learned_test"]
-    print(f"held-out objective: fixed rates 1 {res['objective_fixed_rate1_test']:.4e}, even 1.94 "
-          f"{res['objective_fixed_even_1.94_test']:.4e}, learned {res['objective_learned_test']:.4e}", flush=True)
+    res["gain_vs_stable_fixed"] = res["objective_stable_fixed_test"] / res["objective_learned_test"]
+    print(f"held-out objective: fixed rates 1 {res['objective_fixed_rate1_test']:.4e}, stable fixed "
+          f"{res['objective_stable_fixed_test']:.4e}, learned {res['objective_learned_test']:.4e}", flush=True)
     del data, train, test
     torch.cuda.empty_cache()
     # 3. Taylor-Green rollout: coarse runs from the filtered fine initial state
@@ -275,6 +278,7 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
                                                    stream=stream),
             "fixed_rate1": cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)}
     runs["learned"].closure_load(learned, sigma)
+    runs["learned"].closure_tie_even(True)
     runs["learned"].closure_enable(True)
     fine.box_filter(factor, buf)
     for c in runs.values():

@@ -35,7 +35,8 @@ def near_eq_state(orc, shape, seed, eps=0.03):
     return S * inputs.perturbation(S.shape, seed + 1, eps)
 
 
-def test_closure_step_matches_oracle(cm, orc):
+@pytest.mark.parametrize("tie", [False, True])
+def test_closure_step_matches_oracle(cm, orc, tie):
     shape = (3, 5, 128)
     S = near_eq_state(orc, shape, 50)
     S = (S - orc.lattice("D3Q27")["w"][:, None, None, None]).astype(np.float32).astype(np.float64) \
@@ -44,6 +45,7 @@ def test_closure_step_matches_oracle(cm, orc):
     sigma = np.random.default_rng(52).uniform(0.005, 0.03, 27).astype(np.float32).astype(np.float64)
     ctx = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.6})
     ctx.closure_load(P, sigma)
+    ctx.closure_tie_even(tie)
     ctx.closure_enable(True)
     ctx.set_populations(S)
     ctx.step(1)
@@ -52,7 +54,7 @@ def test_closure_step_matches_oracle(cm, orc):
     nodes = np.arange(int(np.prod(shape)))
     fin = orc.gather_nodes("D3Q27", S, nodes)
     cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
-    ref, om = orc.collide_closure(cfg, fin, P, sigma)
+    ref, om = orc.collide_closure(cfg, fin, P, sigma, tie_even=tie)
     plain = orc.collide(orc.Cfg(lattice="D3Q27", tau={2: 0.6}, tau_hi=1.0), fin)
     assert om.std() > 0.05   # the network really varies the rates
     controlled = np.abs(ref - plain).max()
@@ -83,7 +85,8 @@ def test_constant_network_equals_plain_kernel(cm, orc):
     assert np.abs(fa - fb).max() <= 1e-6 * scale + 1e-7
 
 
-def test_closure_gradient_matches_oracle(cm, orc):
+@pytest.mark.parametrize("tie", [False, True])
+def test_closure_gradient_matches_oracle(cm, orc, tie):
     import torch
     shape = (3, 4, 64)
     n = int(np.prod(shape))
@@ -96,13 +99,14 @@ def test_closure_gradient_matches_oracle(cm, orc):
     sigma = np.random.default_rng(63).uniform(0.005, 0.03, 27).astype(np.float32).astype(np.float64)
     ctx = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.6})
     ctx.closure_load(P, sigma)
+    ctx.closure_tie_even(tie)
     obj, g = ctx.closure_objective(st, tg, n_pairs=2)
     ctx.destroy()
     cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
     fin = np.concatenate([orc.gather_nodes("D3Q27", (st[k].double().cpu().numpy().reshape((27,) + shape)
                                                      + w[:, None, None, None]), np.arange(n)) for k in range(2)])
     tgt = np.concatenate([(tg[k].double().cpu().numpy() + w[:, None]).T for k in range(2)])
-    o_obj, o_g = orc.closure_loss_grad(cfg, fin, tgt, P, sigma)
+    o_obj, o_g = orc.closure_loss_grad(cfg, fin, tgt, P, sigma, tie_even=tie)
     rel = np.linalg.norm(g - o_g) / np.linalg.norm(o_g)
     print(f"objective {obj:.6e} vs {o_obj:.6e}; gradient relative L2 error {rel:.3e}")
     assert obj == pytest.approx(o_obj, rel=1e-3)

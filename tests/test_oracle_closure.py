@@ -97,3 +97,36 @@ def test_gradient_matches_finite_differences(orc):
         Pm[k] -= h
         fd = (orc.closure_loss_grad(cfg, f, fbar, Pp, norm)[0] - orc.closure_loss_grad(cfg, f, fbar, Pm, norm)[0]) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-12), k
+
+
+def test_tie_even(orc):
+    """With orders 4 and 6 tied to omega_2 the network's outputs 1 and 3 are
+    unused: a constant network gives the plain collision with the tied rates,
+    and the gradient of those outputs' weights vanishes (finite differences
+    agree on the others)."""
+    f = states(orc, 6, 12)
+    norm = np.ones(27)
+    P = random_params(13)
+    W1, b1, W2, b2, W3, b3 = unpack(P)
+    W3[:] = 0.0
+    rates = np.array([0.9, 1.3, 0.7, 1.8])
+    b3[:] = np.log((rates - 0.5) / 1.45 / (1 - (rates - 0.5) / 1.45))
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
+    got, om = orc.collide_closure(cfg, f, P, norm, tie_even=True)
+    ref = orc.collide(orc.Cfg(lattice="D3Q27", tau={2: 0.6, 3: 1 / 0.9, 4: 0.6, 5: 1 / 0.7, 6: 0.6}), f)
+    assert np.abs(got - ref).max() < 1e-15
+    fbar = states(orc, 6, 14)
+    P = random_params(15, scale=0.3)
+    norm = np.random.default_rng(16).uniform(0.002, 0.02, 27)
+    L0, g = orc.closure_loss_grad(cfg, f, fbar, P, norm, tie_even=True)
+    W3g = g[1952:2080].reshape(4, 32)
+    assert np.abs(W3g[1]).max() == 0.0 and np.abs(W3g[3]).max() == 0.0
+    assert g[2081] == 0.0 and g[2083] == 0.0 and abs(g[2080]) > 0
+    h = 1e-4
+    for k in (5, 900, 1960, 2080, 2082):
+        Pp, Pm = P.copy(), P.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        fd = (orc.closure_loss_grad(cfg, f, fbar, Pp, norm, True)[0]
+              - orc.closure_loss_grad(cfg, f, fbar, Pm, norm, True)[0]) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-12), k
