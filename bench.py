@@ -39,7 +39,7 @@ STORAGE_BYTES = 4
 PEAK_HBM_GBS = 8000.0
 KERNEL = "k_step_tp<3, kF32>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q27_256_f32.json")
-KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/kernels.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
+KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/step_tp.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
                   "paper_1808_04406_amd/csrc/common.hpp"]
 
 

@@ -47,9 +47,30 @@ __host__ __device__ constexpr int kperm(int k) {
     return (k % 8) < 4 ? 4 * (k / 8) + (k % 8) : 16 + 4 * (k / 8) + (k % 8) - 4;
 }
 
-__device__ __forceinline__ float gelu_f(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+// Normal CDF Phi(a) and density factor exp(-a^2 / 2), branch-free.  Phi uses
+// the rational approximation of Hastings as printed by Abramowitz and Stegun
+// (formula 7.1.26: erf(y) = 1 - t (a1 + t (a2 + ... + t a5)) exp(-y^2),
+// t = 1 / (1 + p y), |error| <= 1.5e-7), applied at y = |a| / sqrt(2).
+__device__ __forceinline__ float normal_cdf_f(float a, float& e) {
+    const float y = fabsf(a) * 0.70710678118654752f;
+    const float t = recip<float>(fmaf(0.3275911f, y, 1.0f));
+    float poly = fmaf(t, 1.061405429f, -1.453152027f);
+    poly = fmaf(t, poly, 1.421413741f);
+    poly = fmaf(t, poly, -0.284496736f);
+    poly = fmaf(t, poly, 0.254829592f);
+    poly *= t;
+    e = __expf(-y * y);
+    const float q = 0.5f * poly * e;   // Phi(-|a|)
+    return a >= 0.0f ? 1.0f - q : q;
+}
+__device__ __forceinline__ float gelu_f(float a) {
+    float e;
+    return a * normal_cdf_f(a, e);
+}
 __device__ __forceinline__ float gelu_grad_f(float a) {
-    return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * __expf(-0.5f * a * a);
+    float e;
+    const float phi = normal_cdf_f(a, e);
+    return phi + a * 0.39894228040143268f * e;
 }
 __device__ __forceinline__ float sigmoid_f(float z) { return 1.0f / (1.0f + __expf(-z)); }
 

@@ -32,6 +32,18 @@ __device__ __forceinline__ R recip(R x) {
     else return R(1) / x;
 }
 
+// Periodic neighbour indices.
+__device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+
+// source coordinate v - e (periodic), |e| <= 3, for the D2Q37 gather
+__device__ __forceinline__ uint32_t wrap_sub(uint32_t v, int e, uint32_t n) {
+    int s = (int)v - e;
+    s += (s < 0) ? (int)n : 0;
+    s -= (s >= (int)n) ? (int)n : 0;
+    return (uint32_t)s;
+}
+
 // ---------------------------------------------------------------------------
 // Lattice velocity tables.
 // D2Q9 / D3Q27: e in {-1,0,1}^D, index i = (ex+1) + 3(ey+1) + 9(ez+1).

@@ -1,127 +1,19 @@
-// HIP kernels of the cmlb library (gfx950) and their host launchers.
+// HIP kernels of the cmlb library (gfx950) other than the step kernels
+// (step_tp.hip, step_d37.hip, kernels_closure.hip), and their launchers.
 //
-//  k_step_tp / k_step_d37   fused pull-stream + collide (the hot path)
 //  k_init_*                 state <- discrete equilibrium of given fields
 //  k_moments                rho, u, theta readout (FP64)
 //  k_decode / k_encode      full FP64 populations <-> storage
 //  k_reduce_*               deterministic FP64 global diagnostics
 //
 // Layout: populations are structure-of-arrays F[i][z][y][x], x fastest, in
-// the storage type.  The step kernel runs one thread per node; a block covers
-// one contiguous x-segment of a row, so the y/z neighbour rows of every
-// population are block-uniform addresses and each wavefront reads and writes
-// 27 (37) contiguous runs.  Two buffers alternate (pull from one, write the
-// other), so reads and writes never alias.
+// the storage type.
 #include "launch.hpp"
 
 #include "collide_d2q37.hpp"
 #include "collide_tp.hpp"
 
 namespace cmlb {
-
-__device__ __forceinline__ uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
-__device__ __forceinline__ uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
-
-// source coordinate v - e (periodic), |e| <= 3, for the D2Q37 gather
-__device__ __forceinline__ uint32_t wrap_sub(uint32_t v, int e, uint32_t n) {
-    int s = (int)v - e;
-    s += (s < 0) ? (int)n : 0;
-    s -= (s >= (int)n) ? (int)n : 0;
-    return (uint32_t)s;
-}
-
-// ---------------------------------------------------------------------------
-// Hot path: D2Q9 / D3Q27 stream + collide
-// ---------------------------------------------------------------------------
-template <int D, int ST>
-__global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
-    using S = Store<ST>;
-    using R = typename S::R;
-    using T = typename S::T;
-    constexpr int Q = TP<D>::Q;
-    const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const uint32_t chunk = blockIdx.x % a.g.nchunks;
-    const uint32_t row = blockIdx.x / a.g.nchunks;
-    const uint32_t x = chunk * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    const uint32_t y = row % ny, z = row / ny;
-    // Row bases are block-uniform (scalar registers); lanes add a 32-bit byte
-    // offset, which maps onto the saddr + voffset form of global loads/stores.
-    const char* __restrict__ src = static_cast<const char*>(a.src);
-    char* __restrict__ dst = static_cast<char*>(a.dst);
-    const uint64_t plane_bytes = a.g.plane * sizeof(T);
-    const uint32_t xoff[3] = {wrap_inc(x, nx) * (uint32_t)sizeof(T), x * (uint32_t)sizeof(T),
-                              wrap_dec(x, nx) * (uint32_t)sizeof(T)};  // x - e for e = -1, 0, +1
-    const uint32_t ysrc[3] = {wrap_inc(y, ny), y, wrap_dec(y, ny)};
-    const uint32_t zsrc[3] = {D == 3 ? wrap_inc(z, nz) : 0u, z, D == 3 ? wrap_dec(z, nz) : 0u};
-
-    R h[Q];
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int ex = TP<D>::ex(i), ey = TP<D>::ey(i), ez = TP<D>::ez(i);
-        const char* rowp = src + i * plane_bytes + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * nx * sizeof(T);
-        R v = S::load(reinterpret_cast<const T*>(rowp + xoff[ex + 1]));
-        if constexpr (S::kScaled) v *= R(a.inv_s[i]);
-        h[i] = v;
-    });
-
-    R om[8];
-    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
-    tp_collide<D, R>(h, R(a.rho0), om);
-
-    char* outrow = dst + ((uint64_t)z * ny + y) * nx * sizeof(T);
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        R v = h[i];
-        if constexpr (S::kScaled) v *= R(a.s[i]);
-        S::store(reinterpret_cast<T*>(outrow + i * plane_bytes + xoff[1]), v);
-    });
-}
-
-// ---------------------------------------------------------------------------
-// Hot path: D2Q37 stream + collide (order-4 Hermite truncation)
-// ---------------------------------------------------------------------------
-template <int ST, int MODEL>
-__global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
-    using S = Store<ST>;
-    using R = typename S::R;
-    using T = typename S::T;
-    const uint32_t nx = a.g.nx, ny = a.g.ny;
-    const uint32_t chunk = blockIdx.x % a.g.nchunks;
-    const uint32_t y = blockIdx.x / a.g.nchunks;
-    const uint32_t x = chunk * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    const char* __restrict__ src = static_cast<const char*>(a.src);
-    char* __restrict__ dst = static_cast<char*>(a.dst);
-    const uint64_t plane_bytes = a.g.plane * sizeof(T);
-
-    R h[37];
-    static_for<0, 37>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
-        const uint32_t ys = wrap_sub(y, ey, ny);                       // block-uniform
-        const uint32_t xo = wrap_sub(x, ex, nx) * (uint32_t)sizeof(T);  // lane byte offset
-        const char* rowp = src + i * plane_bytes + (uint64_t)ys * nx * sizeof(T);
-        R v = S::load(reinterpret_cast<const T*>(rowp + xo));
-        if constexpr (S::kScaled) v *= R(a.inv_s[i]);
-        h[i] = v;
-    });
-
-    R om[8];
-    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
-    R wc[8];
-    static_for<0, 8>([&](auto N) { wc[decltype(N)::value] = R(a.wcls[decltype(N)::value]); });
-    d37_collide<MODEL, R>(h, R(a.rho0), om, R(a.r), wc, a.thermal != 0, R(a.theta0));
-
-    char* outrow = dst + (uint64_t)y * nx * sizeof(T);
-    const uint32_t xo = x * (uint32_t)sizeof(T);
-    static_for<0, 37>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        R v = h[i];
-        if constexpr (S::kScaled) v *= R(a.s[i]);
-        S::store(reinterpret_cast<T*>(outrow + i * plane_bytes + xo), v);
-    });
-}
 
 // ---------------------------------------------------------------------------
 // Initialisation from fields (FP64 arithmetic, then encode)
@@ -409,12 +301,6 @@ __global__ __launch_bounds__(256) void k_box_filter(StepArgs a, int factor, floa
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-static void step_shape(const GridArgs& g, dim3& grid, dim3& block, uint32_t rows) {
-    uint32_t bs = g.nx >= 256 ? 256u : ((g.nx + 63u) / 64u) * 64u;
-    block = dim3(bs);
-    grid = dim3(g.nchunks * rows);
-}
-
 GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz) {
     GridArgs g;
     g.nx = nx;
@@ -433,41 +319,9 @@ static dim3 flat_grid(uint64_t n) {
     return dim3((uint32_t)b);
 }
 
-template <int D, int ST>
-static void launch_tp(const StepArgs& a, hipStream_t s) {
-    dim3 grid, block;
-    step_shape(a.g, grid, block, a.g.ny * a.g.nz);
-    hipLaunchKernelGGL((k_step_tp<D, ST>), grid, block, 0, s, a);
-}
-
-template <int ST, int MODEL>
-static void launch_d37(const StepArgs& a, hipStream_t s) {
-    dim3 grid, block;
-    step_shape(a.g, grid, block, a.g.ny);
-    hipLaunchKernelGGL((k_step_d37<ST, MODEL>), grid, block, 0, s, a);
-}
-
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s) {
-#define CMLB_TP(D)                                                   \
-    switch (storage) {                                               \
-        case kF64: launch_tp<D, kF64>(a, s); return 0;               \
-        case kF32: launch_tp<D, kF32>(a, s); return 0;               \
-        case kBF16: launch_tp<D, kBF16>(a, s); return 0;             \
-        case kF16: launch_tp<D, kF16>(a, s); return 0;               \
-    }                                                                \
-    return -1;
-    if (lattice == kD2Q9) { CMLB_TP(2) }
-    if (lattice == kD3Q27) { CMLB_TP(3) }
-#undef CMLB_TP
-    if (lattice == kD2Q37) {
-        const bool raw = (model == kRawMRT);
-        switch (storage) {
-            case kF64: raw ? launch_d37<kF64, kRawMRT>(a, s) : launch_d37<kF64, kCM>(a, s); return 0;
-            case kF32: raw ? launch_d37<kF32, kRawMRT>(a, s) : launch_d37<kF32, kCM>(a, s); return 0;
-            case kBF16: raw ? launch_d37<kBF16, kRawMRT>(a, s) : launch_d37<kBF16, kCM>(a, s); return 0;
-            case kF16: raw ? launch_d37<kF16, kRawMRT>(a, s) : launch_d37<kF16, kCM>(a, s); return 0;
-        }
-    }
+    if (lattice == kD2Q9 || lattice == kD3Q27) return launch_step_tp(lattice, storage, a, s);
+    if (lattice == kD2Q37) return launch_step_d37(storage, model, a, s);
     return -1;
 }
 

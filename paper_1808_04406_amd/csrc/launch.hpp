@@ -7,8 +7,17 @@ namespace cmlb {
 
 GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz);
 
+// Step-kernel launch shape: one block per x-segment of each of `rows` rows.
+inline void step_shape(const GridArgs& g, dim3& grid, dim3& block, uint32_t rows) {
+    const uint32_t bs = g.nx >= 256 ? 256u : ((g.nx + 63u) / 64u) * 64u;
+    block = dim3(bs);
+    grid = dim3(g.nchunks * rows);
+}
+
 // Each returns 0, or -1 for an unsupported lattice/storage/model combination.
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s);
+int launch_step_tp(int lattice, int storage, const StepArgs& a, hipStream_t s);     // step_tp.hip
+int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s);      // step_d37.hip
 int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_codec(int lattice, int storage, bool decode, void* stor, double* full, const StepArgs& a,

@@ -1,0 +1,77 @@
+// Fused pull-stream + collide for the thermal D2Q37 lattice (order-4
+// Hermite truncation; central-moment or raw-moment MRT), and its launcher.
+// Same thread/block mapping as the tensor-product step: one thread per
+// node, one x-segment of a row per block, block-uniform source rows.
+#include "launch.hpp"
+
+#include "collide_d2q37.hpp"
+
+namespace cmlb {
+
+// ---------------------------------------------------------------------------
+// Hot path: D2Q37 stream + collide (order-4 Hermite truncation)
+// ---------------------------------------------------------------------------
+template <int ST, int MODEL>
+__global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
+    using S = Store<ST>;
+    using R = typename S::R;
+    using T = typename S::T;
+    const uint32_t nx = a.g.nx, ny = a.g.ny;
+    const uint32_t chunk = blockIdx.x % a.g.nchunks;
+    const uint32_t y = blockIdx.x / a.g.nchunks;
+    const uint32_t x = chunk * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const char* __restrict__ src = static_cast<const char*>(a.src);
+    char* __restrict__ dst = static_cast<char*>(a.dst);
+    const uint64_t plane_bytes = a.g.plane * sizeof(T);
+
+    R h[37];
+    static_for<0, 37>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
+        const uint32_t ys = wrap_sub(y, ey, ny);                       // block-uniform
+        const uint32_t xo = wrap_sub(x, ex, nx) * (uint32_t)sizeof(T);  // lane byte offset
+        const char* rowp = src + i * plane_bytes + (uint64_t)ys * nx * sizeof(T);
+        R v = S::load(reinterpret_cast<const T*>(rowp + xo));
+        if constexpr (S::kScaled) v *= R(a.inv_s[i]);
+        h[i] = v;
+    });
+
+    R om[8];
+    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
+    R wc[8];
+    static_for<0, 8>([&](auto N) { wc[decltype(N)::value] = R(a.wcls[decltype(N)::value]); });
+    d37_collide<MODEL, R>(h, R(a.rho0), om, R(a.r), wc, a.thermal != 0, R(a.theta0));
+
+    char* outrow = dst + (uint64_t)y * nx * sizeof(T);
+    const uint32_t xo = x * (uint32_t)sizeof(T);
+    static_for<0, 37>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        R v = h[i];
+        if constexpr (S::kScaled) v *= R(a.s[i]);
+        S::store(reinterpret_cast<T*>(outrow + i * plane_bytes + xo), v);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Launcher
+// ---------------------------------------------------------------------------
+template <int ST, int MODEL>
+static void launch_d37(const StepArgs& a, hipStream_t s) {
+    dim3 grid, block;
+    step_shape(a.g, grid, block, a.g.ny);
+    hipLaunchKernelGGL((k_step_d37<ST, MODEL>), grid, block, 0, s, a);
+}
+
+int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s) {
+    const bool raw = (model == kRawMRT);
+    switch (storage) {
+        case kF64: raw ? launch_d37<kF64, kRawMRT>(a, s) : launch_d37<kF64, kCM>(a, s); return 0;
+        case kF32: raw ? launch_d37<kF32, kRawMRT>(a, s) : launch_d37<kF32, kCM>(a, s); return 0;
+        case kBF16: raw ? launch_d37<kBF16, kRawMRT>(a, s) : launch_d37<kBF16, kCM>(a, s); return 0;
+        case kF16: raw ? launch_d37<kF16, kRawMRT>(a, s) : launch_d37<kF16, kCM>(a, s); return 0;
+    }
+    return -1;
+}
+
+}  // namespace cmlb
