@@ -43,6 +43,19 @@ def fit_decay(t, amp) -> float:
     return -slope
 
 
+def fit_damped_cosine(t, a, alpha0: float, omega0: float):
+    """Least-squares fit of a(t) = A exp(-alpha t) cos(Omega t + phi) (the
+    standing acoustic wave of Sec. III.A, eq:modes); returns (alpha, Omega).
+    alpha0 and omega0 start the iteration."""
+    from scipy.optimize import least_squares
+    t = np.asarray(t, np.float64)
+    a = np.asarray(a, np.float64)
+    p0 = [a[0], alpha0, omega0, 0.0]
+    res = least_squares(lambda p: p[0] * np.exp(-p[1] * t) * np.cos(p[2] * t + p[3]) - a, p0,
+                        x_scale=[abs(a[0]), abs(alpha0), abs(omega0), 1.0], xtol=1e-14, ftol=1e-14, gtol=1e-14)
+    return res.x[1], res.x[2]
+
+
 def dispersion(nu: float, kappa: float, theta0: float, k: float, D: int = 2):
     """Closed forms eq:dr (all quantities in xi-units).
 

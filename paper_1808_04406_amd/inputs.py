@@ -73,6 +73,88 @@ def waves2d(nx: int, ny: int, shear_amp: float = 0.0, thermal_amp: float = 0.0,
     return rho, u, theta
 
 
+def nsf_modes(nu: float, kappa: float, theta0: float, k: float, dim: int = 2, rho0: float = 1.0):
+    """Eigen-system of the Navier-Stokes-Fourier equations linearised about a
+    uniform state at rest, for one wave e^(omega t + i k x) (Sec. III.A).
+
+    Units are the paper's (velocities scaled by sqrt(kT/m), so p = rho theta,
+    c_v = D/2, gamma = (D + 2)/D).  The monatomic stress has no bulk part,
+    so the longitudinal viscosity is 2 (1 - 1/D) nu; heat conducts with
+    diffusivity kappa = lambda / (rho c_p).  Variables (rho~, u~_par, theta~):
+
+        omega rho~   = -i k rho0 u~_par
+        omega u~_par = -i k (theta0 rho~ / rho0 + theta~) - 2 (1 - 1/D) nu k^2 u~_par
+        omega theta~ = -i k (2/D) theta0 u~_par - gamma kappa k^2 theta~
+
+    and omega = -nu k^2 for u~_perp.  Returns a dict with the thermal root
+    (real), the acoustic pair (omega_plus with positive imaginary part) and
+    their eigenvectors (rho~, u~_par, theta~), each scaled to rho~ = 1 for the
+    acoustic pair and theta~ = 1 for the thermal mode.
+    """
+    g = (dim + 2.0) / dim
+    A = np.array([[0.0, -1j * k * rho0, 0.0],
+                  [-1j * k * theta0 / rho0, -2.0 * (1.0 - 1.0 / dim) * nu * k * k, -1j * k],
+                  [0.0, -1j * k * (2.0 / dim) * theta0, -g * kappa * k * k]], dtype=complex)
+    w, V = np.linalg.eig(A)
+    it = int(np.argmin(np.abs(w.imag)))
+    ip = int(np.argmax(w.imag))
+    im = int(np.argmin(w.imag))
+    return {"viscous": -nu * k * k,
+            "thermal": w[it].real, "thermal_vec": V[:, it] / V[2, it],
+            "plus": w[ip], "plus_vec": V[:, ip] / V[0, ip],
+            "minus": w[im], "minus_vec": V[:, im] / V[0, im]}
+
+
+def linear_modes(n: int, nu: float, kappa: float, theta0: float, r: float, amp=(0.001, 0.001, 0.001),
+                 k_viscous=(1, 0), k_thermal=(1, 1), k_acoustic=(1, 0), background=(0.0, 0.0), rho0: float = 1.0):
+    """Superposition of a viscous wave, a thermal wave and a standing acoustic
+    wave on an n x n periodic grid, each built from the eigenvectors of
+    ``nsf_modes`` (Sec. III.A, Fig. 1 setup), plus a uniform background
+    velocity.
+
+    Velocities are in the paper's units inside and are returned in lattice
+    units (divided by r, the lattice scale of the quadrature); a mode number m
+    along an axis is the wave number 2 pi m / (n r).  amp = (a_v, a_t, a_a):
+    u~_perp = a_v (viscous); theta~ = a_t theta0 (thermal); rho~ = a_a rho0
+    (acoustic, sum of the omega_plus and omega_minus waves, so the density
+    is a_a rho0 cos(k.x) at t = 0).  The background velocity is in the
+    paper's units too.
+    """
+    a_v, a_t, a_a = amp
+    x, y = grid((n, n))
+    rho = np.full((n, n), rho0)
+    u = np.zeros((2, n, n))
+    theta = np.full((n, n), theta0)
+
+    def wave(m):
+        kv = 2 * np.pi * np.array(m, float) / (n * r)
+        kk = float(np.linalg.norm(kv))
+        phase = 2 * np.pi * (m[0] * x + m[1] * y) / n
+        return kv / kk, kk, np.exp(1j * phase)
+
+    # viscous: u_perp only
+    e, kk, ph = wave(k_viscous)
+    perp = np.array([-e[1], e[0]])
+    up = (a_v * ph).real
+    u += perp[:, None, None] * up
+    # thermal mode
+    e, kk, ph = wave(k_thermal)
+    vec = nsf_modes(nu, kappa, theta0, kk, 2, rho0)["thermal_vec"] * (a_t * theta0)
+    rho += (vec[0] * ph).real
+    u += e[:, None, None] * (vec[1] * ph).real
+    theta += (vec[2] * ph).real
+    # standing acoustic wave
+    e, kk, ph = wave(k_acoustic)
+    m = nsf_modes(nu, kappa, theta0, kk, 2, rho0)
+    vec = 0.5 * (m["plus_vec"] + m["minus_vec"]) * (a_a * rho0)
+    rho += (vec[0] * ph).real
+    u += e[:, None, None] * (vec[1] * ph).real
+    theta += (vec[2] * ph).real
+    u[0] += background[0]
+    u[1] += background[1]
+    return rho, u / r, theta
+
+
 def random_multimode(n: int, seed: int, kmax: int = 4, umax: float = 0.05, dim: int = 3):
     """Random-phase solenoidal velocity field on an n^dim periodic grid.
 
