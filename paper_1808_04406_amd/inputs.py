@@ -155,6 +155,19 @@ def linear_modes(n: int, nu: float, kappa: float, theta0: float, r: float, amp=(
     return rho, u / r, theta
 
 
+def double_shear_layer(n: int, u0: float, sharpness: float = 80.0, delta: float = 0.05, rho0: float = 1.0,
+                       theta0: float = 1.0):
+    """Double shear layer on the unit square sampled at x = i/n, y = j/n
+    (Sec. III.B): u_x = u0 tanh(sharpness (y - 1/4)) for y <= 1/2 and
+    u0 tanh(sharpness (3/4 - y)) above; u_y = delta u0 sin(2 pi (x + 1/4));
+    uniform rho and theta.  u0 is in the caller's velocity units."""
+    x, y = grid((n, n))
+    x, y = x / n, y / n
+    ux = np.where(y <= 0.5, u0 * np.tanh(sharpness * (y - 0.25)), u0 * np.tanh(sharpness * (0.75 - y)))
+    uy = delta * u0 * np.sin(2 * np.pi * (x + 0.25))
+    return np.full((n, n), rho0), np.stack([ux, uy]), np.full((n, n), theta0)
+
+
 def random_multimode(n: int, seed: int, kmax: int = 4, umax: float = 0.05, dim: int = 3):
     """Random-phase solenoidal velocity field on an n^dim periodic grid.
 

@@ -3,6 +3,7 @@
     python -m paper_1808_04406_amd.studies precision [--n 512] [--steps 5000]
     python -m paper_1808_04406_amd.studies thermal   [--n 1024] [--steps 5000]
     python -m paper_1808_04406_amd.studies closure   [--n 512]
+    python -m paper_1808_04406_amd.studies modes
 
 precision: the D3Q27 Taylor-Green vortex at Re = 1e5 run in FP64, FP32, FP16
 and BF16 storage from the same initial fields; kinetic-energy and enstrophy
@@ -19,6 +20,19 @@ closure: the learned closure (rates of orders 3..6 from a per-node network),
 trained on the GPU on box-filtered fine runs, its objective on held-out data
 against networks with fixed rates, and a coarse Taylor-Green rollout against
 the filtered fine run.
+
+modes: the linear-mode apparatus of Sec. III.A on D2Q37 thermal CM-MRT.
+Fig. 1 (viscous, thermal and standing acoustic waves from the eigenvectors
+of the linearised Navier-Stokes-Fourier system; decay rates and acoustic
+frequency fitted against eq:dr), the grid convergence of the viscosity and
+diffusivity errors for L = 20 ... 320 (the 37-velocity curve of Fig. 2), and
+Fig. 3 (viscosity and diffusivity errors against a background velocity
+normal to k, raw-moment MRT against CM-MRT).
+
+dsl: the stability boundary of the double shear layer (Sec. III.B, Figs. 5
+and 6): for each model (isothermal raw-moment MRT, isothermal CM-MRT,
+thermal CM-MRT), Prandtl number and Reynolds number, the largest Mach number
+whose 128^2 run stays finite and bounded to t/t_c = 2, found by bisection.
 
 Results are written as JSON (``--out``) and summarised on stdout.
 """
@@ -103,6 +117,191 @@ def _decay_rate(t, a):
     t = np.asarray(t, float)
     y = np.log(np.abs(np.asarray(a)))
     return -np.polyfit(t, y, 1)[0]
+
+
+def _fit_damped_cosine(t, a, alpha0, omega0):
+    """(alpha, Omega) of the least-squares fit a(t) = A exp(-alpha t) cos(Omega t + phi)."""
+    from scipy.optimize import least_squares
+    t = np.asarray(t, float)
+    a = np.asarray(a, float)
+    res = least_squares(lambda p: p[0] * np.exp(-p[1] * t) * np.cos(p[2] * t + p[3]) - a,
+                        [a[0], alpha0, omega0, 0.0], x_scale=[abs(a[0]), abs(alpha0), abs(omega0), 1.0],
+                        xtol=1e-14, ftol=1e-14, gtol=1e-14)
+    return float(res.x[1]), float(res.x[2])
+
+
+def _mode2(field, m):
+    """(2/N) sum field exp(-i k.x) for integer mode numbers m = (mx, my)."""
+    ny, nx = field.shape
+    x = np.arange(nx)[None, :]
+    y = np.arange(ny)[:, None]
+    return 2.0 * np.sum(field * np.exp(-2j * np.pi * (m[0] * x / nx + m[1] * y / ny))) / field.size
+
+
+def wave_run(n, nu, kappa, theta0, tau4=1.0, steps=350, every=5, model="cm", storage="f32", u0=0.0,
+             amp=(0.001, 0.001, 0.001), k_thermal=(1, 1), stream=None):
+    """One linear-mode run: D2Q37 thermal, tau_2 = 1/2 + nu/theta0,
+    tau_3 = 1/2 + kappa/theta0 (paper's units), background (0, u0).  Returns
+    the measured viscous and thermal decay rates, the acoustic decay rate and
+    frequency (when the acoustic amplitude is non-zero), the eq:dr values and
+    the relative errors."""
+    r = cmlb.lattice_info("D2Q37")["r"]
+    ctx = cmlb.Context("D2Q37", (n, n), storage=storage, thermal=True, model=model,
+                       tau={2: 0.5 + nu / theta0, 3: 0.5 + kappa / theta0, 4: tau4}, stream=stream)
+    rho, u, th = inputs.linear_modes(n, nu, kappa, theta0, r, amp=amp, k_thermal=k_thermal, background=(0.0, u0))
+    ctx.init_fields(rho, u, th)
+    ts, av, at, aa = [], [], [], []
+    t0 = time.perf_counter()
+    for t in range(0, steps + 1, every):
+        if t:
+            ctx.step(every)
+        g_rho, g_u, g_th = ctx.get_moments()
+        ts.append(t)
+        av.append(_mode2(g_u[1] - u0 / r, (1, 0)))
+        at.append(_mode2(np.log(g_th * g_rho ** (1.0 - 2.0)), k_thermal))   # entropy, c_v = 1, gamma = 2
+        aa.append(_mode2(g_rho * g_th, (1, 0)))                              # pressure
+    wall = time.perf_counter() - t0
+    ctx.destroy()
+    ts = np.array(ts)
+    k1 = 2 * math.pi / (n * r)
+    kt = k1 * math.hypot(*k_thermal)
+    g, cs = 2.0, math.sqrt(2.0 * theta0)
+    lam = 1.0 + (g - 3.0) * nu / kappa
+
+    def dr(k):   # eq:dr
+        pe = cs / (kappa * k)
+        return (nu * k * k, cs * k * (1 / pe + (g - 1) * lam / pe ** 3),
+                cs * k * ((g - lam) / (2 * pe) - (g - 1) * lam / (2 * pe ** 3)),
+                cs * k * (1 - ((g + lam) ** 2 - 4 * lam) / (8 * pe ** 2)))
+
+    v_th, _, ar_th, ai_th = dr(k1)
+    t_th = dr(kt)[1]
+    out = {"n": n, "model": model, "storage": storage, "tau4": tau4, "u0": u0, "steps": steps, "wall_s": wall,
+           "viscous_theory": v_th, "thermal_theory": t_th,
+           "viscous": _decay_rate(ts[1:], np.abs(av[1:])), "thermal": _decay_rate(ts[1:], np.abs(at[1:]))}
+    out["viscous_err"] = out["viscous"] / v_th - 1
+    out["thermal_err"] = out["thermal"] / t_th - 1
+    if amp[2] != 0.0:
+        aa = np.array(aa)
+        signed = (aa * np.conj(aa[0]) / abs(aa[0])).real
+        ar, ai = _fit_damped_cosine(ts, signed, ar_th, ai_th)
+        out.update({"acoustic_rate_theory": ar_th, "acoustic_freq_theory": ai_th, "acoustic_rate": ar,
+                    "acoustic_freq": ai, "acoustic_rate_err": ar / ar_th - 1, "acoustic_freq_err": ai / ai_th - 1})
+    return out
+
+
+def modes(stream=None):
+    nu, kappa, theta0 = 0.1, 0.2, 1.2
+    tau2 = 0.5 + nu / theta0
+    res = {"nu": nu, "kappa": kappa, "theta0": theta0, "fig1": [], "convergence": [], "galilean": []}
+    for storage in ("f64", "f32"):
+        for tau4 in (1.0, tau2):
+            o = wave_run(100, nu, kappa, theta0, tau4=tau4, storage=storage, stream=stream)
+            res["fig1"].append(o)
+            print(f"Fig. 1 {storage} tau4={tau4:.5f}: errors viscous {o['viscous_err']:+.3e} thermal "
+                  f"{o['thermal_err']:+.3e} acoustic {o['acoustic_rate_err']:+.3e} / {o['acoustic_freq_err']:+.3e}",
+                  flush=True)
+    for n in (20, 40, 80, 160, 320):
+        steps = int(round(1000 * (n / 100.0) ** 2))
+        every = max(1, steps // 100)
+        steps = every * (steps // every)
+        o = wave_run(n, nu, kappa, theta0, tau4=1.0, steps=steps, every=every, storage="f64",
+                     amp=(0.001, 0.001, 0.0), stream=stream)
+        res["convergence"].append(o)
+        print(f"L={n}: viscosity error {o['viscous_err']:+.3e}, diffusivity error {o['thermal_err']:+.3e}", flush=True)
+    for model in ("raw_mrt", "cm"):
+        for u0 in (0.0, 0.025, 0.05, 0.075, 0.1, 0.15, 0.2):
+            o = wave_run(100, nu, kappa, theta0, tau4=1.0, steps=1000, every=20, model=model, storage="f64",
+                         u0=u0, amp=(0.001, 0.001, 0.0), k_thermal=(1, 0), stream=stream)
+            res["galilean"].append(o)
+            print(f"Fig. 3 {model} u0={u0}: viscosity error {o['viscous_err']:+.3e}, diffusivity error "
+                  f"{o['thermal_err']:+.3e}", flush=True)
+    return res
+
+
+def max_stable(stable, lo, hi, tol):
+    """Bisection for the largest x in [lo, hi] with stable(x) true, assuming
+    a single stable-to-unstable transition.  Returns (x_max, calls), where
+    x_max is the largest stable point evaluated (lo if even lo is unstable,
+    then flagged by calls[0][1] False) and calls lists (x, stable) in order."""
+    calls = []
+
+    def ev(x):
+        ok = bool(stable(x))
+        calls.append((x, ok))
+        return ok
+
+    if not ev(lo):
+        return lo, calls
+    if ev(hi):
+        return hi, calls
+    while hi - lo > tol:
+        mid = 0.5 * (lo + hi)
+        if ev(mid):
+            lo = mid
+        else:
+            hi = mid
+    return lo, calls
+
+
+def dsl_run(ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0, checks=32,
+            ke_bound=2.0, history=False, stream=None):
+    """One double-shear-layer run (Sec. III.B) on D2Q37.
+
+    Units as in the paper: velocities in units of the isothermal sound speed
+    (Ma = u0), lengths in lattice spacings c, so u0 = Ma / r cells per step,
+    nu = Ma r L / Re, tau_2 = 1/2 + nu, tau_3 = 1/2 + nu / Pr (theta0 = 1),
+    tau_4 = tau_2 unless given.  The run goes to t = t_end t_c with
+    t_c = L / u0 steps and is stable if every check finds all populations
+    finite and <u^2>/u0^2 <= ke_bound."""
+    r = cmlb.lattice_info("D2Q37")["r"]
+    u_lat = ma / r
+    nu = ma * r * n / re
+    tau2 = 0.5 + nu
+    tau = {2: tau2, 3: 0.5 + nu / pr, 4: tau2 if tau4 is None else tau4}
+    ctx = cmlb.Context("D2Q37", (n, n), storage=storage, thermal=thermal, model=model, tau=tau, stream=stream)
+    rho, u, th = inputs.double_shear_layer(n, u_lat)
+    ctx.init_fields(rho, u, th)
+    steps = int(math.ceil(t_end * n / u_lat))
+    marks = sorted(set(int(round(steps * (j + 1) / checks)) for j in range(checks)))
+    done, ok, hist = 0, True, [(0, 1.0)]
+    g0 = ctx.reduce(allow_unstable=True)
+    e0 = g0["ke"]
+    for m in marks:
+        ctx.step(m - done)
+        done = m
+        g = ctx.reduce(allow_unstable=True)
+        ratio = g["ke"] / e0 if np.isfinite(g["ke"]) else float("inf")
+        hist.append((done, ratio))
+        if g["nonfinite"] > 0 or not ratio <= ke_bound:
+            ok = False
+            break
+    ctx.destroy()
+    out = {"stable": ok, "steps": steps, "steps_run": done, "tau": tau}
+    if history:
+        out["history"] = hist
+    return out
+
+
+def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0), tol=0.005, stream=None):
+    out = {"n": n, "tol": tol, "criterion": "finite and <u^2>/<u^2>_0 <= 2 at 32 checks up to t/t_c = 2",
+           "boundaries": [], "fig6": None}
+    t0 = time.perf_counter()
+    # Fig. 6: the Mach sequence of the thermal CM-MRT run at Pr = 1, Re = 1e7
+    out["fig6"] = {str(ma): dsl_run(ma, 1e7, 1.0, history=True, stream=stream)
+                   for ma in (0.2, 0.25, 0.2625, 0.2688, 0.275)}
+    for ma, o in out["fig6"].items():
+        print(f"Fig. 6 Ma={ma}: stable={o['stable']}, steps {o['steps_run']}/{o['steps']}", flush=True)
+    for label, model, thermal in (("isothermal raw MRT", "raw_mrt", False), ("isothermal CM-MRT", "cm", False),
+                                  ("thermal CM-MRT", "cm", True)):
+        for pr in prs:
+            for re in res_:
+                m, calls = max_stable(lambda ma: dsl_run(ma, re, pr, model=model, thermal=thermal,
+                                                         stream=stream)["stable"], 0.05, 1.2, tol)
+                out["boundaries"].append({"model": label, "pr": pr, "re": re, "ma_max": m, "calls": calls})
+                print(f"{label} Pr={pr} Re={re:.0e}: Ma_max = {m:.4f} ({len(calls)} runs)", flush=True)
+    out["wall_s"] = time.perf_counter() - t0
+    return out
 
 
 def thermal(n=1024, steps=5000, every=250, kx=4, tau2=0.6, prs=(0.71, 7.0), us=(0.0, 0.1), storage="f32",
@@ -318,7 +517,7 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "thermal", "closure"])
+    ap.add_argument("study", choices=["precision", "thermal", "closure", "modes", "dsl"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--every", type=int, default=None)
@@ -334,6 +533,10 @@ def main(argv=None):
             res = precision(n=a.n or 512, steps=a.steps, every=a.every or 100, stream=stream)
         elif a.study == "closure":
             res = closure(n_fine=a.n or 512, stream=stream)
+        elif a.study == "modes":
+            res = modes(stream=stream)
+        elif a.study == "dsl":
+            res = dsl(n=a.n or 128, stream=stream)
         else:
             res = thermal(n=a.n or 1024, steps=a.steps, every=a.every or 250, storage=a.storage, model=a.model,
                           stream=stream)

@@ -3,6 +3,7 @@ every symbol the header declares, derives the same lattice tables as the
 oracle (independently), and rejects invalid parameters before touching a
 device."""
 import ctypes
+import math
 import os
 import re
 
@@ -59,3 +60,30 @@ def test_null_context_is_rejected(cm):
     assert L.cmlb_sync(None) == cm.EINVAL
     assert L.cmlb_step_count(None) == -1
     L.cmlb_destroy(None)
+
+
+def test_max_stable_bisection():
+    """Host logic of the stability-boundary search (Sec. III.B)."""
+    from paper_1808_04406_amd.studies import max_stable
+    for edge in (0.05, 0.2688, 0.7, 1.19):
+        m, calls = max_stable(lambda x: x <= edge, 0.05, 1.2, 0.005)
+        assert m <= edge < m + 0.005 + 1e-12
+        assert len(calls) <= 2 + math.ceil(math.log2(1.15 / 0.005))
+        assert all(ok == (x <= edge) for x, ok in calls)
+    m, calls = max_stable(lambda x: False, 0.05, 1.2, 0.005)
+    assert m == 0.05 and calls == [(0.05, False)]
+    m, calls = max_stable(lambda x: True, 0.05, 1.2, 0.005)
+    assert m == 1.2 and len(calls) == 2
+
+
+def test_double_shear_layer_fields():
+    """Sec. III.B initial fields: shear layers at y = 1/4 and 3/4, perturbation delta u0."""
+    from paper_1808_04406_amd import inputs
+    rho, u, th = inputs.double_shear_layer(128, 0.2)
+    assert u.shape == (2, 128, 128)
+    assert np.allclose(u[0][32], 0.0) and np.allclose(u[0][96], 0.0)      # y = 1/4, 3/4
+    assert u[0][64].min() == pytest.approx(0.2 * math.tanh(20.0))           # y = 1/2
+    assert u[0][0].max() == pytest.approx(-0.2 * math.tanh(20.0))
+    assert abs(u[1]).max() == pytest.approx(0.05 * 0.2, rel=1e-12)
+    assert u[1][:, 0] == pytest.approx(np.full(128, 0.01))                 # sin(pi/2) at x = 0
+    assert (rho == 1.0).all() and (th == 1.0).all()

@@ -39,22 +39,71 @@ def _wave_run(orc, n, nu, kappa, theta0, steps, every, model="cm", background=(0
     return np.array(ts), np.array(av), np.array(at)
 
 
-def test_fig1_viscous_and_thermal_rates(orc):
-    """100^2, nu = 0.1, kappa = 0.2, theta0 = 1.2: the paper reports errors of
-    0.17 % (viscous) and 0.19 % (thermal).  tau4 is not stated; with tau4 = 1
-    the oracle's errors are about 0.4 % and 0.2 %."""
-    from oracle.analysis import dispersion, fit_decay
+def test_nsf_eigensystem_matches_eq_dr():
+    """The linearised Navier-Stokes-Fourier eigen-system used to build the
+    initial waves reproduces the asymptotic dispersion relations eq:dr: the
+    thermal and acoustic roots agree with the printed expansions to their
+    stated order, and the thermal eigenvector is isobaric to leading order."""
+    from oracle.analysis import dispersion
+    for nu, kappa, theta0 in ((0.1, 0.2, 1.2), (0.05, 0.01, 1.0), (0.01, 0.1, 0.8)):
+        for k in (0.01, 0.05):
+            m = inputs.nsf_modes(nu, kappa, theta0, k)
+            v, t, ar, ai = dispersion(nu, kappa, theta0, k)
+            cs = math.sqrt(2.0 * theta0)
+            inv_pe = kappa * k / cs
+            assert -m["viscous"] == pytest.approx(v, rel=1e-15)
+            # neglected terms are O(Pe^-5) (rates) and O(Pe^-4) (frequency), relative to c_s k
+            assert abs(-m["thermal"] - t) / (cs * k) < 10 * inv_pe ** 5 + 1e-15
+            assert abs(-m["plus"].real - ar) / (cs * k) < 10 * inv_pe ** 5 + 1e-15
+            assert abs(m["plus"].imag - ai) / (cs * k) < 10 * inv_pe ** 4 + 1e-15
+            assert m["minus"] == pytest.approx(np.conj(m["plus"]), rel=1e-12)
+            vec = m["thermal_vec"]
+            assert abs(vec[0] * theta0 + 1.0) < 0.05   # rho~ / rho0 = -theta~ / theta0
+    # a classical limit: kappa = nu = 0 gives undamped sound at c_s = sqrt(gamma theta0)
+    m = inputs.nsf_modes(0.0, 1e-300, 1.0, 0.1)
+    assert m["plus"].imag == pytest.approx(math.sqrt(2.0) * 0.1, rel=1e-12)
+
+
+def test_fig1_linear_modes(orc):
+    """Fig. 1: 100^2, nu = 0.1, kappa = 0.2, theta0 = 1.2; a viscous wave
+    (1, 0), a thermal wave (1, 1) and a standing acoustic wave (1, 0), all of
+    amplitude 0.001 and built from the eigenvectors.  Fitted against eq:dr
+    the paper reports errors of 0.17 % (viscous), 0.19 % (thermal), 0.19 %
+    (acoustic decay) and 0.01 % (acoustic frequency).  tau4 is not stated;
+    at tau4 = 1 the oracle gives about 0.40, 0.14, 0.19 and 0.03 %."""
+    from oracle.analysis import dispersion, fit_damped_cosine, fit_decay, mode_amplitude
     g = json.load(open(os.path.join(GOLDEN, "fig1_constants.json")))
-    ts, av, at = _wave_run(orc, 100, g["nu_xi"], g["kappa_xi"], g["theta0"], 400, 40, kt=(1, 1))
+    n, nu, kappa, theta0 = 100, g["nu_xi"], g["kappa_xi"], g["theta0"]
+    r = orc.lattice("D2Q37")["r"]
+    cfg = orc.Cfg(lattice="D2Q37", tau={2: 0.5 + nu / theta0, 3: 0.5 + kappa / theta0, 4: 1.0}, thermal=True)
+    rho, u, th = inputs.linear_modes(n, nu, kappa, theta0, r, amp=(g["amplitude"],) * 3)
+    S = orc.init_equilibrium(cfg, rho, u, th)
+    ts, av, at, aa = [], [], [], []
+    for t in range(0, 351, 5):
+        if t:
+            orc.run(cfg, S, 5)
+        rr, uu, tt = orc.moments("D2Q37", S)
+        ts.append(t)
+        av.append(mode_amplitude(uu[1], (1, 0)))
+        at.append(mode_amplitude(np.log(tt * rr ** (1.0 - 2.0)), (1, 1)))   # entropy, c_v = 1, gamma = 2
+        aa.append(mode_amplitude(rr * tt, (1, 0)))                              # pressure
+    ts, aa = np.array(ts), np.array(aa)
+    k1 = 2 * math.pi / n / r
+    v_th, _, ar_th, ai_th = dispersion(nu, kappa, theta0, k1)
+    _, t_th, _, _ = dispersion(nu, kappa, theta0, math.sqrt(2) * k1)
+    # the printed constants are these closed forms
+    assert v_th == pytest.approx(g["viscous_rate"], rel=2e-3)
+    assert t_th == pytest.approx(g["thermal_rate"], rel=5e-3)
+    assert ar_th == pytest.approx(g["acoustic_rate"], rel=2e-3)
+    assert ai_th == pytest.approx(g["acoustic_frequency"], rel=2e-3)
     visc = fit_decay(ts[1:], av[1:])
     therm = fit_decay(ts[1:], at[1:])
-    assert visc == pytest.approx(g["viscous_rate"], rel=0.005)
-    assert therm == pytest.approx(g["thermal_rate"], rel=0.005)
-    r = orc.lattice("D2Q37")["r"]
-    k1 = 2 * math.pi / 100 / r
-    v_th, _, _, _ = dispersion(0.1, 0.2, 1.2, k1)
-    _, t_th, _, _ = dispersion(0.1, 0.2, 1.2, math.sqrt(2) * k1)
-    assert abs(visc / v_th - 1) < 0.005 and abs(therm / t_th - 1) < 0.005
+    signed = (aa * np.conj(aa[0]) / abs(aa[0])).real
+    ar, ai = fit_damped_cosine(ts, signed, ar_th, ai_th)
+    assert abs(visc / v_th - 1) < 0.005
+    assert abs(therm / t_th - 1) < 0.005
+    assert abs(ar / ar_th - 1) < 0.005
+    assert abs(ai / ai_th - 1) < 0.0005
 
 
 def test_fig3_galilean_invariance_of_diffusivity(orc):
