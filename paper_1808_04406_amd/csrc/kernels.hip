@@ -258,14 +258,16 @@ __global__ __launch_bounds__(256) void k_reduce_vort(GridArgs g, int D, const do
     block_partials(acc, partials);
 }
 
-// Sum the partial rows of both passes in a fixed order.
-__global__ __launch_bounds__(64) void k_reduce_final(const double* p1, const double* p2, int nblocks, double* out) {
-    const int k = threadIdx.x;
-    if (k >= kRedVals) return;
+// Sum the partial rows of both passes in a fixed order: wave k sums value k,
+// lane l takes rows l, l + 64, ... in order, then a fixed shuffle tree.
+__global__ __launch_bounds__(64 * kRedVals) void k_reduce_final(const double* p1, const double* p2, int nblocks,
+                                                                double* out) {
+    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double* p = (k == 6) ? p2 : p1;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += p[(uint64_t)b * kRedVals + k];
-    out[k] = s;
+    for (int b = lane; b < nblocks; b += 64) s += p[(uint64_t)b * kRedVals + k];
+    s = wave_sum(s);
+    if (lane == 0) out[k] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -417,7 +419,7 @@ int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, doubl
 #undef L_RED
     const int D = (lattice == kD3Q27) ? 3 : 2;
     hipLaunchKernelGGL(k_reduce_vort, grid, block, 0, s, a.g, D, uf, p2);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, p1, p2, (int)grid.x, out);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64 * kRedVals), 0, s, p1, p2, (int)grid.x, out);
     return 0;
 }
 
