@@ -41,6 +41,16 @@ KERNEL = "k_step_tp<3, kF32>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q27_256_f32.json")
 KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/step_tp.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
                   "paper_1808_04406_amd/csrc/common.hpp"]
+# The learned-closure step is bound by vector-ALU issue; its instruction count
+# per launch comes from a committed rocprofv3 counter summary.
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_k_step_closure_d3q27_128_f32.json")
+CLOSURE_SOURCES = ["paper_1808_04406_amd/csrc/kernels_closure.hip", "paper_1808_04406_amd/csrc/closure.hpp",
+                   "paper_1808_04406_amd/csrc/collide_tp.hpp", "paper_1808_04406_amd/csrc/common.hpp"]
+# Vector-ALU issue peak in lane-instructions per second: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz (a wave64 instruction occupies a SIMD for 4 cycles;
+# packed FP32 is not used).
+PEAK_VALU_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
+STORAGE_TAG = {"f64": "kF64", "f32": "kF32", "f16": "kF16", "bf16": "kBF16"}
 
 
 def tau_shear(n=N, u0=U0, re=RE):
@@ -53,12 +63,25 @@ def rates(tau):
     return {2: tau, 3: 1.0, 4: tau, 5: 1.0, 6: tau}
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=None):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def measured_valu():
+    """VALU wave-instructions per launch of the closure step (128^3), or None
+    if the summary is missing or was taken on a different kernel source."""
+    try:
+        with open(VALU_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash(CLOSURE_SOURCES):
+        return None
+    return t.get("valu_wave_instructions_per_launch")
 
 
 def measured_traffic(bytes_per_launch_alg):
@@ -158,7 +181,13 @@ WORKLOADS = {
                       "(amplitude 0.01), tau_2=0.6, Pr=0.71, background 0.1, FP32 storage"),
     "waves2048_f32": ("D2Q37", (2048, 2048), "f32", "D2Q37 thermal CM-MRT 2048^2, shear + thermal waves "
                       "(amplitude 0.01), tau_2=0.6, Pr=0.71, background 0.1, FP32 storage"),
+    "waves2048_rawmrt_f32": ("D2Q37", (2048, 2048), "f32", "D2Q37 thermal raw-moment MRT 2048^2, shear + thermal "
+                             "waves (amplitude 0.01), tau_2=0.6, Pr=0.71, background 0.1, FP32 storage"),
+    "waves2048_regbgk_f32": ("D2Q37", (2048, 2048), "f32", "D2Q37 thermal regularised BGK 2048^2, shear + thermal "
+                             "waves (amplitude 0.01), tau=0.6, background 0.1, FP32 storage"),
 }
+WORKLOAD_MODEL = {"waves2048_rawmrt_f32": "raw_mrt", "waves2048_regbgk_f32": "reg_bgk"}
+MODEL_TAG = {"cm": "kCM", "raw_mrt": "kRawMRT", "reg_bgk": "kCM"}
 QS = {"D3Q27": 27, "D2Q37": 37}
 SBYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
@@ -189,7 +218,8 @@ def setup_workload(name, torch, cmlb, inputs, stream):
         n = shape[0]
         tau2, pr = 0.6, 0.71
         taus = {2: tau2, 3: 0.5 + (tau2 - 0.5) / pr, 4: tau2}
-        ctx = cmlb.Context("D2Q37", shape, storage=storage, thermal=True, tau=taus, external=bufs, stream=stream)
+        ctx = cmlb.Context("D2Q37", shape, storage=storage, thermal=True, model=WORKLOAD_MODEL.get(name, "cm"),
+                           tau=taus, external=bufs, stream=stream)
         rho, u, theta = inputs.waves2d(n, n, shear_amp=0.01, thermal_amp=0.01, k=(1, 0), background=(0.0, 0.1))
     d = [torch.from_numpy(a.reshape(-1)).to("cuda") for a in (rho, u)]
     d_th = None if theta is None else torch.from_numpy(theta.reshape(-1)).to("cuda")
@@ -231,9 +261,21 @@ def run(torch, cmlb, inputs, stream, args):
     alg_bytes = per_node * nodes
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic(alg_bytes) if args.workload == "tgv256_f32" else None
-    kernel = KERNEL if lattice == "D3Q27" else "k_step_d37<%s, kCM>" % storage
+    if lattice == "D3Q27":
+        kernel = "k_step_tp<3, %s>" % STORAGE_TAG[storage]
+    else:
+        kernel = "k_step_d37<%s, %s>" % (STORAGE_TAG[storage], MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")])
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
     if args.workload.endswith("closure_f32"):
         kernel = "k_step_closure"
+        valu = measured_valu()
+        if valu is not None:
+            lane_rate = valu * 64 / (kernel_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "achieved": round(lane_rate, 2), "peak": PEAK_VALU_TLANE,
+                    "unit": "T lane-instructions/s (VALU)", "frac": round(lane_rate / PEAK_VALU_TLANE, 4),
+                    "traffic": None, "valu_wave_instructions_per_launch": valu,
+                    "hbm_GBps": round(achieved, 1), "hbm_frac": round(achieved / PEAK_HBM_GBS, 4)}
     out = {
         "metric": "MLUPS of CM-MRT stream+collide, % HBM roofline; error vs FP64 oracle",
         "value": round(value, 1),
@@ -250,11 +292,8 @@ def run(torch, cmlb, inputs, stream, args):
         "config": {"workload": desc, "lattice": lattice, "grid": list(shape), "storage": storage,
                    "tau_shear": taus[2], "tau_by_order": {str(k): v for k, v in taus.items()},
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": kernel, "kernel_ms": round(kernel_ms, 5),
-                     "bytes_per_node_update": per_node,
-                     "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "roofline": dict(roof, kernel=kernel, kernel_ms=round(kernel_ms, 5), bytes_per_node_update=per_node,
+                         copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4)),
     }
     return out
 
