@@ -37,9 +37,9 @@ RE = 1600.0
 Q = 27
 STORAGE_BYTES = 4
 PEAK_HBM_GBS = 8000.0
-KERNEL = "k_step_tp<3, kF32>"
+KERNEL = "k_step2_tp<kF32>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q27_256_f32.json")
-KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/step_tp.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
+KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/step_tp2.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
                   "paper_1808_04406_amd/csrc/common.hpp"]
 # The learned-closure step is bound by vector-ALU issue; its instruction count
 # per launch comes from a committed rocprofv3 counter summary.
@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
+                    help="2: pairs of D3Q27 steps in one launch where supported (default); 1: one launch per step")
     ap.add_argument("--workload", default="tgv256_f32", choices=sorted(WORKLOADS),
                     help="default: the D3Q27 256^3 FP32 Taylor-Green benchmark; others report the precision "
                          "form and the thermal lattice with the same JSON fields")
@@ -231,6 +233,10 @@ def setup_workload(name, torch, cmlb, inputs, stream):
 def run(torch, cmlb, inputs, stream, args):
     ctx, bufs, mass0, taus, desc, nodes, q, sb = setup_workload(args.workload, torch, cmlb, inputs, stream)
     lattice, shape, storage, _ = WORKLOADS[args.workload]
+    closure = args.workload.endswith("closure_f32")
+    # pairs of D3Q27 steps run as one launch (intermediate state on chip)
+    fused = lattice == "D3Q27" and storage != "f64" and not closure and args.steps_per_launch == 2
+    ctx.set_step_fusion(args.steps_per_launch)
 
     ctx.step(args.warmup)
     torch.cuda.synchronize()
@@ -245,7 +251,9 @@ def run(torch, cmlb, inputs, stream, args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    kernel_ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
+    launches = (args.steps // 2 + args.steps % 2) if fused else args.steps
+    kernel_ms = ev0.elapsed_time(ev1) / max(launches, 1)
+    updates_per_launch = 2 if fused else 1
 
     g = ctx.reduce()
     assert g["nonfinite"] == 0, "simulation diverged"
@@ -258,16 +266,20 @@ def run(torch, cmlb, inputs, stream, args):
 
     value = nodes * args.steps / wall / 1e6
     per_node = 2 * q * sb
-    alg_bytes = per_node * nodes
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(alg_bytes) if args.workload == "tgv256_f32" else None
-    if lattice == "D3Q27":
+    # algorithmic bytes per launch: 2 Q s per node update (each population read
+    # and written once) x the node updates of one launch
+    alg_bytes = per_node * nodes * updates_per_launch
+    achieved = per_node * nodes * args.steps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    traffic = measured_traffic(alg_bytes) if (args.workload == "tgv256_f32" and fused) else None
+    if fused:
+        kernel = "k_step2_tp<%s>" % STORAGE_TAG[storage]
+    elif lattice == "D3Q27":
         kernel = "k_step_tp<3, %s>" % STORAGE_TAG[storage]
     else:
         kernel = "k_step_d37<%s, %s>" % (STORAGE_TAG[storage], MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
-    if args.workload.endswith("closure_f32"):
+    if closure:
         kernel = "k_step_closure"
         valu = measured_valu()
         if valu is not None:
@@ -292,7 +304,8 @@ def run(torch, cmlb, inputs, stream, args):
         "config": {"workload": desc, "lattice": lattice, "grid": list(shape), "storage": storage,
                    "tau_shear": taus[2], "tau_by_order": {str(k): v for k, v in taus.items()},
                    "parallelism": "single GPU"},
-        "roofline": dict(roof, kernel=kernel, kernel_ms=round(kernel_ms, 5), bytes_per_node_update=per_node,
+        "roofline": dict(roof, kernel=kernel, kernel_ms=round(kernel_ms, 5), steps_per_launch=updates_per_launch,
+                         bytes_per_node_update=per_node, algorithmic_bytes_per_launch=alg_bytes,
                          copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4)),
     }
     return out

@@ -80,6 +80,7 @@ def lib():
         L.cmlb_init_fields.argtypes = [vp, dp, dp, dp]
         L.cmlb_init_fields_device.argtypes = [vp, vp, vp, vp]
         L.cmlb_step.argtypes = [vp, c_i64]
+        L.cmlb_set_step_fusion.argtypes = [vp, c_int]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
         L.cmlb_get_populations.argtypes = [vp, dp]
@@ -221,6 +222,10 @@ class Context:
 
     def step(self, n=1):
         self._check(lib().cmlb_step(self.h, int(n)))
+
+    def set_step_fusion(self, steps_per_launch):
+        """2 (default): pairs of D3Q27 steps in one launch where supported; 1: one launch per step."""
+        self._check(lib().cmlb_set_step_fusion(self.h, int(steps_per_launch)))
 
     def sync(self):
         self._check(lib().cmlb_sync(self.h))

@@ -138,6 +138,7 @@ struct cmlb_ctx {
     double omega[8] = {};
     float s[37] = {}, inv_s[37] = {};
     int64_t steps = 0;
+    int fuse = 2;                 // steps per launch where the two-step kernel applies
     std::string err;
     // reduction scratch (allocated on first use)
     double* red_u = nullptr;
@@ -405,17 +406,31 @@ int cmlb_step(cmlb_ctx* c, int64_t n) {
     if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
     if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
     StepArgs a = base_args(c);
-    for (int64_t k = 0; k < n; ++k) {
+    for (int64_t k = 0; k < n;) {
         a.src = c->f[c->cur];
         a.dst = c->f[1 - c->cur];
-        if (c->closure_on) launch_step_closure(a, c->cl_net, c->stream);
-        else if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream))
+        int adv = 1;
+        if (c->closure_on) {
+            launch_step_closure(a, c->cl_net, c->stream);
+        } else if (c->fuse == 2 && n - k >= 2 && launch_step2_tp(c->p.lattice, c->p.storage, a, c->stream) == 0) {
+            adv = 2;
+        } else if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream)) {
             return fail(c, CMLB_EINVAL, "unsupported configuration");
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
         c->cur = 1 - c->cur;
-        c->steps++;
+        c->steps += adv;
+        k += adv;
     }
+    return CMLB_OK;
+}
+
+int cmlb_set_step_fusion(cmlb_ctx* c, int steps_per_launch) {
+    if (!c) return CMLB_EINVAL;
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return fail(c, CMLB_EINVAL, "steps per launch must be 1 or 2");
+    c->fuse = steps_per_launch;
     return CMLB_OK;
 }
 

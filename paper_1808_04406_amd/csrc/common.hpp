@@ -101,6 +101,7 @@ struct Store<kF64> {
     static constexpr bool kScaled = false;
     __device__ static R load(const T* p) { return *p; }
     __device__ static void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R round(R v) { return v; }   // value after a store and a load
     __host__ __device__ static double to_double(T v) { return v; }
     __host__ __device__ static T from_double(double v) { return v; }
 };
@@ -112,6 +113,7 @@ struct Store<kF32> {
     static constexpr bool kScaled = false;
     __device__ static R load(const T* p) { return *p; }
     __device__ static void store(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R round(R v) { return v; }
     __host__ __device__ static double to_double(T v) { return v; }
     __host__ __device__ static T from_double(double v) { return (float)v; }
 };
@@ -134,6 +136,7 @@ struct Store<kBF16> {
     static constexpr bool kScaled = true;
     __device__ static R load(const T* p) { return bf16_to_f32(*p); }
     __device__ static void store(T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
+    __device__ static R round(R v) { return bf16_to_f32(f32_to_bf16_rne(v)); }
     __host__ __device__ static double to_double(T v) { return bf16_to_f32(v); }
     __host__ __device__ static T from_double(double v) { return f32_to_bf16_rne((float)v); }
 };
@@ -147,6 +150,7 @@ struct Store<kF16> {
     __device__ static void store(T* p, R v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (_Float16)v), p);
     }
+    __device__ static R round(R v) { return (float)(_Float16)v; }
     __device__ static double to_double(T v) { return (double)__builtin_bit_cast(_Float16, v); }
     __device__ static T from_double(double v) { return __builtin_bit_cast(uint16_t, (_Float16)(float)v); }
 };

@@ -1,0 +1,193 @@
+// Two D3Q27 stream + collide steps per launch (temporal blocking), and its
+// launcher.
+//
+// The update of two consecutive steps at a node needs the once-updated
+// populations of its 26 neighbours. Each workgroup owns a tile of TX x TY
+// nodes in x-y and a chunk of planes in z, and marches up the chunk one
+// plane at a time:
+//   1. the first step is computed for the tile plus a one-node halo (the
+//      "region", (TX+2) x (TY+2) nodes) of plane q, pulling from the stored
+//      state in HBM; the results go to LDS, rounded exactly as a store and a
+//      reload through the storage type would round them;
+//   2. the second step is computed for the tile's own nodes of plane q - 1,
+//      pulling from LDS, and written to HBM.
+// A node's second step pulls population i from plane (q-1) - e_z,i: the nine
+// populations with e_z = -1 from plane q (just computed), the nine with
+// e_z = 0 from plane q - 1 and the nine with e_z = +1 from plane q - 2. LDS
+// therefore holds one slot of the first group, two of the second and three
+// of the third (54 populations per region node, 142,560 bytes for 64 x 8),
+// so one workgroup fills a CU's LDS. The stored state read by the first step
+// of plane q + 2 is fetched two iterations ahead into registers.
+//
+// Each population is read from HBM once per region node and written once per
+// tile node: per two node updates about (TX+2)(TY+2)/(TX TY) x 108 B of
+// reads (halo reads of a neighbouring tile often hit L2, since consecutive
+// tiles are placed on one XCD) and 108 B of writes, against 432 B for two
+// single steps. The arithmetic is the single-step kernel's, node by node, so
+// the result equals two single steps exactly.
+#include "launch.hpp"
+
+#include "collide_tp.hpp"
+
+namespace cmlb {
+
+constexpr int kTbTX = 64, kTbTY = 8, kTbThreads = 704;
+constexpr int kTbRX = kTbTX + 2, kTbRY = kTbTY + 2, kTbRN = kTbRX * kTbRY;
+static_assert(kTbThreads >= kTbRN && kTbThreads >= kTbTX * kTbTY && kTbThreads % 64 == 0, "tile threads");
+static_assert(54 * kTbRN * 4 <= 160 * 1024, "LDS of one CU");
+
+struct Step2Args {
+    StepArgs a;
+    uint32_t ntx, nty;   // tiles in x and y
+    uint32_t cz;         // planes per z chunk
+};
+
+template <int ST>
+__global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    constexpr int TX = kTbTX, TY = kTbTY, RX = kTbRX, RN = kTbRN;
+    __shared__ float lds[54 * RN];
+    float* sD = lds;             // [9][RN]     e_z = -1 group, plane q
+    float* sM = lds + 9 * RN;    // [2][9][RN]  e_z =  0 group, planes q, q - 1
+    float* sU = lds + 27 * RN;   // [3][9][RN]  e_z = +1 group, planes q, q - 1, q - 2
+    const StepArgs& a = A.a;
+    const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+
+    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
+    // range of tiles so that halo reads of neighbouring tiles share its L2.
+    uint32_t b = blockIdx.x;
+    if (gridDim.x % 8 == 0) b = (b % 8) * (gridDim.x / 8) + b / 8;
+    const uint32_t bx = b % A.ntx, by = (b / A.ntx) % A.nty, bz = b / (A.ntx * A.nty);
+    const uint32_t x0 = bx * TX, y0 = by * TY, z0 = bz * A.cz;
+    const uint32_t zend = min(z0 + A.cz, nz);
+    const int t = threadIdx.x;
+    const char* __restrict__ src = static_cast<const char*>(a.src);
+    char* __restrict__ dst = static_cast<char*>(a.dst);
+    const uint64_t plane_bytes = a.g.plane * sizeof(T);
+    const uint32_t rowb = nx * (uint32_t)sizeof(T);
+
+    // First step: region node r of this thread, its pulled x offsets and y rows.
+    const bool act1 = t < RN;
+    const int r = act1 ? t : 0;
+    const int rx = r % RX, ry = r / RX;
+    const uint32_t gx = (x0 + rx + nx - 1) % nx, gy = (y0 + ry + ny - 1) % ny;
+    const uint32_t xoff[3] = {wrap_inc(gx, nx) * (uint32_t)sizeof(T), gx * (uint32_t)sizeof(T),
+                              wrap_dec(gx, nx) * (uint32_t)sizeof(T)};   // x - e for e = -1, 0, +1
+    const uint32_t ysrc[3] = {wrap_inc(gy, ny), gy, wrap_dec(gy, ny)};
+    // Second step: tile node of this thread.
+    const bool in2 = t < TX * TY;
+    const int ix = t % TX, iy = t / TX;
+    const uint32_t gx2 = x0 + ix, gy2 = y0 + iy;
+    const bool act2 = in2 && gx2 < nx && gy2 < ny;
+    const int rc2 = (iy + 1) * RX + (ix + 1);
+
+    float om[8];
+    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = (float)a.omega[decltype(N)::value]; });
+    const float rho0 = (float)a.rho0;
+
+    auto load_state = [&](float (&h)[27], uint32_t qz) {
+        const uint32_t zs[3] = {wrap_inc(qz, nz), qz, wrap_dec(qz, nz)};
+        static_for<0, 27>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
+            const uint32_t off = (zs[ez + 1] * ny + ysrc[ey + 1]) * rowb + xoff[ex + 1];
+            float v = S::load(reinterpret_cast<const T*>(src + i * plane_bytes + off));
+            if constexpr (S::kScaled) v *= a.inv_s[i];
+            h[i] = v;
+        });
+    };
+    const int J = (int)(zend - z0) + 1;   // iterations j = 0..J: first step at plane z0 - 1 + j
+    // Iteration j: first step of plane z0 - 1 + j from h (then h <- the state
+    // pulled for plane z0 + 1 + j), second step of plane z0 - 2 + j.
+    auto iteration = [&](int j, float (&h)[27], uint32_t qz_ahead) {
+        if (act1) {
+            tp_collide<3, float>(h, rho0, om);
+            float* pM = sM + (j & 1) * 9 * RN;
+            float* pU = sU + (j % 3) * 9 * RN;
+            static_for<0, 27>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                float v = h[i];
+                if constexpr (S::kScaled) v = S::round(v * a.s[i]) * a.inv_s[i];
+                else v = S::round(v);
+                float* slot = i < 9 ? sD : (i < 18 ? pM : pU);
+                slot[(i % 9) * RN + r] = v;
+            });
+            if (j + 2 <= J) load_state(h, qz_ahead);
+        }
+        __syncthreads();
+        if (j >= 2 && in2) {
+            const float* pM = sM + ((j - 1) & 1) * 9 * RN;
+            const float* pU = sU + ((j - 2) % 3) * 9 * RN;
+            float g[27];
+            static_for<0, 27>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
+                const float* slot = ez == -1 ? sD : (ez == 0 ? pM : pU);
+                g[i] = slot[(i % 9) * RN + rc2 - ey * RX - ex];
+            });
+            tp_collide<3, float>(g, rho0, om);
+            if (act2) {
+                const uint32_t p = z0 + (uint32_t)j - 2;
+                const uint32_t off = (p * ny + gy2) * rowb + gx2 * (uint32_t)sizeof(T);
+                static_for<0, 27>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    float v = g[i];
+                    if constexpr (S::kScaled) v *= a.s[i];
+                    S::store(reinterpret_cast<T*>(dst + i * plane_bytes + off), v);
+                });
+            }
+        }
+        __syncthreads();
+    };
+
+    // Two register sets alternate so that the state for iteration j + 2 is in
+    // flight during iteration j + 1.
+    float ha[27], hb[27];
+    const uint32_t q0 = (z0 + nz - 1) % nz, q1 = wrap_inc(q0, nz);
+    if (act1) {
+        load_state(ha, q0);
+        load_state(hb, q1);
+    }
+    uint32_t qa = wrap_inc(q1, nz);   // plane of iteration j + 2
+    for (int j = 0; j <= J; j += 2) {
+        iteration(j, ha, qa);
+        qa = wrap_inc(qa, nz);
+        if (j + 1 <= J) iteration(j + 1, hb, qa);
+        qa = wrap_inc(qa, nz);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launcher
+// ---------------------------------------------------------------------------
+template <int ST>
+static void launch_tb(const StepArgs& a, hipStream_t s) {
+    Step2Args A;
+    A.a = a;
+    A.ntx = (a.g.nx + kTbTX - 1) / kTbTX;
+    A.nty = (a.g.ny + kTbTY - 1) / kTbTY;
+    // z chunks: enough blocks for every CU (256), at most 128 planes each
+    const uint32_t tiles = A.ntx * A.nty;
+    const uint32_t want = (256 + tiles - 1) / tiles;
+    uint32_t cz = (a.g.nz + want - 1) / want;
+    cz = cz < 4 ? 4 : (cz > 128 ? 128 : cz);
+    A.cz = cz;
+    const uint32_t nzc = (a.g.nz + cz - 1) / cz;
+    hipLaunchKernelGGL((k_step2_tp<ST>), dim3(tiles * nzc), dim3(kTbThreads), 0, s, A);
+}
+
+int launch_step2_tp(int lattice, int storage, const StepArgs& a, hipStream_t s) {
+    if (lattice != kD3Q27) return -1;
+    // lane byte offsets within a population plane are 32-bit
+    const uint64_t elem = storage == kF32 ? 4 : 2;
+    if (a.g.plane * elem >= (1ull << 31)) return -1;
+    switch (storage) {
+        case kF32: launch_tb<kF32>(a, s); return 0;
+        case kBF16: launch_tb<kBF16>(a, s); return 0;
+        case kF16: launch_tb<kF16>(a, s); return 0;
+    }
+    return -1;   // FP64: one step per launch
+}
+
+}  // namespace cmlb

@@ -57,6 +57,7 @@ def test_create_rejects_invalid_params(cm, bad):
 def test_null_context_is_rejected(cm):
     L = cm.lib()
     assert L.cmlb_step(None, 1) == cm.EINVAL
+    assert L.cmlb_set_step_fusion(None, 2) == cm.EINVAL
     assert L.cmlb_sync(None) == cm.EINVAL
     assert L.cmlb_step_count(None) == -1
     L.cmlb_destroy(None)

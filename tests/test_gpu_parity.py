@@ -348,3 +348,53 @@ def test_tgv_long_run_stable_rates(cm):
         ke.append(g["ke"])
     ctx.destroy()
     assert all(b < a for a, b in zip(ke, ke[1:]))
+
+
+FUSION_SHAPES = [
+    (5, 7, 37),      # one tile, ragged in x and y
+    (3, 4, 300),     # five x tiles with a tail
+    (2, 3, 1),       # nx = 1
+    (1, 1, 1),       # every neighbour is the node itself
+    (12, 17, 70),    # several tiles in x and y, nz not a multiple of the z chunk
+    (40, 24, 128),   # several z chunks
+]
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("shape", FUSION_SHAPES)
+def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
+    """Pairs of D3Q27 steps in one launch (intermediate state on chip) give
+    bitwise the same populations as one launch per step; odd counts end with
+    a single step."""
+    L = orc.lattice("D3Q27")
+    S = random_state(orc, "D3Q27", shape, seed=sum(shape) + 3)
+    tau = taus("D3Q27", seed=len(shape) + shape[-1])
+    scale = f16_scales(L["w"]) if storage == "f16" else None
+    out = {}
+    for fuse in (1, 2):
+        ctx = cm.Context("D3Q27", shape, storage=storage, tau=tau, scale=scale)
+        try:
+            ctx.set_step_fusion(fuse)
+            ctx.set_populations(S)
+            ctx.step(2)
+            a = ctx.get_populations()
+            ctx.step(5)
+            out[fuse] = (a, ctx.get_populations(), ctx.step_count())
+        finally:
+            ctx.destroy()
+    assert out[1][2] == out[2][2] == 7
+    assert np.array_equal(out[1][0], out[2][0])
+    assert np.array_equal(out[1][1], out[2][1])
+
+
+def test_two_step_launch_options(cm):
+    ctx = cm.Context("D3Q27", (4, 4, 4), storage="f64", tau={2: 0.6})
+    try:
+        with pytest.raises(cm.CmlbError):
+            ctx.set_step_fusion(3)
+        ctx.set_step_fusion(2)   # FP64 storage: one step per launch, silently
+        ctx.init_fields(np.ones((4, 4, 4)), np.zeros((3, 4, 4, 4)))
+        ctx.step(3)
+        assert ctx.step_count() == 3
+    finally:
+        ctx.destroy()
