@@ -279,6 +279,11 @@ def run(torch, cmlb, inputs, stream, args):
         kernel = "k_step_d37<%s, %s>" % (STORAGE_TAG[storage], MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+    if traffic is not None:
+        # bytes the launch actually moves (rocprofv3 counters) per unit time
+        moved = traffic / (kernel_ms * 1e-3) / 1e9
+        roof.update(traffic_ratio=round(traffic / alg_bytes, 4), moved_GBps=round(moved, 1),
+                    moved_frac=round(moved / PEAK_HBM_GBS, 4))
     if closure:
         kernel = "k_step_closure"
         valu = measured_valu()
