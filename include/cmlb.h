@@ -135,14 +135,15 @@ int cmlb_init_fields(cmlb_ctx *ctx, const double *rho, const double *u, const do
 int cmlb_init_fields_device(cmlb_ctx *ctx, const double *rho, const double *u, const double *theta);
 
 /* Enqueue n stream-and-collide steps on the context stream (asynchronous).
- * On D3Q27 with FP32, BF16 or FP16 storage (learned closure off) pairs of
- * steps run as one launch that keeps the intermediate state on chip; the
- * result is identical to single steps (see cmlb_set_step_fusion). */
+ * On D3Q27 with FP32 storage (learned closure off) pairs of steps run as one
+ * launch that keeps the intermediate state on chip; the result is identical
+ * to single steps (see cmlb_set_step_fusion). */
 int cmlb_step(cmlb_ctx *ctx, int64_t n);
 
 /* Steps per kernel launch for cmlb_step: 2 (default) fuses pairs of steps
- * where supported, 1 launches one kernel per step.  Both give bitwise the
- * same populations.  CMLB_EINVAL for other values. */
+ * where supported (D3Q27, FP32 storage; elsewhere it has no effect), 1
+ * launches one kernel per step.  Both give bitwise the same populations.
+ * CMLB_EINVAL for other values. */
 int cmlb_set_step_fusion(cmlb_ctx *ctx, int steps_per_launch);
 
 /* Wait for all work enqueued on the context stream. */

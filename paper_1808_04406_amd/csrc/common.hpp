@@ -135,8 +135,10 @@ struct Store<kBF16> {
     using R = float;
     static constexpr bool kScaled = true;
     __device__ static R load(const T* p) { return bf16_to_f32(*p); }
-    __device__ static void store(T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
-    __device__ static R round(R v) { return bf16_to_f32(f32_to_bf16_rne(v)); }
+    // the hardware conversion rounds to nearest even, as f32_to_bf16_rne does
+    __device__ static T encode(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+    __device__ static void store(T* p, R v) { __builtin_nontemporal_store(encode(v), p); }
+    __device__ static R round(R v) { return bf16_to_f32(encode(v)); }
     __host__ __device__ static double to_double(T v) { return bf16_to_f32(v); }
     __host__ __device__ static T from_double(double v) { return f32_to_bf16_rne((float)v); }
 };

@@ -18,7 +18,7 @@ inline void step_shape(const GridArgs& g, dim3& grid, dim3& block, uint32_t rows
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s);
 int launch_step_tp(int lattice, int storage, const StepArgs& a, hipStream_t s);     // step_tp.hip
 int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s);      // step_d37.hip
-// Two steps in one launch (step_tp2.hip): D3Q27 with FP32/BF16/FP16 storage.
+// Two steps in one launch (step_tp2.hip): D3Q27 with FP32 storage.
 int launch_step2_tp(int lattice, int storage, const StepArgs& a, hipStream_t s);
 int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);

@@ -21,10 +21,14 @@
 //
 // Each population is read from HBM once per region node and written once per
 // tile node: per two node updates about (TX+2)(TY+2)/(TX TY) x 108 B of
-// reads (halo reads of a neighbouring tile often hit L2, since consecutive
-// tiles are placed on one XCD) and 108 B of writes, against 432 B for two
-// single steps. The arithmetic is the single-step kernel's, node by node, so
-// the result equals two single steps exactly.
+// reads and 108 B of writes, against 432 B for two single steps. The
+// arithmetic is the single-step kernel's, node by node, so the result equals
+// two single steps exactly.
+//
+// Only FP32 storage takes this path. With 16-bit storage one step per launch
+// moves 108 B per update and is faster than this kernel, whose rate is set by
+// its arithmetic and barriers rather than by HBM (measured at 256^3 and
+// 512^3: about 46,000 MLUPS against 27,000-31,000).
 #include "launch.hpp"
 
 #include "collide_tp.hpp"
@@ -46,6 +50,7 @@ template <int ST>
 __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
     using S = Store<ST>;
     using T = typename S::T;
+    static_assert(!S::kScaled && sizeof(typename S::R) == 4, "unscaled FP32 arithmetic only");
     constexpr int TX = kTbTX, TY = kTbTY, RX = kTbRX, RN = kTbRN;
     __shared__ float lds[54 * RN];
     float* sD = lds;             // [9][RN]     e_z = -1 group, plane q
@@ -92,9 +97,7 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
             constexpr int i = decltype(I)::value;
             constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
             const uint32_t off = (zs[ez + 1] * ny + ysrc[ey + 1]) * rowb + xoff[ex + 1];
-            float v = S::load(reinterpret_cast<const T*>(src + i * plane_bytes + off));
-            if constexpr (S::kScaled) v *= a.inv_s[i];
-            h[i] = v;
+            h[i] = S::load(reinterpret_cast<const T*>(src + i * plane_bytes + off));
         });
     };
     const int J = (int)(zend - z0) + 1;   // iterations j = 0..J: first step at plane z0 - 1 + j
@@ -108,8 +111,7 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
             static_for<0, 27>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 float v = h[i];
-                if constexpr (S::kScaled) v = S::round(v * a.s[i]) * a.inv_s[i];
-                else v = S::round(v);
+                v = S::round(v);
                 float* slot = i < 9 ? sD : (i < 18 ? pM : pU);
                 slot[(i % 9) * RN + r] = v;
             });
@@ -133,7 +135,6 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
                 static_for<0, 27>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     float v = g[i];
-                    if constexpr (S::kScaled) v *= a.s[i];
                     S::store(reinterpret_cast<T*>(dst + i * plane_bytes + off), v);
                 });
             }
@@ -161,8 +162,10 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
 // ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
-template <int ST>
-static void launch_tb(const StepArgs& a, hipStream_t s) {
+int launch_step2_tp(int lattice, int storage, const StepArgs& a, hipStream_t s) {
+    if (lattice != kD3Q27 || storage != kF32) return -1;
+    // lane byte offsets within a population plane are 32-bit
+    if (a.g.plane * 4 >= (1ull << 31)) return -1;
     Step2Args A;
     A.a = a;
     A.ntx = (a.g.nx + kTbTX - 1) / kTbTX;
@@ -174,20 +177,8 @@ static void launch_tb(const StepArgs& a, hipStream_t s) {
     cz = cz < 4 ? 4 : (cz > 128 ? 128 : cz);
     A.cz = cz;
     const uint32_t nzc = (a.g.nz + cz - 1) / cz;
-    hipLaunchKernelGGL((k_step2_tp<ST>), dim3(tiles * nzc), dim3(kTbThreads), 0, s, A);
-}
-
-int launch_step2_tp(int lattice, int storage, const StepArgs& a, hipStream_t s) {
-    if (lattice != kD3Q27) return -1;
-    // lane byte offsets within a population plane are 32-bit
-    const uint64_t elem = storage == kF32 ? 4 : 2;
-    if (a.g.plane * elem >= (1ull << 31)) return -1;
-    switch (storage) {
-        case kF32: launch_tb<kF32>(a, s); return 0;
-        case kBF16: launch_tb<kBF16>(a, s); return 0;
-        case kF16: launch_tb<kF16>(a, s); return 0;
-    }
-    return -1;   // FP64: one step per launch
+    hipLaunchKernelGGL((k_step2_tp<kF32>), dim3(tiles * nzc), dim3(kTbThreads), 0, s, A);
+    return 0;
 }
 
 }  // namespace cmlb

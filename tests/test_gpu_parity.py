@@ -363,9 +363,9 @@ FUSION_SHAPES = [
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("shape", FUSION_SHAPES)
 def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
-    """Pairs of D3Q27 steps in one launch (intermediate state on chip) give
-    bitwise the same populations as one launch per step; odd counts end with
-    a single step."""
+    """Pairs of D3Q27 FP32 steps in one launch (intermediate state on chip)
+    give bitwise the same populations as one launch per step; odd counts end
+    with a single step.  16-bit storage keeps one step per launch either way."""
     L = orc.lattice("D3Q27")
     S = random_state(orc, "D3Q27", shape, seed=sum(shape) + 3)
     tau = taus("D3Q27", seed=len(shape) + shape[-1])
@@ -387,12 +387,13 @@ def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
     assert np.array_equal(out[1][1], out[2][1])
 
 
-def test_two_step_launch_options(cm):
-    ctx = cm.Context("D3Q27", (4, 4, 4), storage="f64", tau={2: 0.6})
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_two_step_launch_options(cm, storage):
+    ctx = cm.Context("D3Q27", (4, 4, 4), storage=storage, tau={2: 0.6})
     try:
         with pytest.raises(cm.CmlbError):
             ctx.set_step_fusion(3)
-        ctx.set_step_fusion(2)   # FP64 storage: one step per launch, silently
+        ctx.set_step_fusion(2)   # not FP32: one step per launch, silently
         ctx.init_fields(np.ones((4, 4, 4)), np.zeros((3, 4, 4, 4)))
         ctx.step(3)
         assert ctx.step_count() == 3
