@@ -235,7 +235,7 @@ def run(torch, cmlb, inputs, stream, args):
     lattice, shape, storage, _ = WORKLOADS[args.workload]
     closure = args.workload.endswith("closure_f32")
     # pairs of D3Q27 steps run as one launch (intermediate state on chip)
-    fused = lattice == "D3Q27" and storage != "f64" and not closure and args.steps_per_launch == 2
+    fused = lattice == "D3Q27" and storage == "f32" and not closure and args.steps_per_launch == 2
     ctx.set_step_fusion(args.steps_per_launch)
 
     ctx.step(args.warmup)
