@@ -116,9 +116,25 @@ def cpu_baseline(tau, target_s=12.0):
     oracle.run(cfg, S, steps, threads=threads)
     dt = time.perf_counter() - t0
     assert np.isfinite(S).all()
+    # one core, a few steps of the same sample
+    t0 = time.perf_counter()
+    k1 = max(1, min(10, int(3.0 / max(one * threads, 1e-3))))
+    oracle.run(cfg, S, k1, threads=1)
+    one_core = n ** 3 * k1 / (time.perf_counter() - t0) / 1e6
     return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"D3Q27 TGV 64^3 (same u0, tau), {steps} steps after 1 warm-up step, FP64, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s", "one_core_MLUPS": round(one_core, 3), "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def copy_bandwidth(torch, nbytes=4 << 30, reps=10):
