@@ -153,6 +153,12 @@ int cmlb_sync(cmlb_ctx *ctx);
  * (host FP64; any pointer may be NULL).  Synchronises. */
 int cmlb_get_moments(cmlb_ctx *ctx, double *rho, double *u, double *theta);
 
+/* As cmlb_get_moments into caller-owned device arrays (FP64, same layout;
+ * any pointer may be NULL), enqueued on the context stream without waiting:
+ * order later work on that stream or call cmlb_sync.  Used for on-device
+ * diagnostics such as the kinetic-energy spectrum. */
+int cmlb_get_moments_device(cmlb_ctx *ctx, double *rho, double *u, double *theta);
+
 /* Read / write the full populations f_i (decoded, host FP64, [i][node]).
  * Writing encodes to the storage type (round to nearest even). Synchronises. */
 int cmlb_get_populations(cmlb_ctx *ctx, double *f);

@@ -83,6 +83,7 @@ def lib():
         L.cmlb_set_step_fusion.argtypes = [vp, c_int]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
+        L.cmlb_get_moments_device.argtypes = [vp, vp, vp, vp]
         L.cmlb_get_populations.argtypes = [vp, dp]
         L.cmlb_set_populations.argtypes = [vp, dp]
         L.cmlb_reduce.argtypes = [vp, P(Globals)]
@@ -237,6 +238,21 @@ class Context:
         th = np.zeros(shape)
         self._check(lib().cmlb_get_moments(self.h, _dp(rho), _dp(u), _dp(th)))
         return rho, u, th
+
+    def get_moments_device(self, rho=None, u=None, theta=None):
+        """Write rho, u (lattice units), theta into FP64 device tensors (any may
+        be None), ordered on the context stream."""
+        import torch
+
+        def ptr(t, n):
+            if t is None:
+                return None
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("expected a contiguous float64 CUDA tensor of %d elements" % n)
+            return t.data_ptr()
+        nodes = int(np.prod(self.shape))
+        self._check(lib().cmlb_get_moments_device(self.h, ptr(rho, nodes), ptr(u, self.D * nodes),
+                                                  ptr(theta, nodes)))
 
     def get_populations(self):
         f = np.zeros((self.Q,) + self.shape)

@@ -465,6 +465,22 @@ int cmlb_get_moments(cmlb_ctx* c, double* rho, double* u, double* theta) {
     return CMLB_OK;
 }
 
+int cmlb_get_moments_device(cmlb_ctx* c, double* rho, double* u, double* theta) {
+    if (!c) return CMLB_EINVAL;
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    StepArgs a = base_args(c);
+    a.src = c->f[c->cur];
+    FieldArgs fa{};
+    fa.out_rho = rho;
+    fa.out_u = u;
+    fa.out_theta = theta;
+    launch_moments(c->p.lattice, c->p.storage, a, fa, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "moments kernel launch");
+    return CMLB_OK;
+}
+
 static int codec(cmlb_ctx* c, double* f, bool decode) {
     if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
     const size_t bytes = c->nodes * c->L.Q * sizeof(double);

@@ -88,3 +88,26 @@ def test_double_shear_layer_fields():
     assert abs(u[1]).max() == pytest.approx(0.05 * 0.2, rel=1e-12)
     assert u[1][:, 0] == pytest.approx(np.full(128, 0.01))                 # sin(pi/2) at x = 0
     assert (rho == 1.0).all() and (th == 1.0).all()
+
+
+def test_energy_spectrum_closed_forms():
+    """E(k) of fields with known spectra (CPU tensors; the GPU path runs the
+    same function on device moments)."""
+    import torch
+    from paper_1808_04406_amd import diagnostics, inputs
+    u0 = 0.05
+    _, u = inputs.tgv3d(32, u0)
+    E = diagnostics.spectrum_of(torch.from_numpy(u)).numpy()
+    assert E[2] == pytest.approx(u0 ** 2 / 8, rel=1e-12)           # all modes at |m| = sqrt(3)
+    assert abs(E.sum() - E[2]) < 1e-15
+    n, A = 24, 0.01
+    x = np.arange(n)
+    v = np.zeros((2, n, n))
+    v[1] = A * np.sin(2 * np.pi * 5 * x / n)[None, :]                 # shear wave, mode 5 along x
+    E = diagnostics.spectrum_of(torch.from_numpy(v)).numpy()
+    assert E[5] == pytest.approx(A ** 2 / 4, rel=1e-12)
+    w = np.random.default_rng(1).normal(size=(3, 16, 16, 16))
+    E = diagnostics.spectrum_of(torch.from_numpy(w)).numpy()
+    assert E.sum() == pytest.approx(0.5 * (w ** 2).sum(0).mean(), rel=1e-12)   # Parseval
+    with pytest.raises(ValueError):
+        diagnostics.spectrum_of(torch.zeros((3, 4, 4, 8), dtype=torch.float64))
