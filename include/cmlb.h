@@ -175,6 +175,14 @@ int cmlb_state(cmlb_ctx *ctx, void **f_cur, size_t *bytes, void **hip_stream);
 /* Number of steps taken since the last init or set. */
 int64_t cmlb_step_count(const cmlb_ctx *ctx);
 
+/* Set the step counter (a resumed checkpoint continues its count).
+ * CMLB_EINVAL for negative values. */
+int cmlb_set_step_count(cmlb_ctx *ctx, int64_t steps);
+
+/* Relaxation times in use, indexed by order: tau[n] for n = 0..7 (entries 0
+ * and 1 are unused; 0 means the default 1).  Host array of 8 doubles. */
+int cmlb_get_tau(const cmlb_ctx *ctx, double *tau);
+
 /* Storage scale s_i actually in use (Q values). */
 int cmlb_get_scale(const cmlb_ctx *ctx, double *scale);
 

@@ -90,6 +90,8 @@ def lib():
         L.cmlb_state.argtypes = [vp, P(vp), P(ctypes.c_size_t), P(vp)]
         L.cmlb_step_count.argtypes = [vp]
         L.cmlb_step_count.restype = c_i64
+        L.cmlb_set_step_count.argtypes = [vp, c_i64]
+        L.cmlb_get_tau.argtypes = [vp, dp]
         L.cmlb_get_scale.argtypes = [vp, dp]
         fp = P(ctypes.c_float)
         L.cmlb_store_state_device.argtypes = [vp, vp]
@@ -171,6 +173,7 @@ class Context:
         self.params = make_params(lattice, shape, storage, model, thermal, rho0, theta0, tau, scale,
                                   device, stream)
         self._external = external  # keep caller tensors alive
+        self._closure = None         # closure inputs (kept for checkpoints)
         h = ctypes.c_void_p()
         if external is None:
             rc = lib().cmlb_create(ctypes.byref(self.params), ctypes.byref(h))
@@ -279,6 +282,15 @@ class Context:
     def step_count(self):
         return lib().cmlb_step_count(self.h)
 
+    def set_step_count(self, n):
+        self._check(lib().cmlb_set_step_count(self.h, int(n)))
+
+    def get_tau(self):
+        """Relaxation times by order (8 values; entries 0 and 1 unused)."""
+        t = np.zeros(8)
+        self._check(lib().cmlb_get_tau(self.h, _dp(t)))
+        return t
+
     def get_scale(self):
         s = np.zeros(37)
         self._check(lib().cmlb_get_scale(self.h, _dp(s)))
@@ -304,12 +316,17 @@ class Context:
             raise ValueError("closure needs 2084 parameters and 27 scales")
         fp = ctypes.POINTER(ctypes.c_float)
         self._check(lib().cmlb_closure_load(self.h, p.ctypes.data_as(fp), s.ctypes.data_as(fp)))
+        self._closure = {"sigma": s.copy(), "enabled": False, "tie_even": False}
 
     def closure_enable(self, on=True):
         self._check(lib().cmlb_closure_enable(self.h, 1 if on else 0))
+        if getattr(self, "_closure", None) is not None:
+            self._closure["enabled"] = bool(on)
 
     def closure_tie_even(self, on=True):
         self._check(lib().cmlb_closure_tie_even(self.h, 1 if on else 0))
+        if getattr(self, "_closure", None) is not None:
+            self._closure["tie_even"] = bool(on)
 
     def closure_get(self):
         p = np.zeros(CLOSURE_NPARAM, np.float32)

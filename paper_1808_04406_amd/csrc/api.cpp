@@ -262,8 +262,10 @@ int create_impl(const cmlb_params* p, void* fa, void* fb, cmlb_ctx** out) {
     }
     const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(p->storage);
     if (fa || fb) {
-        if (!fa || !fb || fa == fb || ((uintptr_t)fa % 256) || ((uintptr_t)fb % 256)) {
-            g_create_error = "external buffers must be two distinct non-NULL 256-byte aligned pointers";
+        const uintptr_t a0 = (uintptr_t)fa, b0 = (uintptr_t)fb;
+        const bool overlap = a0 < b0 + bytes && b0 < a0 + bytes;   // the step reads one and writes the other
+        if (!fa || !fb || overlap || (a0 % 256) || (b0 % 256)) {
+            g_create_error = "external buffers must be two non-overlapping non-NULL 256-byte aligned pointers";
             cmlb_destroy(c);
             return CMLB_EINVAL;
         }
@@ -559,6 +561,19 @@ int cmlb_state(cmlb_ctx* c, void** f_cur, size_t* bytes, void** stream) {
 }
 
 int64_t cmlb_step_count(const cmlb_ctx* c) { return c ? c->steps : -1; }
+
+int cmlb_set_step_count(cmlb_ctx* c, int64_t steps) {
+    if (!c) return CMLB_EINVAL;
+    if (steps < 0) return fail(c, CMLB_EINVAL, "negative step count");
+    c->steps = steps;
+    return CMLB_OK;
+}
+
+int cmlb_get_tau(const cmlb_ctx* c, double* tau) {
+    if (!c || !tau) return CMLB_EINVAL;
+    for (int k = 0; k < 8; ++k) tau[k] = c->p.tau[k];
+    return CMLB_OK;
+}
 
 int cmlb_store_state_device(cmlb_ctx* c, void* dst) {
     if (!c) return CMLB_EINVAL;

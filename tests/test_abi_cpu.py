@@ -58,6 +58,7 @@ def test_null_context_is_rejected(cm):
     L = cm.lib()
     assert L.cmlb_step(None, 1) == cm.EINVAL
     assert L.cmlb_set_step_fusion(None, 2) == cm.EINVAL
+    assert L.cmlb_set_step_count(None, 3) == cm.EINVAL
     assert L.cmlb_sync(None) == cm.EINVAL
     assert L.cmlb_step_count(None) == -1
     L.cmlb_destroy(None)
@@ -111,3 +112,22 @@ def test_energy_spectrum_closed_forms():
     assert E.sum() == pytest.approx(0.5 * (w ** 2).sum(0).mean(), rel=1e-12)   # Parseval
     with pytest.raises(ValueError):
         diagnostics.spectrum_of(torch.zeros((3, 4, 4, 8), dtype=torch.float64))
+
+
+def test_checkpoint_header_errors(tmp_path):
+    from paper_1808_04406_amd import checkpoint
+    bad = tmp_path / "x.bin"
+    bad.write_bytes(b"NOTACKPT" + b"\0" * 32)
+    with pytest.raises(ValueError):
+        checkpoint.read_header(str(bad))
+    import json
+    import struct
+    hb = json.dumps({"lattice": "D3Q27"}).encode()
+    ok = tmp_path / "y.bin"
+    ok.write_bytes(checkpoint.MAGIC + struct.pack("<IQ", checkpoint.VERSION, len(hb)) + hb)
+    h, off = checkpoint.read_header(str(ok))
+    assert h["lattice"] == "D3Q27" and off == 20 + len(hb)
+    old = tmp_path / "z.bin"
+    old.write_bytes(checkpoint.MAGIC + struct.pack("<IQ", 99, len(hb)) + hb)
+    with pytest.raises(ValueError):
+        checkpoint.read_header(str(old))

@@ -423,3 +423,43 @@ def test_device_moments_and_energy_spectrum(cm):
         assert E[2] / E.sum() > 0.999          # the Taylor-Green modes, |m| = sqrt(3)
     finally:
         ctx.destroy()
+
+
+@pytest.mark.parametrize("kind,shape,storage,thermal,closure", [
+    ("D3Q27", (6, 10, 70), "f32", False, False),
+    ("D3Q27", (6, 10, 70), "f16", False, False),
+    ("D2Q37", (24, 40), "bf16", True, False),
+    ("D3Q27", (4, 8, 64), "f32", False, True),
+])
+def test_checkpoint_resume_is_bitwise(cm, orc, tmp_path, kind, shape, storage, thermal, closure):
+    """Save after 9 steps, continue 7; a context loaded from the file and
+    stepped 7 times holds bitwise the same populations and step count."""
+    from paper_1808_04406_amd import checkpoint
+    L = orc.lattice(kind)
+    S = random_state(orc, kind, shape, seed=41, thermal=thermal)
+    tau = taus(kind, 5)
+    ctx = cm.Context(kind, shape, storage=storage, thermal=thermal, tau=tau,
+                     scale=f16_scales(L["w"]) if storage == "f16" else None)
+    try:
+        ctx.set_populations(S)
+        if closure:
+            P = 0.3 * np.random.default_rng(3).normal(size=cm.CLOSURE_NPARAM)
+            ctx.closure_load(P, np.full(27, 0.01))
+            ctx.closure_tie_even(True)
+            ctx.closure_enable(True)
+        ctx.step(9)
+        ctx.set_tau([tau[2] * 1.01])
+        path = str(tmp_path / "state.cmlb")
+        checkpoint.save(ctx, path)
+        ctx.step(7)
+        want, n_want = ctx.get_populations(), ctx.step_count()
+    finally:
+        ctx.destroy()
+    ctx = checkpoint.load(path)
+    try:
+        assert ctx.step_count() == 9
+        ctx.step(7)
+        assert ctx.step_count() == n_want == 16
+        assert np.array_equal(ctx.get_populations(), want)
+    finally:
+        ctx.destroy()
