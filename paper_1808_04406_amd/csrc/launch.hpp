@@ -7,11 +7,25 @@ namespace cmlb {
 
 GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz);
 
-// Step-kernel launch shape: one block per x-segment of each of `rows` rows.
-inline void step_shape(const GridArgs& g, dim3& grid, dim3& block, uint32_t rows) {
-    const uint32_t bs = g.nx >= 256 ? 256u : ((g.nx + 63u) / 64u) * 64u;
+// Step-kernel launch shape: one block per x-segment of each of `rows` rows,
+// segments of up to max_block nodes (a whole row when it fits, so that the
+// x-shifted reads of a row stay in one block and one L2), and the matching
+// chunk count written to a.g.nchunks.
+inline void step_shape(StepArgs& a, dim3& grid, dim3& block, uint32_t rows, uint32_t max_block) {
+    uint32_t bs = ((a.g.nx + 63u) / 64u) * 64u;
+    if (bs > max_block) bs = max_block;
+    a.g.nchunks = (a.g.nx + bs - 1) / bs;
     block = dim3(bs);
-    grid = dim3(g.nchunks * rows);
+    grid = dim3(a.g.nchunks * rows);
+}
+
+// Block index -> logical block: blocks are dealt round-robin to the 8 XCDs;
+// give each XCD a contiguous run of logical blocks, so that the chunks of one
+// row, which share cache lines at their edges, meet in one L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t nchunks) {
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    if (nchunks == 1 || nb % 8 != 0) return b;
+    return (b % 8) * (nb / 8) + b / 8;
 }
 
 // Each returns 0, or -1 for an unsupported lattice/storage/model combination.

@@ -1,7 +1,8 @@
 // Fused pull-stream + collide for the thermal D2Q37 lattice (order-4
 // Hermite truncation; central-moment or raw-moment MRT), and its launcher.
 // Same thread/block mapping as the tensor-product step: one thread per
-// node, one x-segment of a row per block, block-uniform source rows.
+// node, one x-segment of a row (up to 512 nodes) per block, block-uniform
+// source rows.
 #include "launch.hpp"
 
 #include "collide_d2q37.hpp"
@@ -12,13 +13,14 @@ namespace cmlb {
 // Hot path: D2Q37 stream + collide (order-4 Hermite truncation)
 // ---------------------------------------------------------------------------
 template <int ST, int MODEL>
-__global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
+__global__ __launch_bounds__(512) void k_step_d37(StepArgs a) {
     using S = Store<ST>;
     using R = typename S::R;
     using T = typename S::T;
     const uint32_t nx = a.g.nx, ny = a.g.ny;
-    const uint32_t chunk = blockIdx.x % a.g.nchunks;
-    const uint32_t y = blockIdx.x / a.g.nchunks;
+    const uint32_t blk = xcd_block(a.g.nchunks);
+    const uint32_t chunk = blk % a.g.nchunks;
+    const uint32_t y = blk / a.g.nchunks;
     const uint32_t x = chunk * blockDim.x + threadIdx.x;
     if (x >= nx) return;
     const char* __restrict__ src = static_cast<const char*>(a.src);
@@ -57,9 +59,9 @@ __global__ __launch_bounds__(256) void k_step_d37(StepArgs a) {
 // Launcher
 // ---------------------------------------------------------------------------
 template <int ST, int MODEL>
-static void launch_d37(const StepArgs& a, hipStream_t s) {
+static void launch_d37(StepArgs a, hipStream_t s) {
     dim3 grid, block;
-    step_shape(a.g, grid, block, a.g.ny);
+    step_shape(a, grid, block, a.g.ny, 512);   // FP64 needs up to 142 VGPRs: at most 512 threads
     hipLaunchKernelGGL((k_step_d37<ST, MODEL>), grid, block, 0, s, a);
 }
 

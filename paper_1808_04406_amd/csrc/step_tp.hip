@@ -1,10 +1,10 @@
 // Fused pull-stream + collide for the tensor-product lattices D2Q9 and
 // D3Q27 (the hot path), and its launcher.
 //
-// One thread per node; a block covers one contiguous x-segment of a row, so
-// the y/z neighbour rows of every population are block-uniform addresses
-// and each wavefront reads and writes 27 (9) contiguous runs of the
-// structure-of-arrays field F[i][z][y][x].  Two buffers alternate (pull from
+// One thread per node; a block covers one contiguous x-segment of a row (the
+// whole row up to 1024 nodes), so the y/z neighbour rows of every population
+// are block-uniform addresses and each wavefront reads and writes 27 (9)
+// contiguous runs of the structure-of-arrays field F[i][z][y][x].  Two buffers alternate (pull from
 // one, write the other), so reads and writes never alias.
 #include "launch.hpp"
 
@@ -16,14 +16,15 @@ namespace cmlb {
 // Hot path: D2Q9 / D3Q27 stream + collide
 // ---------------------------------------------------------------------------
 template <int D, int ST>
-__global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
+__global__ __launch_bounds__(1024) void k_step_tp(StepArgs a) {
     using S = Store<ST>;
     using R = typename S::R;
     using T = typename S::T;
     constexpr int Q = TP<D>::Q;
     const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const uint32_t chunk = blockIdx.x % a.g.nchunks;
-    const uint32_t row = blockIdx.x / a.g.nchunks;
+    const uint32_t blk = xcd_block(a.g.nchunks);
+    const uint32_t chunk = blk % a.g.nchunks;
+    const uint32_t row = blk / a.g.nchunks;
     const uint32_t x = chunk * blockDim.x + threadIdx.x;
     if (x >= nx) return;
     const uint32_t y = row % ny, z = row / ny;
@@ -64,9 +65,9 @@ __global__ __launch_bounds__(256) void k_step_tp(StepArgs a) {
 // Launcher
 // ---------------------------------------------------------------------------
 template <int D, int ST>
-static void launch_tp(const StepArgs& a, hipStream_t s) {
+static void launch_tp(StepArgs a, hipStream_t s) {
     dim3 grid, block;
-    step_shape(a.g, grid, block, a.g.ny * a.g.nz);
+    step_shape(a, grid, block, a.g.ny * a.g.nz, 1024);
     hipLaunchKernelGGL((k_step_tp<D, ST>), grid, block, 0, s, a);
 }
 
