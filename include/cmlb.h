@@ -54,8 +54,9 @@ enum { CMLB_D2Q9 = 0, CMLB_D3Q27 = 1, CMLB_D2Q37 = 2 };
 
 /* Storage of the population field.  Every type stores the deviation
  * g_i = s_i (f_i - w_i rho0); arithmetic is FP64 for CMLB_F64 and FP32 for
- * the others.  s_i is a power of two (1 for F64/F32/BF16; for F16 chosen
- * from w_i so that |f_i - w_i rho0| up to 8 w_i stays representable). */
+ * the others.  The automatic s_i is a power of two: 1 for F64/F32/BF16, and
+ * for F16 chosen from w_i so that |f_i - w_i rho0| up to 8 w_i stays
+ * representable (cmlb_params.scale overrides it). */
 enum { CMLB_F64 = 0, CMLB_F32 = 1, CMLB_BF16 = 2, CMLB_F16 = 3 };
 
 /* Collision model.  CMLB_MODEL_CM is the paper's central-moment MRT
@@ -110,7 +111,9 @@ int cmlb_create(const cmlb_params *p, cmlb_ctx **out);
 
 /* As cmlb_create, but the population buffers f_a and f_b are device memory
  * owned by the caller (for example PyTorch tensors), each at least
- * Q * nx*ny*nz elements of the storage type, 256-byte aligned, distinct. */
+ * Q * nx*ny*nz elements of the storage type, 256-byte aligned and not
+ * overlapping (a step reads one and writes the other); CMLB_EINVAL
+ * otherwise. */
 int cmlb_create_external(const cmlb_params *p, void *f_a, void *f_b, cmlb_ctx **out);
 
 /* Reason for the last failed create on this thread. */
