@@ -41,6 +41,10 @@ run at rest (velocity deviation relative to u0, and the kinetic energy and
 enstrophy histories). The D3Q27 velocity set cannot resolve the third
 per-axis moment, so a small O(U^2) deviation is expected.
 
+tgv: the benchmark's D3Q27 Taylor-Green vortex (Re = 1600, FP32) for 2000
+steps; FP64 kinetic-energy and enstrophy histories and the energy balance
+of incompressible periodic flow, dKE/dt = -2 nu Z, with nu = (tau - 1/2)/3.
+
 Results are written as JSON (``--out``) and summarised on stdout.
 """
 from __future__ import annotations
@@ -321,6 +325,35 @@ def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0)
     return out
 
 
+def tgv_energy(n=256, steps=2000, every=20, u0=0.05, re=1600.0, stream=None):
+    tau = 0.5 + 3.0 * u0 * (n / (2 * math.pi)) / re
+    nu = (tau - 0.5) / 3.0
+    ctx = cmlb.Context("D3Q27", (n,) * 3, storage="f32", tau=_tgv_rates(tau), stream=stream)
+    rho, u = inputs.tgv3d(n, u0)
+    ctx.init_fields(rho, u)
+    del rho, u
+    t, ke, z = [], [], []
+    t0 = time.perf_counter()
+    for k in range(0, steps + 1, every):
+        if k:
+            ctx.step(every)
+        g = ctx.reduce()
+        t.append(k)
+        ke.append(g["ke"])
+        z.append(g["enstrophy"])
+    wall = time.perf_counter() - t0
+    ctx.destroy()
+    t, ke, z = np.array(t, float), np.array(ke), np.array(z)
+    dke = (ke[2:] - ke[:-2]) / (t[2:] - t[:-2])          # central differences
+    rel = (dke + 2.0 * nu * z[1:-1]) / (2.0 * nu * z[1:-1])
+    res = {"n": n, "steps": steps, "every": every, "u0": u0, "re": re, "tau": tau, "nu_lattice": nu,
+           "t": t.tolist(), "ke": ke.tolist(), "enstrophy": z.tolist(),
+           "balance_rel_err": rel.tolist(), "max_abs_balance_rel_err": float(np.abs(rel).max()), "wall_s": wall}
+    print(f"TGV {n}^3 Re={re}: max |dKE/dt + 2 nu Z| / (2 nu Z) = {res['max_abs_balance_rel_err']:.3e}, "
+          f"KE {ke[0]:.4e} -> {ke[-1]:.4e}, Z {z[0]:.4e} -> {z[-1]:.4e}", flush=True)
+    return res
+
+
 def galilean(n=256, steps=2000, every=100, us=(0.05, 0.1), u0=0.05, re=1600.0, stream=None):
     tau = 0.5 + 3.0 * u0 * (n / (2 * math.pi)) / re
     res = {"n": n, "steps": steps, "u0": u0, "re": re, "tau": tau, "runs": {}}
@@ -582,7 +615,7 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "thermal", "closure", "modes", "dsl", "galilean"])
+    ap.add_argument("study", choices=["precision", "thermal", "closure", "modes", "dsl", "galilean", "tgv"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--every", type=int, default=None)
@@ -602,6 +635,9 @@ def main(argv=None):
             res = modes(stream=stream)
         elif a.study == "dsl":
             res = dsl(n=a.n or 128, stream=stream)
+        elif a.study == "tgv":
+            res = tgv_energy(n=a.n or 256, steps=a.steps if a.steps != 5000 else 2000, every=a.every or 20,
+                             stream=stream)
         elif a.study == "galilean":
             res = galilean(n=a.n or 256, steps=a.steps if a.steps != 5000 else 2000, every=a.every or 100,
                            stream=stream)

@@ -182,3 +182,16 @@ def test_galilean_tgv_small(cm):
     assert r["runs"]["0.1"]["max_du_over_u0"][0] < 1e-6          # identical initial states
     assert d05 < 0.05 and d10 < 0.05
     assert 1.5 < d10 / d05 < 4.5
+
+
+def test_tgv_energy_balance(cm):
+    """D3Q27 Taylor-Green vortex, 64^3, Re = 100: the kinetic energy decays as
+    dKE/dt = -2 nu Z (incompressible periodic flow), with nu = (tau - 1/2)/3
+    in lattice units.  Deviations come from compressibility, O(Ma^2) ~ 1e-2
+    at u0 = 0.05, and from the second-order differences in Z, O((k dx)^2) ~
+    3e-3; the bound is 2 %."""
+    from paper_1808_04406_amd import studies
+    r = studies.tgv_energy(n=64, steps=400, every=10, re=100.0)
+    print("max rel. balance error", r["max_abs_balance_rel_err"])
+    assert r["max_abs_balance_rel_err"] < 0.02
+    assert r["ke"][-1] < r["ke"][0]
