@@ -149,6 +149,17 @@ int cmlb_step(cmlb_ctx *ctx, int64_t n);
  * CMLB_EINVAL for other values. */
 int cmlb_set_step_fusion(cmlb_ctx *ctx, int steps_per_launch);
 
+/* Replay the steps of cmlb_step from a HIP graph of `steps` steps (a
+ * positive multiple of 4; 0, the default, launches every kernel directly).
+ * The graph is captured on the context stream at the first cmlb_step of at
+ * least `steps` steps and replayed n / steps times; the remaining steps are
+ * launched directly.  Results are bitwise those of direct launches.  The
+ * graph is recaptured after cmlb_set_tau, cmlb_set_step_fusion and
+ * cmlb_closure_enable, and whenever the buffer parity differs from the
+ * captured one.  Useful where launches are short (small grids).
+ * CMLB_EINVAL for other values. */
+int cmlb_set_graph_steps(cmlb_ctx *ctx, int steps);
+
 /* Wait for all work enqueued on the context stream. */
 int cmlb_sync(cmlb_ctx *ctx);
 

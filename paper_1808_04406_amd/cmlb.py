@@ -81,6 +81,7 @@ def lib():
         L.cmlb_init_fields_device.argtypes = [vp, vp, vp, vp]
         L.cmlb_step.argtypes = [vp, c_i64]
         L.cmlb_set_step_fusion.argtypes = [vp, c_int]
+        L.cmlb_set_graph_steps.argtypes = [vp, c_int]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
         L.cmlb_get_moments_device.argtypes = [vp, vp, vp, vp]
@@ -226,6 +227,10 @@ class Context:
 
     def step(self, n=1):
         self._check(lib().cmlb_step(self.h, int(n)))
+
+    def set_graph_steps(self, steps):
+        """Replay steps from a HIP graph of `steps` steps (multiple of 4; 0 = direct launches)."""
+        self._check(lib().cmlb_set_graph_steps(self.h, int(steps)))
 
     def set_step_fusion(self, steps_per_launch):
         """2 (default): pairs of D3Q27 steps in one launch where supported; 1: one launch per step."""

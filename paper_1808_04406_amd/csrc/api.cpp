@@ -139,6 +139,11 @@ struct cmlb_ctx {
     float s[37] = {}, inv_s[37] = {};
     int64_t steps = 0;
     int fuse = 2;                 // steps per launch where the two-step kernel applies
+    // HIP graph of graph_steps steps (0: launch eagerly), captured from the
+    // buffer parity graph_cur; replays leave the parity unchanged
+    int graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    int graph_cur = -1;
     std::string err;
     // reduction scratch (allocated on first use)
     double* red_u = nullptr;
@@ -165,6 +170,13 @@ int fail(cmlb_ctx* c, int code, const std::string& msg) {
 
 int hip_fail(cmlb_ctx* c, hipError_t e, const char* where) {
     return fail(c, CMLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Forget the captured step graph (its kernel arguments are out of date).
+void graph_drop(cmlb_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_cur = -1;
 }
 
 StepArgs base_args(const cmlb_ctx* c) {
@@ -338,6 +350,7 @@ void cmlb_destroy(cmlb_ctx* c) {
     if (c->cl_net) (void)hipFree(c->cl_net);
     if (c->cl_partials) (void)hipFree(c->cl_partials);
     if (c->cl_grad) (void)hipFree(c->cl_grad);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -351,6 +364,7 @@ int cmlb_set_tau(cmlb_ctx* c, const double* tau, int n) {
         if (!(tau[k] > 0.0) || !std::isfinite(tau[k])) return fail(c, CMLB_EINVAL, "tau must be positive and finite");
     for (int k = 0; k < n; ++k) c->p.tau[k + 2] = tau[k];
     set_omegas(c);
+    graph_drop(c);   // the rates are kernel arguments
     return CMLB_OK;
 }
 
@@ -402,11 +416,8 @@ int cmlb_init_fields(cmlb_ctx* c, const double* rho, const double* u, const doub
     return CMLB_OK;
 }
 
-int cmlb_step(cmlb_ctx* c, int64_t n) {
-    if (!c) return CMLB_EINVAL;
-    if (n < 0) return fail(c, CMLB_EINVAL, "negative step count");
-    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
-    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+// Enqueue n steps on the context stream, one or two steps per launch.
+static int enqueue_steps(cmlb_ctx* c, int64_t n) {
     StepArgs a = base_args(c);
     for (int64_t k = 0; k < n;) {
         a.src = c->f[c->cur];
@@ -428,11 +439,73 @@ int cmlb_step(cmlb_ctx* c, int64_t n) {
     return CMLB_OK;
 }
 
+// Capture graph_steps steps from the current buffer parity into c->gexec.
+static int graph_capture(cmlb_ctx* c) {
+    graph_drop(c);
+    const int cur0 = c->cur;
+    const int64_t steps0 = c->steps;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture begin");
+    int rc = enqueue_steps(c, c->graph_steps);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    const bool back = c->cur == cur0;   // an even number of launches
+    c->cur = cur0;                       // nothing ran yet
+    c->steps = steps0;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture end");
+    if (!back) {
+        (void)hipGraphDestroy(g);
+        return fail(c, CMLB_EINVAL, "graph steps must give an even number of launches");
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return hip_fail(c, e, "graph instantiate");
+    }
+    c->graph_cur = cur0;
+    return CMLB_OK;
+}
+
+int cmlb_step(cmlb_ctx* c, int64_t n) {
+    if (!c) return CMLB_EINVAL;
+    if (n < 0) return fail(c, CMLB_EINVAL, "negative step count");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    if (c->graph_steps > 0 && n >= c->graph_steps) {
+        if (!c->gexec || c->graph_cur != c->cur) {
+            int rc = graph_capture(c);
+            if (rc) return rc;
+        }
+        const int64_t reps = n / c->graph_steps;
+        for (int64_t r = 0; r < reps; ++r) {
+            hipError_t e = hipGraphLaunch(c->gexec, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+            c->steps += c->graph_steps;
+        }
+        n -= reps * c->graph_steps;
+    }
+    return enqueue_steps(c, n);
+}
+
+int cmlb_set_graph_steps(cmlb_ctx* c, int steps) {
+    if (!c) return CMLB_EINVAL;
+    if (steps < 0 || steps % 4 != 0) return fail(c, CMLB_EINVAL, "graph steps must be 0 or a positive multiple of 4");
+    graph_drop(c);
+    c->graph_steps = steps;
+    return CMLB_OK;
+}
+
 int cmlb_set_step_fusion(cmlb_ctx* c, int steps_per_launch) {
     if (!c) return CMLB_EINVAL;
     if (steps_per_launch != 1 && steps_per_launch != 2)
         return fail(c, CMLB_EINVAL, "steps per launch must be 1 or 2");
     c->fuse = steps_per_launch;
+    graph_drop(c);
     return CMLB_OK;
 }
 
@@ -662,6 +735,7 @@ int cmlb_closure_enable(cmlb_ctx* c, int on) {
         if (rc) return rc;
     }
     c->closure_on = on != 0;
+    graph_drop(c);
     return CMLB_OK;
 }
 

@@ -508,3 +508,54 @@ def test_checkpoint_resume_is_bitwise(cm, orc, tmp_path, kind, shape, storage, t
         assert np.array_equal(ctx.get_populations(), want)
     finally:
         ctx.destroy()
+
+
+@pytest.mark.parametrize("kind,shape,thermal,closure", [
+    ("D3Q27", (12, 10, 70), False, False),   # two steps per launch
+    ("D2Q37", (24, 40), True, False),
+    ("D3Q27", (4, 8, 64), False, True),      # learned closure, one step per launch
+])
+def test_graph_replay_equals_direct_launches(cm, orc, kind, shape, thermal, closure):
+    """Steps replayed from a HIP graph give bitwise the direct launches' state:
+    several replays, with the program's own work (moments, reductions,
+    synchronisation) between them, a rate change (recapture) and step counts
+    that leave remainders and flip the buffer parity."""
+    S = random_state(orc, kind, shape, seed=23, thermal=thermal)
+    tau = taus(kind, 9)
+    ctxs = [cm.Context(kind, shape, storage="f32", thermal=thermal, tau=tau) for _ in range(2)]
+    try:
+        ctxs[1].set_graph_steps(8)
+        P = 0.3 * np.random.default_rng(4).normal(size=cm.CLOSURE_NPARAM)
+        for c in ctxs:
+            c.set_populations(S)
+            if closure:
+                c.closure_load(P, np.full(27, 0.01))
+                c.closure_tie_even(True)
+                c.closure_enable(True)
+        for k, n in enumerate((8, 17, 3, 24, 9, 16)):
+            if k == 3:
+                for c in ctxs:
+                    c.set_tau([tau[2] * 1.02])
+            for c in ctxs:
+                c.step(n)
+            ctxs[1].get_moments()
+            ctxs[1].reduce()
+            ctxs[1].sync()
+            a, b = ctxs[0].get_populations(), ctxs[1].get_populations()
+            assert ctxs[0].step_count() == ctxs[1].step_count()
+            assert np.array_equal(a, b), (k, n)
+    finally:
+        for c in ctxs:
+            c.destroy()
+
+
+def test_graph_steps_validation(cm):
+    ctx = cm.Context("D3Q27", (4, 4, 4), storage="f32", tau={2: 0.6})
+    try:
+        for bad in (-4, 6, 1):
+            with pytest.raises(cm.CmlbError):
+                ctx.set_graph_steps(bad)
+        ctx.set_graph_steps(0)
+        ctx.set_graph_steps(4)
+    finally:
+        ctx.destroy()
