@@ -143,10 +143,15 @@ int cmlb_init_fields_device(cmlb_ctx *ctx, const double *rho, const double *u, c
  * to single steps (see cmlb_set_step_fusion). */
 int cmlb_step(cmlb_ctx *ctx, int64_t n);
 
-/* Steps per kernel launch for cmlb_step: 2 (default) fuses pairs of steps
- * where supported (D3Q27, FP32 storage; elsewhere it has no effect), 1
- * launches one kernel per step.  Both give bitwise the same populations.
- * CMLB_EINVAL for other values. */
+/* Steps per kernel launch for cmlb_step.  Two steps per launch are
+ * supported on D3Q27 with FP32 storage and the learned closure off; elsewhere
+ * every value launches one kernel per step.
+ *   0 (default)  automatic: two steps per launch where supported, unless a
+ *                cost model of the grid's launch shape expects two single
+ *                launches to be faster (small grids);
+ *   1            one kernel per step;
+ *   2            two steps per launch wherever supported.
+ * All give bitwise the same populations.  CMLB_EINVAL for other values. */
 int cmlb_set_step_fusion(cmlb_ctx *ctx, int steps_per_launch);
 
 /* Replay the steps of cmlb_step from a HIP graph of `steps` steps (a

@@ -162,22 +162,72 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
 // ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
-int launch_step2_tp(int lattice, int storage, const StepArgs& a, hipStream_t s) {
+// One 704-thread workgroup fills a CU's LDS, so a launch of B workgroups runs
+// in ceil(B / 256) rounds.  A workgroup whose chunk has cz planes makes
+// cz + 2 first-step iterations (its first step starts one plane below the
+// chunk and ends one plane above it) and cz second-step iterations.
+//
+// Cost model of a launch (fitted to MI355X measurements of grids from 32^3
+// to 384^3, within about 6 %): a first-step iteration of a full round takes
+// 3.55 us and a second-step one 2.75 us; half of that time scales with the
+// fraction of tile nodes inside the grid (ragged tiles move less data); a
+// launch costs 3 us.  The z chunking is the one with the lowest modelled
+// time.  A single step costs 3 us plus 38 ps per node (its HBM rate), which
+// decides, in automatic mode, between this kernel and two single steps.
+constexpr double kTb1Us = 3.55, kTb2Us = 2.75, kLaunchUs = 3.0, kStepPsPerNode = 38.0;
+
+namespace {
+struct Step2Plan {
+    Step2Args A;
+    uint32_t blocks;
+    double cost_us;   // model time of the launch
+};
+
+Step2Plan step2_plan(const StepArgs& a) {
+    // the plan depends on the grid only; callers step one grid many times
+    thread_local uint32_t key[3] = {0, 0, 0};
+    thread_local Step2Plan last;
+    if (key[0] == a.g.nx && key[1] == a.g.ny && key[2] == a.g.nz) {
+        Step2Plan P = last;
+        P.A.a = a;
+        return P;
+    }
+    Step2Plan P;
+    P.A.a = a;
+    P.A.ntx = (a.g.nx + kTbTX - 1) / kTbTX;
+    P.A.nty = (a.g.ny + kTbTY - 1) / kTbTY;
+    const uint64_t tiles = (uint64_t)P.A.ntx * P.A.nty;
+    const double fill = (double)a.g.nx * a.g.ny / ((double)tiles * kTbTX * kTbTY);
+    const double scale = 0.5 + 0.5 * fill;
+    double best = 0.0;
+    uint32_t best_cz = a.g.nz;
+    // beyond 4096 chunks every count needs more rounds than it saves planes
+    for (uint32_t nzc = 1; nzc <= a.g.nz && nzc <= 4096; ++nzc) {
+        const uint32_t cz = (a.g.nz + nzc - 1) / nzc;
+        if ((a.g.nz + cz - 1) / cz != nzc) continue;   // the same chunking as a smaller count
+        const double rounds = (double)((tiles * nzc + 255) / 256);
+        const double t = rounds * ((cz + 2) * kTb1Us + cz * kTb2Us) * scale;
+        if (nzc == 1 || t < best) { best = t; best_cz = cz; }
+    }
+    P.A.cz = best_cz;
+    P.blocks = (uint32_t)(tiles * ((a.g.nz + best_cz - 1) / best_cz));
+    P.cost_us = kLaunchUs + best;
+    key[0] = a.g.nx; key[1] = a.g.ny; key[2] = a.g.nz;
+    last = P;
+    return P;
+}
+}  // namespace
+
+int launch_step2_tp(int lattice, int storage, const StepArgs& a, bool force, hipStream_t s) {
     if (lattice != kD3Q27 || storage != kF32) return -1;
     // lane byte offsets within a population plane are 32-bit
     if (a.g.plane * 4 >= (1ull << 31)) return -1;
-    Step2Args A;
-    A.a = a;
-    A.ntx = (a.g.nx + kTbTX - 1) / kTbTX;
-    A.nty = (a.g.ny + kTbTY - 1) / kTbTY;
-    // z chunks: enough blocks for every CU (256), at most 128 planes each
-    const uint32_t tiles = A.ntx * A.nty;
-    const uint32_t want = (256 + tiles - 1) / tiles;
-    uint32_t cz = (a.g.nz + want - 1) / want;
-    cz = cz < 4 ? 4 : (cz > 128 ? 128 : cz);
-    A.cz = cz;
-    const uint32_t nzc = (a.g.nz + cz - 1) / cz;
-    hipLaunchKernelGGL((k_step2_tp<kF32>), dim3(tiles * nzc), dim3(kTbThreads), 0, s, A);
+    const Step2Plan P = step2_plan(a);
+    if (!force) {
+        const double single_us = kLaunchUs + (double)a.g.plane * kStepPsPerNode * 1e-6;
+        if (P.cost_us >= 2.0 * single_us) return -1;
+    }
+    hipLaunchKernelGGL((k_step2_tp<kF32>), dim3(P.blocks), dim3(kTbThreads), 0, s, P.A);
     return 0;
 }
 

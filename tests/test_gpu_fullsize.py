@@ -1,0 +1,161 @@
+"""Parity at the full sizes of the paper-shaped workloads, on sampled outputs.
+
+* D3Q27 512^3 Taylor-Green vortex at Re = 1e5 (u0 = 0.05), the precision
+  form: BF16 and FP16 deviation storage (FP32 arithmetic) and FP32 storage,
+  two steps.  Population byte offsets reach 14 GB, so 64-bit addressing of
+  the population planes is exercised; the FP32 pair of steps runs in one
+  launch of the two-step kernel.  The oracle computes the two steps at each
+  sampled node from the equilibrium of the initial fields on its 5^3
+  neighbourhood, rounding the intermediate state through the storage codec
+  as the stored state is rounded.
+* D2Q37 1024^2 thermal shear and temperature waves (Pr = 7, background
+  velocity 0.1 normal to k): two steps, every node.
+* D3Q27 128^3 learned closure on a perturbed Taylor-Green state: one step
+  at sampled nodes.
+
+Tolerances as in the small parity tests (per storage, relative to the
+largest deviation |f_i - w_i rho0|), doubled for two steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1808_04406_amd import inputs
+
+from test_gpu_parity import TOL, f16_scales, quantise
+from test_gpu_closure import params
+
+pytestmark = pytest.mark.gpu
+
+TORCH_DTYPE = {"f32": "float32", "bf16": "bfloat16", "f16": "float16"}
+
+
+@pytest.fixture(scope="module")
+def tgv512():
+    n, u0, re = 512, 0.05, 1.0e5
+    rho, u = inputs.tgv3d(n, u0)
+    nu = u0 * (n / (2 * math.pi)) / re
+    t2 = 0.5 + 3.0 * nu
+    return n, rho, u, {2: t2, 3: 1.0, 4: t2, 5: 1.0, 6: t2}
+
+
+def sampled_state(ctx, storage, nodes, scale, w):
+    """Stored populations of the given nodes, decoded (f = g / s + w rho0) on the host."""
+    import torch
+    _, nbytes, _ = ctx.state()
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ctx.store_state_device(buf)
+    ctx.sync()
+    g = buf.view(getattr(torch, TORCH_DTYPE[storage])).view(27, -1)
+    sel = g[:, torch.from_numpy(nodes).cuda()].double().cpu().numpy()
+    del buf, g
+    torch.cuda.empty_cache()
+    return (sel / scale[:, None] + w[:, None]).T
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16", "f32"])
+def test_precision_form_512_two_steps_sampled(cm, orc, tgv512, storage):
+    import torch
+    n, rho, u, tau = tgv512
+    L = orc.lattice("D3Q27")
+    e, w = L["e"][:, :3], L["w"]
+    scale = f16_scales(w) if storage == "f16" else np.ones(27)
+    ctx = cm.Context("D3Q27", (n, n, n), storage=storage, tau=tau,
+                     scale=scale if storage == "f16" else None)
+    try:
+        d_rho = torch.from_numpy(rho.reshape(-1)).cuda()
+        d_u = torch.from_numpy(u.reshape(-1)).cuda()
+        ctx.init_fields_device(d_rho, d_u)
+        del d_rho, d_u
+        ctx.step(2)
+        rng = np.random.default_rng(17)
+        nodes = np.concatenate([rng.choice(n ** 3, 40, replace=False),
+                                [0, n - 1, n * n - 1, n ** 3 - n * n, n ** 3 - 1]]).astype(np.int64)
+        got = sampled_state(ctx, storage, nodes, scale, w)
+        g = ctx.reduce()
+    finally:
+        ctx.destroy()
+        torch.cuda.empty_cache()
+
+    def stored(f):   # FP64 populations -> what the storage codec keeps
+        return quantise((f - w) * scale, storage) / scale + w
+
+    cfg = orc.Cfg(lattice="D3Q27", tau=tau)
+    pos = np.stack([nodes % n, (nodes // n) % n, nodes // (n * n)], 1)
+    nb = pos[:, None, :] - e[None, :, :]                                   # [node, j, 3]
+
+    def f0(p):
+        p = p % n
+        return stored(np.stack([orc.equilibrium("D3Q27", rho[z, y, x], u[:, z, y, x], 1.0)
+                                for x, y, z in p.reshape(-1, 3)]))
+
+    pulled = np.stack([f0(nb - e[i][None, None, :])[:, i] for i in range(27)], 1)
+    f1 = stored(orc.collide(cfg, pulled)).reshape(len(nodes), 27, 27)      # [node, j, i]
+    ref = orc.collide(cfg, np.stack([f1[:, i, i] for i in range(27)], 1))
+    if storage != "f32":
+        ref = stored(ref)
+    err = np.abs(got - ref).max()
+    dev = np.abs(ref - w).max()
+    print(f"512^3 {storage} two steps, sampled: max|df| = {err:.3e} (deviation scale {dev:.3e})")
+    assert err <= 2 * TOL[storage] * dev
+    mass0 = rho.sum()
+    assert abs(g["mass"] - mass0) / mass0 < (1e-6 if storage == "f32" else 1e-3)
+    assert g["nonfinite"] == 0
+
+
+def test_thermal_waves_1024_two_steps(cm, orc):
+    n, kx, amp, pr, tau2 = 1024, 4, 0.01, 7.0, 0.6
+    r = cm.lattice_info("D2Q37")["r"]
+    tau = {2: tau2, 3: 0.5 + (tau2 - 0.5) / pr, 4: tau2}
+    rho, u, th = inputs.waves2d(n, n, shear_amp=amp / r, thermal_amp=amp, k=(kx, 0), background=(0.0, 0.1))
+    cfg = orc.Cfg(lattice="D2Q37", tau=tau, thermal=True)
+    S = orc.init_equilibrium(cfg, rho, u, th)
+    w = orc.lattice("D2Q37")["w"][:, None, None]
+    ctx = cm.Context("D2Q37", (n, n), storage="f32", thermal=True, tau=tau)
+    try:
+        ctx.set_populations(S)
+        ctx.step(2)
+        got = ctx.get_populations()
+    finally:
+        ctx.destroy()
+    ref = quantise(S - w, "f32") + w
+    for k in range(2):
+        orc.run(cfg, ref, 1)
+        if k == 0:
+            ref = quantise(ref - w, "f32") + w
+    err = np.abs(got - ref).max()
+    dev = np.abs(ref - w).max()
+    print(f"D2Q37 1024^2 thermal waves, two steps: max|df| = {err:.3e} (deviation scale {dev:.3e})")
+    assert err <= 2 * TOL["f32"] * dev
+
+
+def test_closure_128_sampled(cm, orc):
+    n, u0, re = 128, 0.05, 1.0e5
+    rho, u = inputs.tgv3d(n, u0)
+    t2 = 0.5 + 3.0 * u0 * (n / (2 * math.pi)) / re
+    w = orc.lattice("D3Q27")["w"][:, None, None, None]
+    S = orc.init_equilibrium(orc.Cfg(lattice="D3Q27"), rho, u) * inputs.perturbation((27, n, n, n), 90, 0.02)
+    S = quantise(S - w, "f32") + w
+    P = params(91)
+    sigma = np.random.default_rng(92).uniform(0.005, 0.03, 27).astype(np.float32).astype(np.float64)
+    ctx = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: t2})
+    try:
+        ctx.closure_load(P, sigma)
+        ctx.closure_enable(True)
+        ctx.set_populations(S)
+        ctx.step(1)
+        got = ctx.get_populations().reshape(27, -1)
+    finally:
+        ctx.destroy()
+    rng = np.random.default_rng(93)
+    nodes = np.concatenate([rng.choice(n ** 3, 3000, replace=False), [0, n - 1, n ** 3 - 1]])
+    fin = orc.gather_nodes("D3Q27", S, nodes)
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: t2})
+    ref, om = orc.collide_closure(cfg, fin, P, sigma)
+    plain = orc.collide(orc.Cfg(lattice="D3Q27", tau={2: t2}, tau_hi=1.0), fin)
+    assert om.std() > 0.05
+    controlled = np.abs(ref - plain).max()
+    err = np.abs(got[:, nodes].T - ref).max()
+    print(f"closure 128^3 sampled: max|df| = {err:.3e}, network-controlled part {controlled:.3e}")
+    assert err <= 0.02 * controlled + 2e-6 * np.abs(ref - w[:, 0, 0, 0]).max()

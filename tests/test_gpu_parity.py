@@ -401,8 +401,13 @@ FUSION_SHAPES = [
     (2, 3, 1),       # nx = 1
     (1, 1, 1),       # every neighbour is the node itself
     (12, 17, 70),    # several tiles in x and y, nz not a multiple of the z chunk
-    (40, 24, 128),   # several z chunks
+    (40, 24, 128),   # 240 one-plane z chunks
 ]
+
+
+def test_two_step_launch_ragged_z_chunks(cm, orc):
+    """256 workgroups of 128 x-y tiles in two z chunks of 16 and 15 planes."""
+    test_two_step_launch_equals_single_steps(cm, orc, (31, 128, 512), "f32")
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
@@ -416,7 +421,7 @@ def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
     tau = taus("D3Q27", seed=len(shape) + shape[-1])
     scale = f16_scales(L["w"]) if storage == "f16" else None
     out = {}
-    for fuse in (1, 2):
+    for fuse in (1, 2, 0):
         ctx = cm.Context("D3Q27", shape, storage=storage, tau=tau, scale=scale)
         try:
             ctx.set_step_fusion(fuse)
@@ -427,18 +432,21 @@ def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
             out[fuse] = (a, ctx.get_populations(), ctx.step_count())
         finally:
             ctx.destroy()
-    assert out[1][2] == out[2][2] == 7
-    assert np.array_equal(out[1][0], out[2][0])
-    assert np.array_equal(out[1][1], out[2][1])
+    assert out[1][2] == out[2][2] == out[0][2] == 7
+    for k in (0, 2):
+        assert np.array_equal(out[1][0], out[k][0])
+        assert np.array_equal(out[1][1], out[k][1])
 
 
 @pytest.mark.parametrize("storage", ["f64", "bf16"])
 def test_two_step_launch_options(cm, storage):
     ctx = cm.Context("D3Q27", (4, 4, 4), storage=storage, tau={2: 0.6})
     try:
-        with pytest.raises(cm.CmlbError):
-            ctx.set_step_fusion(3)
-        ctx.set_step_fusion(2)   # not FP32: one step per launch, silently
+        for bad in (3, -1):
+            with pytest.raises(cm.CmlbError):
+                ctx.set_step_fusion(bad)
+        for v in (0, 2):         # not FP32: one step per launch, silently
+            ctx.set_step_fusion(v)
         ctx.init_fields(np.ones((4, 4, 4)), np.zeros((3, 4, 4, 4)))
         ctx.step(3)
         assert ctx.step_count() == 3
@@ -524,6 +532,8 @@ def test_graph_replay_equals_direct_launches(cm, orc, kind, shape, thermal, clos
     tau = taus(kind, 9)
     ctxs = [cm.Context(kind, shape, storage="f32", thermal=thermal, tau=tau) for _ in range(2)]
     try:
+        for c in ctxs:
+            c.set_step_fusion(2)   # two-step launches on D3Q27 without the closure
         ctxs[1].set_graph_steps(8)
         P = 0.3 * np.random.default_rng(4).normal(size=cm.CLOSURE_NPARAM)
         for c in ctxs:
