@@ -32,9 +32,9 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t nchunks) {
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s);
 int launch_step_tp(int lattice, int storage, const StepArgs& a, hipStream_t s);     // step_tp.hip
 int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s);      // step_d37.hip
-// Two steps in one launch (step_tp2.hip): D3Q27 with FP32 storage.
-// Two steps in one launch; -1 if the configuration is not supported or, unless
-// force is set, if two single-step launches are expected to be faster.
+// Two steps in one launch (step_tp2.hip, D3Q27 with FP32 storage); -1 if the
+// configuration is not supported or, unless force is set, if two single-step
+// launches are expected to be faster.
 int launch_step2_tp(int lattice, int storage, const StepArgs& a, bool force, hipStream_t s);
 int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
