@@ -161,9 +161,30 @@ int cmlb_set_step_fusion(cmlb_ctx *ctx, int steps_per_launch);
  * launched directly.  Results are bitwise those of direct launches.  The
  * graph is recaptured after cmlb_set_tau, cmlb_set_step_fusion and
  * cmlb_closure_enable, and whenever the buffer parity differs from the
- * captured one.  Useful where launches are short (small grids).
+ * captured one.  On one MI355X replay is no faster than direct launches
+ * (the device, not the host, sets the pace of short launches); it serves
+ * callers that drive steps from graphs of their own.
  * CMLB_EINVAL for other values. */
 int cmlb_set_graph_steps(cmlb_ctx *ctx, int steps);
+
+/* Most contexts one cmlb_step_batch call can step together. */
+#define CMLB_MAX_BATCH 16
+
+/* Enqueue n steps of each of `count` contexts (1..CMLB_MAX_BATCH, distinct),
+ * one launch per step for all of them: many small lattices fill the GPU
+ * that one alone would leave mostly idle (Sec. III.B: the stability search
+ * runs hundreds of 128^2 lattices).  The contexts must agree in lattice,
+ * storage, collision model, thermal flag, grid, rho0, theta0, storage scales
+ * and device, and have the learned closure off; relaxation times, buffer
+ * parities and streams may differ.  Each context's populations and step
+ * count end exactly as after cmlb_step(ctx, n) with one step per launch
+ * (which gives the same populations as any fusion setting).  Asynchronous:
+ * the launches go on ctxs[0]'s stream after the work already enqueued on
+ * the other contexts' streams, and work enqueued later on any of those
+ * streams runs after them.  If validation fails nothing is enqueued (the
+ * message is on ctxs[0]); CMLB_EINVAL if ctxs or ctxs[0] is NULL or
+ * count < 1. */
+int cmlb_step_batch(cmlb_ctx *const *ctxs, int count, int64_t n);
 
 /* Wait for all work enqueued on the context stream. */
 int cmlb_sync(cmlb_ctx *ctx);

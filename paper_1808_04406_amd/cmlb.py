@@ -21,6 +21,7 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 MODELS = {"cm": 0, "raw_mrt": 1, "reg_bgk": 2}
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
+MAX_BATCH = 16   # CMLB_MAX_BATCH
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", EUNSTABLE: "EUNSTABLE"}
 
 
@@ -82,6 +83,7 @@ def lib():
         L.cmlb_step.argtypes = [vp, c_i64]
         L.cmlb_set_step_fusion.argtypes = [vp, c_int]
         L.cmlb_set_graph_steps.argtypes = [vp, c_int]
+        L.cmlb_step_batch.argtypes = [P(vp), c_int, c_i64]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
         L.cmlb_get_moments_device.argtypes = [vp, vp, vp, vp]
@@ -159,6 +161,18 @@ def _stream_handle(stream):
         raise ValueError("pass a non-default stream (e.g. torch.cuda.Stream()); the default stream "
                          "does not order with the library's own stream")
     return h
+
+
+def step_batch(ctxs, n=1):
+    """cmlb_step_batch: n steps of each context, one launch per step for all of
+    them (at most MAX_BATCH contexts of one configuration)."""
+    ctxs = list(ctxs)
+    if not ctxs:
+        return
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.h for c in ctxs])
+    rc = lib().cmlb_step_batch(arr, len(ctxs), int(n))
+    if rc:
+        raise CmlbError(rc, lib().cmlb_last_error(ctxs[0].h).decode() if ctxs[0].h else "invalid batch")
 
 
 class Context:

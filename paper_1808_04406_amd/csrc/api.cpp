@@ -125,6 +125,9 @@ size_t storage_bytes(int st) { return st == CMLB_F64 ? 8 : st == CMLB_F32 ? 4 : 
 
 }  // namespace
 
+static_assert(CMLB_MAX_BATCH == cmlb::kMaxBatch, "batch size limit");
+static_assert(sizeof(cmlb::BatchArgs) <= 4096, "batch arguments fit the kernel argument segment");
+
 struct cmlb_ctx {
     cmlb_params p{};
     HostLattice L;
@@ -135,6 +138,7 @@ struct cmlb_ctx {
     bool own_stream = false;
     bool initialised = false;
     hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;      // orders batched launches across streams (created on first use)
     double omega[8] = {};
     float s[37] = {}, inv_s[37] = {};
     int64_t steps = 0;
@@ -351,6 +355,7 @@ void cmlb_destroy(cmlb_ctx* c) {
     if (c->cl_partials) (void)hipFree(c->cl_partials);
     if (c->cl_grad) (void)hipFree(c->cl_grad);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->ev) (void)hipEventDestroy(c->ev);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -491,6 +496,77 @@ int cmlb_step(cmlb_ctx* c, int64_t n) {
         n -= reps * c->graph_steps;
     }
     return enqueue_steps(c, n);
+}
+
+int cmlb_step_batch(cmlb_ctx* const* ctxs, int count, int64_t n) {
+    if (!ctxs || count < 1 || !ctxs[0]) return CMLB_EINVAL;
+    cmlb_ctx* c0 = ctxs[0];
+    if (count > CMLB_MAX_BATCH) return fail(c0, CMLB_EINVAL, "more than CMLB_MAX_BATCH contexts in a batch");
+    if (n < 0) return fail(c0, CMLB_EINVAL, "negative step count");
+    const cmlb_params& p0 = c0->p;
+    const int Q = c0->L.Q;
+    for (int k = 0; k < count; ++k) {
+        const cmlb_ctx* c = ctxs[k];
+        if (!c) return fail(c0, CMLB_EINVAL, "NULL context in batch");
+        for (int j = 0; j < k; ++j)
+            if (ctxs[j] == c) return fail(c0, CMLB_EINVAL, "a context appears twice in the batch");
+        if (!c->initialised) return fail(c0, CMLB_ESTATE, "state not initialised");
+        if (c->closure_on) return fail(c0, CMLB_EINVAL, "the learned closure is not batched");
+        const cmlb_params& p = c->p;
+        if (p.lattice != p0.lattice || p.storage != p0.storage || p.model != p0.model || p.thermal != p0.thermal ||
+            p.nx != p0.nx || p.ny != p0.ny || p.nz != p0.nz || p.rho0 != p0.rho0 || p.theta0 != p0.theta0 ||
+            p.device != p0.device)
+            return fail(c0, CMLB_EINVAL, "batched contexts differ in lattice, storage, model, grid, rho0, "
+                                         "theta0 or device");
+        for (int i = 0; i < Q; ++i)
+            if (c->s[i] != c0->s[i]) return fail(c0, CMLB_EINVAL, "batched contexts differ in storage scales");
+    }
+    if (hipSetDevice(p0.device) != hipSuccess) return fail(c0, CMLB_EDEVICE, "hipSetDevice failed");
+    if (n == 0) return CMLB_OK;
+    hipError_t e = hipSuccess;
+    auto event_of = [&](cmlb_ctx* c) {
+        if (!c->ev) e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
+        return e == hipSuccess;
+    };
+    // the launches go on the first context's stream, after the work already
+    // enqueued on the others' streams
+    bool other_streams = false;
+    for (int k = 1; k < count; ++k) {
+        cmlb_ctx* c = ctxs[k];
+        if (c->stream == c0->stream) continue;
+        other_streams = true;
+        if (!event_of(c) || (e = hipEventRecord(c->ev, c->stream)) != hipSuccess ||
+            (e = hipStreamWaitEvent(c0->stream, c->ev, 0)) != hipSuccess)
+            return hip_fail(c0, e, "batch stream ordering");
+    }
+    BatchArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.a = base_args(c0);
+    for (int k = 0; k < count; ++k)
+        for (int m = 0; m < 8; ++m) A.l[k].omega[m] = ctxs[k]->omega[m];
+    for (int64_t t = 0; t < n; ++t) {
+        for (int k = 0; k < count; ++k) {
+            A.l[k].src = ctxs[k]->f[ctxs[k]->cur];
+            A.l[k].dst = ctxs[k]->f[1 - ctxs[k]->cur];
+        }
+        if (launch_step_batch(p0.lattice, p0.storage, p0.model, A, count, c0->stream))
+            return fail(c0, CMLB_EINVAL, "unsupported configuration");
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(c0, e, "batched step kernel launch");
+        for (int k = 0; k < count; ++k) {
+            ctxs[k]->cur = 1 - ctxs[k]->cur;
+            ctxs[k]->steps += 1;
+        }
+    }
+    // later work on the other contexts' streams waits for the batch
+    if (other_streams) {
+        if (!event_of(c0) || (e = hipEventRecord(c0->ev, c0->stream)) != hipSuccess)
+            return hip_fail(c0, e, "batch stream ordering");
+        for (int k = 1; k < count; ++k)
+            if (ctxs[k]->stream != c0->stream && (e = hipStreamWaitEvent(ctxs[k]->stream, c0->ev, 0)) != hipSuccess)
+                return hip_fail(c0, e, "batch stream ordering");
+    }
+    return CMLB_OK;
 }
 
 int cmlb_set_graph_steps(cmlb_ctx* c, int steps) {

@@ -180,6 +180,31 @@ struct StepArgs {
     int thermal;
 };
 
+// Several lattices of one configuration stepped by one launch: blockIdx.y
+// selects the lattice; its buffers and relaxation rates replace those of a.
+constexpr int kMaxBatch = 16;
+
+struct BatchLattice {
+    const void* src;
+    void* dst;
+    double omega[8];
+};
+
+struct BatchArgs {
+    StepArgs a;
+    BatchLattice l[kMaxBatch];
+};
+
+// The step arguments of lattice blockIdx.y of a batch.
+__device__ __forceinline__ StepArgs batch_member(const BatchArgs& A) {
+    StepArgs a = A.a;
+    const BatchLattice& L = A.l[blockIdx.y];
+    a.src = L.src;
+    a.dst = L.dst;
+    for (int n = 0; n < 8; ++n) a.omega[n] = L.omega[n];
+    return a;
+}
+
 struct FieldArgs {
     const double* rho;
     const double* u;      // [D][node], lattice units

@@ -327,6 +327,13 @@ int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStrea
     return -1;
 }
 
+int launch_step_batch(int lattice, int storage, int model, const BatchArgs& A, int count, hipStream_t s) {
+    if (count < 1 || count > kMaxBatch) return -1;
+    if (lattice == kD2Q9 || lattice == kD3Q27) return launch_step_tp_batch(lattice, storage, A, count, s);
+    if (lattice == kD2Q37) return launch_step_d37_batch(storage, model, A, count, s);
+    return -1;
+}
+
 template <int ST>
 static int launch_init_st(int lattice, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
     dim3 grid = flat_grid(a.g.plane), block(256);

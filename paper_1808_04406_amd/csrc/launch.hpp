@@ -32,6 +32,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t nchunks) {
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s);
 int launch_step_tp(int lattice, int storage, const StepArgs& a, hipStream_t s);     // step_tp.hip
 int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s);      // step_d37.hip
+// One step of `count` lattices (A.l[0..count)) in one launch.
+int launch_step_batch(int lattice, int storage, int model, const BatchArgs& A, int count, hipStream_t s);
+int launch_step_tp_batch(int lattice, int storage, const BatchArgs& A, int count, hipStream_t s);
+int launch_step_d37_batch(int storage, int model, const BatchArgs& A, int count, hipStream_t s);
 // Two steps in one launch (step_tp2.hip, D3Q27 with FP32 storage); -1 if the
 // configuration is not supported or, unless force is set, if two single-step
 // launches are expected to be faster.

@@ -13,7 +13,7 @@ namespace cmlb {
 // Hot path: D2Q37 stream + collide (order-4 Hermite truncation)
 // ---------------------------------------------------------------------------
 template <int ST, int MODEL>
-__global__ __launch_bounds__(512) void k_step_d37(StepArgs a) {
+__device__ __forceinline__ void step_d37_body(const StepArgs& a) {
     using S = Store<ST>;
     using R = typename S::R;
     using T = typename S::T;
@@ -55,6 +55,17 @@ __global__ __launch_bounds__(512) void k_step_d37(StepArgs a) {
     });
 }
 
+template <int ST, int MODEL>
+__global__ __launch_bounds__(512) void k_step_d37(StepArgs a) {
+    step_d37_body<ST, MODEL>(a);
+}
+
+// One step of each lattice of a batch (blockIdx.y = lattice).
+template <int ST, int MODEL>
+__global__ __launch_bounds__(512) void k_step_d37_batch(BatchArgs A) {
+    step_d37_body<ST, MODEL>(batch_member(A));
+}
+
 // ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
@@ -63,6 +74,25 @@ static void launch_d37(StepArgs a, hipStream_t s) {
     dim3 grid, block;
     step_shape(a, grid, block, a.g.ny, 512);   // FP64 needs up to 142 VGPRs: at most 512 threads
     hipLaunchKernelGGL((k_step_d37<ST, MODEL>), grid, block, 0, s, a);
+}
+
+template <int ST, int MODEL>
+static void launch_d37_batch(BatchArgs A, int count, hipStream_t s) {
+    dim3 grid, block;
+    step_shape(A.a, grid, block, A.a.g.ny, 512);
+    grid.y = count;
+    hipLaunchKernelGGL((k_step_d37_batch<ST, MODEL>), grid, block, 0, s, A);
+}
+
+int launch_step_d37_batch(int storage, int model, const BatchArgs& A, int count, hipStream_t s) {
+    const bool raw = (model == kRawMRT);
+    switch (storage) {
+        case kF64: raw ? launch_d37_batch<kF64, kRawMRT>(A, count, s) : launch_d37_batch<kF64, kCM>(A, count, s); return 0;
+        case kF32: raw ? launch_d37_batch<kF32, kRawMRT>(A, count, s) : launch_d37_batch<kF32, kCM>(A, count, s); return 0;
+        case kBF16: raw ? launch_d37_batch<kBF16, kRawMRT>(A, count, s) : launch_d37_batch<kBF16, kCM>(A, count, s); return 0;
+        case kF16: raw ? launch_d37_batch<kF16, kRawMRT>(A, count, s) : launch_d37_batch<kF16, kCM>(A, count, s); return 0;
+    }
+    return -1;
 }
 
 int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s) {

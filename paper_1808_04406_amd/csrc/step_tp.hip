@@ -16,7 +16,7 @@ namespace cmlb {
 // Hot path: D2Q9 / D3Q27 stream + collide
 // ---------------------------------------------------------------------------
 template <int D, int ST>
-__global__ __launch_bounds__(1024) void k_step_tp(StepArgs a) {
+__device__ __forceinline__ void step_tp_body(const StepArgs& a) {
     using S = Store<ST>;
     using R = typename S::R;
     using T = typename S::T;
@@ -61,6 +61,17 @@ __global__ __launch_bounds__(1024) void k_step_tp(StepArgs a) {
     });
 }
 
+template <int D, int ST>
+__global__ __launch_bounds__(1024) void k_step_tp(StepArgs a) {
+    step_tp_body<D, ST>(a);
+}
+
+// One step of each lattice of a batch (blockIdx.y = lattice).
+template <int D, int ST>
+__global__ __launch_bounds__(1024) void k_step_tp_batch(BatchArgs A) {
+    step_tp_body<D, ST>(batch_member(A));
+}
+
 // ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
@@ -69,6 +80,29 @@ static void launch_tp(StepArgs a, hipStream_t s) {
     dim3 grid, block;
     step_shape(a, grid, block, a.g.ny * a.g.nz, 1024);
     hipLaunchKernelGGL((k_step_tp<D, ST>), grid, block, 0, s, a);
+}
+
+template <int D, int ST>
+static void launch_tp_batch(BatchArgs A, int count, hipStream_t s) {
+    dim3 grid, block;
+    step_shape(A.a, grid, block, A.a.g.ny * A.a.g.nz, 1024);
+    grid.y = count;
+    hipLaunchKernelGGL((k_step_tp_batch<D, ST>), grid, block, 0, s, A);
+}
+
+int launch_step_tp_batch(int lattice, int storage, const BatchArgs& A, int count, hipStream_t s) {
+    const int D = lattice == kD2Q9 ? 2 : 3;
+#define CMLB_TPB(DD)                                                         \
+    switch (storage) {                                                       \
+        case kF64: launch_tp_batch<DD, kF64>(A, count, s); return 0;         \
+        case kF32: launch_tp_batch<DD, kF32>(A, count, s); return 0;         \
+        case kBF16: launch_tp_batch<DD, kBF16>(A, count, s); return 0;       \
+        case kF16: launch_tp_batch<DD, kF16>(A, count, s); return 0;         \
+    }                                                                        \
+    return -1;
+    if (D == 2) { CMLB_TPB(2) }
+    CMLB_TPB(3)
+#undef CMLB_TPB
 }
 
 int launch_step_tp(int lattice, int storage, const StepArgs& a, hipStream_t s) {

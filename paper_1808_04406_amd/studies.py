@@ -240,34 +240,46 @@ def modes(stream=None):
     return res
 
 
-def max_stable(stable, lo, hi, tol):
-    """Bisection for the largest x in [lo, hi] with stable(x) true, assuming
-    a single stable-to-unstable transition.  Returns (x_max, calls), where
-    x_max is the largest stable point evaluated (lo if even lo is unstable,
-    then flagged by calls[0][1] False) and calls lists (x, stable) in order."""
+def _bisection(lo, hi, tol):
+    """Bisection for the largest x in [lo, hi] that is stable, assuming a
+    single stable-to-unstable transition, as a generator: it yields the next
+    x to evaluate and is sent whether x was stable.  Its return value is
+    (x_max, calls), where x_max is the largest stable point evaluated (lo if
+    even lo is unstable, then flagged by calls[0][1] False) and calls lists
+    (x, stable) in order."""
     calls = []
-
-    def ev(x):
-        ok = bool(stable(x))
-        calls.append((x, ok))
-        return ok
-
-    if not ev(lo):
+    ok = yield lo
+    calls.append((lo, ok))
+    if not ok:
         return lo, calls
-    if ev(hi):
+    ok = yield hi
+    calls.append((hi, ok))
+    if ok:
         return hi, calls
     while hi - lo > tol:
         mid = 0.5 * (lo + hi)
-        if ev(mid):
+        ok = yield mid
+        calls.append((mid, ok))
+        if ok:
             lo = mid
         else:
             hi = mid
     return lo, calls
 
 
-def dsl_run(ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0, checks=32,
-            ke_bound=2.0, history=False, stream=None):
-    """One double-shear-layer run (Sec. III.B) on D2Q37.
+def max_stable(stable, lo, hi, tol):
+    """The bisection above with stable(x) evaluated one point at a time."""
+    g = _bisection(lo, hi, tol)
+    x = next(g)
+    while True:
+        try:
+            x = g.send(bool(stable(x)))
+        except StopIteration as done:
+            return done.value
+
+
+class _DslRun:
+    """One double-shear-layer run (Sec. III.B) on D2Q37, advanced by its caller.
 
     Units as in the paper: velocities in units of the isothermal sound speed
     (Ma = u0), lengths in lattice spacings c, so u0 = Ma / r cells per step,
@@ -275,33 +287,91 @@ def dsl_run(ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32
     tau_4 = tau_2 unless given.  The run goes to t = t_end t_c with
     t_c = L / u0 steps and is stable if every check finds all populations
     finite and <u^2>/u0^2 <= ke_bound."""
-    r = cmlb.lattice_info("D2Q37")["r"]
-    u_lat = ma / r
-    nu = ma * r * n / re
-    tau2 = 0.5 + nu
-    tau = {2: tau2, 3: 0.5 + nu / pr, 4: tau2 if tau4 is None else tau4}
-    ctx = cmlb.Context("D2Q37", (n, n), storage=storage, thermal=thermal, model=model, tau=tau, stream=stream)
-    rho, u, th = inputs.double_shear_layer(n, u_lat)
-    ctx.init_fields(rho, u, th)
-    steps = int(math.ceil(t_end * n / u_lat))
-    marks = sorted(set(int(round(steps * (j + 1) / checks)) for j in range(checks)))
-    done, ok, hist = 0, True, [(0, 1.0)]
-    g0 = ctx.reduce(allow_unstable=True)
-    e0 = g0["ke"]
-    for m in marks:
-        ctx.step(m - done)
-        done = m
-        g = ctx.reduce(allow_unstable=True)
-        ratio = g["ke"] / e0 if np.isfinite(g["ke"]) else float("inf")
-        hist.append((done, ratio))
-        if g["nonfinite"] > 0 or not ratio <= ke_bound:
-            ok = False
-            break
-    ctx.destroy()
-    out = {"stable": ok, "steps": steps, "steps_run": done, "tau": tau}
-    if history:
-        out["history"] = hist
-    return out
+
+    def __init__(self, ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0,
+                 checks=32, ke_bound=2.0, stream=None):
+        r = cmlb.lattice_info("D2Q37")["r"]
+        u_lat = ma / r
+        nu = ma * r * n / re
+        tau2 = 0.5 + nu
+        self.tau = {2: tau2, 3: 0.5 + nu / pr, 4: tau2 if tau4 is None else tau4}
+        self.ctx = cmlb.Context("D2Q37", (n, n), storage=storage, thermal=thermal, model=model, tau=self.tau,
+                                stream=stream)
+        rho, u, th = inputs.double_shear_layer(n, u_lat)
+        self.ctx.init_fields(rho, u, th)
+        self.steps = int(math.ceil(t_end * n / u_lat))
+        self.marks = sorted(set(int(round(self.steps * (j + 1) / checks)) for j in range(checks)))
+        self.mi, self.done, self.ok, self.finished = 0, 0, True, False
+        self.hist = [(0, 1.0)]
+        self.ke_bound = ke_bound
+        self.e0 = self.ctx.reduce(allow_unstable=True)["ke"]
+
+    def to_next(self):
+        return self.marks[self.mi] - self.done
+
+    def advanced(self, k):
+        """Record k steps made by the caller; check at a mark."""
+        self.done += k
+        if self.done < self.marks[self.mi]:
+            return
+        g = self.ctx.reduce(allow_unstable=True)
+        ratio = g["ke"] / self.e0 if np.isfinite(g["ke"]) else float("inf")
+        self.hist.append((self.done, ratio))
+        self.mi += 1
+        if g["nonfinite"] > 0 or not ratio <= self.ke_bound:
+            self.ok = False
+        if not self.ok or self.mi == len(self.marks):
+            self.finished = True
+            self.ctx.destroy()
+
+    def result(self, history=False):
+        out = {"stable": self.ok, "steps": self.steps, "steps_run": self.done, "tau": self.tau}
+        if history:
+            out["history"] = self.hist
+        return out
+
+
+def dsl_run(ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0, checks=32,
+            ke_bound=2.0, history=False, stream=None):
+    """One double-shear-layer run (Sec. III.B), stepped on its own."""
+    run = _DslRun(ma, re, pr, model, thermal, n, tau4, storage, t_end, checks, ke_bound, stream)
+    while not run.finished:
+        k = run.to_next()
+        run.ctx.step(k)
+        run.advanced(k)
+    return run.result(history)
+
+
+def max_stable_batched(cases, lo, hi, tol, model="cm", thermal=True, n=128, stream=None):
+    """max_stable for many (Re, Pr) cases of one model at once: every case
+    runs its own bisection, and the runs in flight advance together, up to
+    cmlb.MAX_BATCH lattices per launch (cmlb_step_batch).  Each run makes the
+    same steps and checks as dsl_run, and batched steps are bitwise those of
+    single ones, so the results equal the sequential search's.  Returns one
+    (x_max, calls) per case."""
+    gens = [_bisection(lo, hi, tol) for _ in cases]
+    results = [None] * len(cases)
+    active = {}
+    for i, (re, pr) in enumerate(cases):
+        active[i] = _DslRun(next(gens[i]), re, pr, model, thermal, n, stream=stream)
+    while active:
+        items = sorted(active.items())
+        k = min(r.to_next() for _, r in items)
+        for j in range(0, len(items), cmlb.MAX_BATCH):
+            cmlb.step_batch([r.ctx for _, r in items[j:j + cmlb.MAX_BATCH]], k)
+        for i, r in items:
+            r.advanced(k)
+            if not r.finished:
+                continue
+            try:
+                x = gens[i].send(r.ok)
+            except StopIteration as done:
+                results[i] = done.value
+                del active[i]
+                continue
+            re, pr = cases[i]
+            active[i] = _DslRun(x, re, pr, model, thermal, n, stream=stream)
+    return results
 
 
 def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0), tol=0.005, stream=None):
@@ -313,15 +383,19 @@ def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0)
                    for ma in (0.2, 0.25, 0.2625, 0.2688, 0.275)}
     for ma, o in out["fig6"].items():
         print(f"Fig. 6 Ma={ma}: stable={o['stable']}, steps {o['steps_run']}/{o['steps']}", flush=True)
+    t_fig6 = time.perf_counter() - t0
     for label, model, thermal in (("isothermal raw MRT", "raw_mrt", False), ("isothermal CM-MRT", "cm", False),
                                   ("thermal CM-MRT", "cm", True)):
-        for pr in prs:
-            for re in res_:
-                m, calls = max_stable(lambda ma: dsl_run(ma, re, pr, model=model, thermal=thermal,
-                                                         stream=stream)["stable"], 0.05, 1.2, tol)
-                out["boundaries"].append({"model": label, "pr": pr, "re": re, "ma_max": m, "calls": calls})
-                print(f"{label} Pr={pr} Re={re:.0e}: Ma_max = {m:.4f} ({len(calls)} runs)", flush=True)
+        cases = [(re, pr) for pr in prs for re in res_]
+        t1 = time.perf_counter()
+        found = max_stable_batched(cases, 0.05, 1.2, tol, model=model, thermal=thermal, n=n, stream=stream)
+        print(f"{label}: {len(cases)} searches, {sum(len(c) for _, c in found)} runs in "
+              f"{time.perf_counter() - t1:.2f} s (batched)", flush=True)
+        for (re, pr), (m, calls) in zip(cases, found):
+            out["boundaries"].append({"model": label, "pr": pr, "re": re, "ma_max": m, "calls": calls})
+            print(f"{label} Pr={pr} Re={re:.0e}: Ma_max = {m:.4f} ({len(calls)} runs)", flush=True)
     out["wall_s"] = time.perf_counter() - t0
+    out["wall_fig6_s"] = t_fig6
     return out
 
 

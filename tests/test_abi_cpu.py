@@ -60,6 +60,9 @@ def test_null_context_is_rejected(cm):
     assert L.cmlb_set_step_fusion(None, 2) == cm.EINVAL
     assert L.cmlb_set_step_count(None, 3) == cm.EINVAL
     assert L.cmlb_set_graph_steps(None, 64) == cm.EINVAL
+    assert L.cmlb_step_batch(None, 1, 1) == cm.EINVAL
+    assert L.cmlb_step_batch((ctypes.c_void_p * 1)(None), 1, 1) == cm.EINVAL
+    assert L.cmlb_step_batch((ctypes.c_void_p * 1)(None), 0, 1) == cm.EINVAL
     assert L.cmlb_sync(None) == cm.EINVAL
     assert L.cmlb_step_count(None) == -1
     L.cmlb_destroy(None)

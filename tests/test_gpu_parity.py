@@ -569,3 +569,69 @@ def test_graph_steps_validation(cm):
         ctx.set_graph_steps(4)
     finally:
         ctx.destroy()
+
+
+BATCH_CASES = [
+    ("D2Q37", (24, 40), "f32", "cm", True),
+    ("D2Q37", (13, 41), "f32", "raw_mrt", False),
+    ("D2Q37", (16, 16), "f64", "cm", True),
+    ("D3Q27", (6, 10, 70), "f32", "cm", False),
+    ("D3Q27", (5, 7, 37), "bf16", "cm", False),
+    ("D2Q9", (19, 70), "f32", "cm", False),
+]
+
+
+@pytest.mark.parametrize("kind,shape,storage,model,thermal", BATCH_CASES)
+def test_step_batch_equals_individual(cm, orc, kind, shape, storage, model, thermal):
+    """Several lattices with different relaxation times and buffer parities
+    stepped in one launch per step end bitwise where cmlb_step leaves them."""
+    count = 5
+    states = [random_state(orc, kind, shape, seed=400 + k, thermal=thermal) for k in range(count)]
+    taus_k = [taus(kind, seed=410 + k) for k in range(count)]
+    mk = lambda k: cm.Context(kind, shape, storage=storage, model=model, thermal=thermal, tau=taus_k[k])
+    solo, batch = [mk(k) for k in range(count)], [mk(k) for k in range(count)]
+    try:
+        for k in range(count):
+            for c in (solo[k], batch[k]):
+                c.set_populations(states[k])
+                c.step(k % 2)          # different buffer parities
+        for n in (7, 4):
+            for c in solo:
+                c.step(n)
+            cm.step_batch(batch, n)
+            for a, b in zip(solo, batch):
+                assert a.step_count() == b.step_count()
+                assert np.array_equal(a.get_populations(), b.get_populations())
+    finally:
+        for c in solo + batch:
+            c.destroy()
+
+
+def test_step_batch_validation(cm):
+    mk = lambda shape=(4, 4, 4), **kw: cm.Context("D3Q27", shape, storage=kw.pop("storage", "f32"), tau={2: 0.6}, **kw)
+    a, b, c, d = mk(), mk(), mk((4, 4, 5)), mk(storage="f64")
+    try:
+        for x in (a, b, c, d):
+            x.init_fields(np.ones(x.shape), np.zeros((3,) + x.shape))
+        for bad in ([a, c], [a, d], [a, a]):
+            with pytest.raises(cm.CmlbError):
+                cm.step_batch(bad, 1)
+        many = [mk() for _ in range(cm.MAX_BATCH + 1)]
+        try:
+            for x in many:
+                x.init_fields(np.ones(x.shape), np.zeros((3,) + x.shape))
+            with pytest.raises(cm.CmlbError):
+                cm.step_batch(many, 1)
+            cm.step_batch(many[:cm.MAX_BATCH], 2)
+            assert all(x.step_count() == 2 for x in many[:cm.MAX_BATCH])
+        finally:
+            for x in many:
+                x.destroy()
+        a.closure_load(np.zeros(cm.CLOSURE_NPARAM), np.ones(27))
+        a.closure_enable(True)
+        with pytest.raises(cm.CmlbError):
+            cm.step_batch([a, b], 1)
+        assert a.step_count() == b.step_count() == 0   # nothing ran
+    finally:
+        for x in (a, b, c, d):
+            x.destroy()

@@ -166,6 +166,19 @@ def test_dsl_stability_classification(cm):
     assert not wild["stable"] and wild["steps_run"] < wild["steps"]
 
 
+@pytest.mark.parametrize("model,thermal", [("cm", True), ("raw_mrt", False)])
+def test_batched_search_equals_sequential(cm, model, thermal):
+    """The stability search run in lockstep batches (17 cases: one full
+    batch of 16 and one more) finds exactly the sequential search's points."""
+    from paper_1808_04406_amd import studies
+    cases = [(re, pr) for pr in (0.1, 1.0, 10.0) for re in (1e3, 1e4, 1e5, 1e6, 1e7, 1e8)][:17]
+    got = studies.max_stable_batched(cases, 0.05, 1.2, 0.04, model=model, thermal=thermal, n=32)
+    for (re, pr), (m, calls) in zip(cases, got):
+        ref = studies.max_stable(lambda ma: studies.dsl_run(ma, re, pr, model=model, thermal=thermal,
+                                                            n=32)["stable"], 0.05, 1.2, 0.04)
+        assert (m, calls) == ref, (re, pr)
+
+
 def test_galilean_tgv_small(cm):
     """D3Q27 Taylor-Green vortex with a background velocity along x, shifted
     back by U t, against the run at rest (32^3, Re = 100, 200 steps).  The
