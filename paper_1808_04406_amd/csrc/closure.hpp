@@ -63,9 +63,26 @@ __device__ __forceinline__ float normal_cdf_f(float a, float& e) {
     const float q = 0.5f * poly * e;   // Phi(-|a|)
     return a >= 0.0f ? 1.0f - q : q;
 }
+// GELU(a) = a Phi(a) = max(a, 0) - |a| Phi(-|a|), with Phi(-y) from the same
+// formula 7.1.26 (halved coefficients, exp(-a^2 / 2) as a base-2 exponential)
+// and no branch on the sign.  The factor y t = y / (1 + p y) is formed as
+// (1 - t) / p, which stays finite for infinite inputs (GELU(+inf) = +inf,
+// GELU(-inf) = 0); its cancellation for small y costs at most ~1e-7 in
+// absolute terms, far below the BF16 rounding of the activations.
 __device__ __forceinline__ float gelu_f(float a) {
-    float e;
-    return a * normal_cdf_f(a, e);
+    constexpr float p = 0.3275911f * 0.70710678118654752f;   // p / sqrt(2)
+    constexpr float inv_p = 1.0f / p;
+    constexpr float h1 = 0.5f * 0.254829592f, h2 = 0.5f * -0.284496736f, h3 = 0.5f * 1.421413741f,
+                    h4 = 0.5f * -1.453152027f, h5 = 0.5f * 1.061405429f;
+    constexpr float c = -0.72134752044448170f;                // -log2(e) / 2
+    const float t = recip<float>(fmaf(p, fabsf(a), 1.0f));
+    float poly = fmaf(t, h5, h4);
+    poly = fmaf(t, poly, h3);
+    poly = fmaf(t, poly, h2);
+    poly = fmaf(t, poly, h1);
+    const float yt = fmaf(-t, inv_p, inv_p);
+    const float e = __builtin_amdgcn_exp2f(a * a * c);
+    return fmaf(-yt * e, poly, fmaxf(a, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad_f(float a) {
     float e;
@@ -103,20 +120,15 @@ __device__ __forceinline__ void mlp_forward_wave(const ClosureNet* __restrict__ 
     // layer 1
     {
         const bf16x8 wa0 = net->w1[0][lane], wa1 = net->w1[1][lane];
-        float bias[2][4];
+        f32x4 bias[2];   // the accumulator input: W x + b in one instruction
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) bias[mt][j] = net->b1[16 * mt + 4 * g + j];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb[nt], zero, 0, 0, 0);
-            f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb[nt], zero, 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                d0[j] += bias[0][j];
-                d1[j] += bias[1][j];
-            }
+            f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb[nt], bias[0], 0, 0, 0);
+            f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb[nt], bias[1], 0, 0, 0);
             if constexpr (KEEP) {
                 tr->a1[0][nt] = d0;
                 tr->a1[1][nt] = d1;
@@ -131,20 +143,15 @@ __device__ __forceinline__ void mlp_forward_wave(const ClosureNet* __restrict__ 
     // layer 2
     {
         const bf16x8 wa0 = net->w2[0][lane], wa1 = net->w2[1][lane];
-        float bias[2][4];
+        f32x4 bias[2];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) bias[mt][j] = net->b2[16 * mt + 4 * g + j];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, hb[nt], zero, 0, 0, 0);
-            f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, hb[nt], zero, 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                d0[j] += bias[0][j];
-                d1[j] += bias[1][j];
-            }
+            f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, hb[nt], bias[0], 0, 0, 0);
+            f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, hb[nt], bias[1], 0, 0, 0);
             if constexpr (KEEP) {
                 tr->a2[0][nt] = d0;
                 tr->a2[1][nt] = d1;
