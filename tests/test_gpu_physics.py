@@ -211,3 +211,39 @@ def test_tgv_energy_balance(cm):
     print("integrated balance error", r["integrated_balance_rel_err"], "pointwise max", r["max_abs_balance_rel_err"])
     assert abs(r["integrated_balance_rel_err"]) < 0.02
     assert r["ke"][-1] < r["ke"][0]
+
+
+def test_tgv2d_d2q9_fp64_against_oracle(cm, orc):
+    """The D2Q9 workload in full: 64^2 Taylor-Green vortex, u0 = 0.05,
+    tau = 0.8, higher orders at rate 1, FP64, 1000 steps.  The GPU run equals
+    the FP64 oracle's to max|du| <= 1e-12 every 100 steps, and its velocity
+    amplitude decays as exp(-2 nu k^2 t), nu = (tau - 1/2)/3, within 1 %."""
+    n, u0, tau = 64, 0.05, 0.8
+    tau_all = {2: tau, 3: 1.0, 4: 1.0}
+    cfg = orc.Cfg(lattice="D2Q9", tau={2: tau}, tau_hi=1.0)
+    rho, u = inputs.tgv2d(n, n, u0)
+    S = orc.init_equilibrium(cfg, rho, u)
+    ctx = cm.Context("D2Q9", (n, n), storage="f64", tau=tau_all)
+    x, y = inputs.grid((n, n))
+    k = 2 * np.pi / n
+    basis = np.sin(k * x) * np.cos(k * y)
+    ts, amps = [], []
+    try:
+        ctx.set_populations(S)
+        for t in range(0, 1001, 100):
+            if t:
+                ctx.step(100)
+                orc.run(cfg, S, 100, threads=4)
+            g_rho, g_u, _ = ctx.get_moments()
+            o_rho, o_u, _ = orc.moments("D2Q9", S)
+            du = np.abs(g_u - o_u).max()
+            assert du <= 1e-12, (t, du)
+            assert np.abs(g_rho - o_rho).max() <= 1e-12
+            ts.append(t)
+            amps.append(np.sum(g_u[0] * basis) / np.sum(basis * basis))
+    finally:
+        ctx.destroy()
+    rate = -np.polyfit(ts[1:], np.log(amps[1:]), 1)[0]
+    nu = (tau - 0.5) / 3.0
+    print(f"D2Q9 64^2 FP64: decay rate {rate:.6e} vs 2 nu k^2 = {2 * nu * k * k:.6e}")
+    assert rate == pytest.approx(2 * nu * k * k, rel=0.01)
