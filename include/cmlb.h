@@ -71,13 +71,18 @@ typedef struct cmlb_params {
     int32_t storage;   /* CMLB_F64, CMLB_F32, CMLB_BF16, CMLB_F16 */
     int32_t model;     /* CMLB_MODEL_* */
     int32_t thermal;   /* 1: theta follows from f (D2Q37 only); 0: theta frozen at theta0 */
-    int64_t nx, ny, nz;/* periodic grid; nz must be 1 for 2D lattices; D2Q37
-                          needs nx, ny >= 3 (its velocities reach 3 cells) */
-    double rho0;       /* reference density of the deviation storage (>0) */
-    double theta0;     /* frozen temperature of isothermal runs (>0) */
+    int64_t nx, ny, nz;/* periodic grid, each 1..2^20; nz must be 1 for 2D
+                          lattices; D2Q37 needs nx, ny >= 3 (its velocities
+                          reach 3 cells); nx*ny*nz < 2^32 and
+                          Q*nx*ny*nz < 2^35 */
+    double rho0;       /* reference density of the deviation storage (>0, finite) */
+    double theta0;     /* frozen temperature of isothermal runs (>0, finite) */
     double tau[8];     /* tau[n]: relaxation time of central-moment order n
-                          (n >= 2; entries 0 and 1 ignored; 0 means 1.0) */
-    double scale[37];  /* storage scale s_i per population; 0 means automatic */
+                          (n >= 2; entries 0 and 1 ignored; 0 means 1.0,
+                          otherwise > 0 and finite) */
+    double scale[37];  /* storage scale s_i per population (entries beyond Q
+                          ignored); 0 means automatic, otherwise > 0 and
+                          finite */
     int32_t device;    /* HIP device ordinal */
     int32_t reserved;  /* must be 0 */
     void *hip_stream;  /* hipStream_t for all work, or NULL for a library stream */
@@ -106,7 +111,9 @@ int cmlb_lattice_info(int lattice, int *D, int *Q, int *e, double *w, double *r)
 /* Create a context: validates p, allocates two population buffers of
  * Q * nx*ny*nz elements of the storage type on p->device.  The state is
  * undefined until cmlb_init_fields or cmlb_set_populations.  On failure
- * *out is NULL and cmlb_create_error() describes the reason. */
+ * *out is NULL and cmlb_create_error() describes the reason: CMLB_EINVAL
+ * for parameters outside the ranges documented in cmlb_params (checked
+ * before any device call), CMLB_EDEVICE or CMLB_ENOMEM from the device. */
 int cmlb_create(const cmlb_params *p, cmlb_ctx **out);
 
 /* As cmlb_create, but the population buffers f_a and f_b are device memory

@@ -135,3 +135,100 @@ def test_checkpoint_header_errors(tmp_path):
     old.write_bytes(checkpoint.MAGIC + struct.pack("<IQ", 99, len(hb)) + hb)
     with pytest.raises(ValueError):
         checkpoint.read_header(str(old))
+
+
+# ---------------------------------------------------------------------------
+# cmlb_create parameter validation against the ranges documented in cmlb.h
+# ---------------------------------------------------------------------------
+_Q_OF = {0: 9, 1: 27, 2: 37}
+
+
+def _documented_valid(p):
+    """The parameter ranges of cmlb_params as the header states them."""
+    lat, sto, mod, th = p["lattice"], p["storage"], p["model"], p["thermal"]
+    if lat not in _Q_OF or sto not in (0, 1, 2, 3) or mod not in (0, 1, 2):
+        return False
+    if (mod != 0 or th != 0) and lat != 2:          # raw MRT, regularised BGK, thermal: D2Q37 only
+        return False
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    if min(nx, ny, nz) < 1 or max(nx, ny, nz) > 2 ** 20:
+        return False
+    if lat != 1 and nz != 1:
+        return False
+    if lat == 2 and (nx < 3 or ny < 3):
+        return False
+    n = nx * ny * nz
+    if n >= 2 ** 32 or n * _Q_OF[lat] >= 2 ** 35:
+        return False
+    if not all(v > 0 and math.isfinite(v) for v in (p["rho0"], p["theta0"])):
+        return False
+    if not all(t == 0 or (t > 0 and math.isfinite(t)) for t in p["tau"][2:]):
+        return False
+    if not all(s == 0 or (s > 0 and math.isfinite(s)) for s in p["scale"][:_Q_OF[lat]]):
+        return False
+    return p["reserved"] == 0
+
+
+def _param_blocks():
+    """Valid parameter blocks with zero, one or two fields set to edge values."""
+    from hypothesis import strategies as st
+    nan, inf = float("nan"), float("inf")
+
+    @st.composite
+    def block(draw):
+        lat = draw(st.integers(0, 2))
+        p = {"lattice": lat, "storage": draw(st.integers(0, 3)),
+             "model": draw(st.integers(0, 2)) if lat == 2 else 0,
+             "thermal": draw(st.integers(0, 1)) if lat == 2 else 0,
+             "nx": draw(st.sampled_from([3, 8, 64, 1000])), "ny": draw(st.sampled_from([3, 8, 64])),
+             "nz": draw(st.sampled_from([1, 8, 64])) if lat == 1 else 1,
+             "rho0": draw(st.sampled_from([1.0, 0.7])), "theta0": draw(st.sampled_from([1.0, 1.2])),
+             "tau": [0.0, 0.0] + draw(st.lists(st.sampled_from([0.0, 0.6, 1.3]), min_size=6, max_size=6)),
+             "scale": draw(st.lists(st.sampled_from([0.0, 0.0, 0.0, 2.0, 0.5]), min_size=37, max_size=37)),
+             "reserved": 0}
+        edits = {
+            "lattice": [-1, 3], "storage": [-1, 4], "model": [-1, 1, 2, 3], "thermal": [1, 2],
+            "nx": [-1, 0, 1, 2, 2 ** 20, 2 ** 20 + 1, 2 ** 31], "ny": [0, 1, 2, 2 ** 20 + 1, 2 ** 31],
+            "nz": [0, 2, 2 ** 20, 2 ** 20 + 1],
+            "rho0": [0.0, -1.0, nan, inf], "theta0": [0.0, -2.0, nan, inf], "reserved": [1, -1],
+            "tau": [-0.5, nan, inf, 0.0], "scale": [-1.0, nan, inf, 0.0],
+        }
+        for _ in range(draw(st.integers(0, 2))):
+            k = draw(st.sampled_from(sorted(edits)))
+            v = draw(st.sampled_from(edits[k]))
+            if k in ("tau", "scale"):
+                p[k] = list(p[k])
+                p[k][draw(st.integers(0, len(p[k]) - 1))] = v
+            else:
+                p[k] = v
+        return p
+
+    return block()
+
+
+def test_create_validation_matches_documented_ranges(cm):
+    from hypothesis import given, settings
+    params = _param_blocks()
+    L = cm.lib()
+
+    @settings(max_examples=2000, deadline=None, derandomize=True)
+    @given(params)
+    def check(p):
+        c = cm.Params()
+        for k in ("lattice", "storage", "model", "thermal", "nx", "ny", "nz", "rho0", "theta0", "reserved"):
+            setattr(c, k, p[k])
+        c.tau[:] = p["tau"]
+        c.scale[:] = p["scale"]
+        h = ctypes.c_void_p()
+        rc = L.cmlb_create(ctypes.byref(c), ctypes.byref(h))
+        if _documented_valid(p):
+            assert rc != cm.EINVAL, L.cmlb_create_error().decode()
+            if rc == cm.OK:     # on a machine with a device
+                L.cmlb_destroy(h)
+            else:
+                assert not h.value
+        else:
+            assert rc == cm.EINVAL and not h.value
+            assert L.cmlb_create_error().decode()
+
+    check()
