@@ -121,9 +121,32 @@ def cpu_baseline(tau, target_s=12.0):
     k1 = max(1, min(10, int(3.0 / max(one * threads, 1e-3))))
     oracle.run(cfg, S, k1, threads=1)
     one_core = n ** 3 * k1 / (time.perf_counter() - t0) / 1e6
+    o_rho, o_u, _ = oracle.moments("D3Q27", S)
+    ref = {"n": n, "steps": 1 + steps + k1, "rho0": rho, "u0": u, "rho": o_rho, "u": o_u}
     return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"D3Q27 TGV 64^3 (same u0, tau), {steps} steps after 1 warm-up step, FP64, "
-                      f"{dt:.1f} s", "one_core_MLUPS": round(one_core, 3), "cpu_model": _cpu_model()}
+                      f"{dt:.1f} s", "one_core_MLUPS": round(one_core, 3), "cpu_model": _cpu_model()}, ref
+
+
+def error_vs_oracle(cmlb, tau, ref):
+    """The benchmarked path (FP32 storage, two steps per launch) on the CPU
+    baseline's 64^3 sample, for as many steps as the oracle took there,
+    against the oracle's final moments."""
+    import numpy as np
+    n, steps = ref["n"], ref["steps"]
+    ctx = cmlb.Context("D3Q27", (n, n, n), storage="f32", tau=rates(tau))
+    try:
+        ctx.set_step_fusion(2)
+        ctx.init_fields(ref["rho0"], ref["u0"])
+        ctx.step(steps)
+        g_rho, g_u, _ = ctx.get_moments()
+    finally:
+        ctx.destroy()
+    return {"max_abs_du_over_u0": float(np.abs(g_u - ref["u"]).max() / U0),
+            "max_abs_drho": float(np.abs(g_rho - ref["rho"]).max()),
+            "steps": steps,
+            "sample": f"D3Q27 TGV {n}^3 (same u0 and rates), FP32 storage, two steps per launch, {steps} steps, "
+                      "against the FP64 oracle run of the CPU baseline"}
 
 
 def _cpu_model():
@@ -179,7 +202,8 @@ def main():
     with torch.cuda.stream(stream):
         out = run(torch, cmlb, inputs, stream, args)
     if not args.no_cpu_baseline and args.workload == "tgv256_f32":
-        out["cpu_baseline"] = cpu_baseline(out["config"]["tau_shear"])
+        out["cpu_baseline"], ref = cpu_baseline(out["config"]["tau_shear"])
+        out["error_vs_oracle"] = error_vs_oracle(cmlb, out["config"]["tau_shear"], ref)
     print(json.dumps(out), flush=True)
 
 
@@ -257,18 +281,29 @@ def run(torch, cmlb, inputs, stream, args):
     ctx.step(args.warmup)
     torch.cuda.synchronize()
 
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # the K timed steps in five segments with events between them (per-launch
+    # time of each segment; their median is reported beside the average)
+    def n_launches(m):
+        return (m // 2 + m % 2) if fused else m
+
+    base = args.steps // 5
+    if fused:
+        base -= base % 2
+    sizes = [base] * 4 + [args.steps - 4 * base]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.step(args.steps)
-    ev1.record(stream)
+    evs[0].record(stream)
+    for k, m in enumerate(sizes):
+        ctx.step(m)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    launches = (args.steps // 2 + args.steps % 2) if fused else args.steps
-    kernel_ms = ev0.elapsed_time(ev1) / max(launches, 1)
+    ev0, ev1 = evs[0], evs[-1]
+    kernel_ms = ev0.elapsed_time(ev1) / max(n_launches(args.steps), 1)
+    seg_ms = [evs[k].elapsed_time(evs[k + 1]) / n_launches(m) for k, m in enumerate(sizes) if n_launches(m) > 0]
+    kernel_ms_median = sorted(seg_ms)[len(seg_ms) // 2] if seg_ms else kernel_ms
     updates_per_launch = 2 if fused else 1
 
     g = ctx.reduce()
@@ -329,7 +364,8 @@ def run(torch, cmlb, inputs, stream, args):
         "config": {"workload": desc, "lattice": lattice, "grid": list(shape), "storage": storage,
                    "tau_shear": taus[2], "tau_by_order": {str(k): v for k, v in taus.items()},
                    "parallelism": "single GPU"},
-        "roofline": dict(roof, kernel=kernel, kernel_ms=round(kernel_ms, 5), steps_per_launch=updates_per_launch,
+        "roofline": dict(roof, kernel=kernel, kernel_ms=round(kernel_ms, 5),
+                         kernel_ms_median_of_5_segments=round(kernel_ms_median, 5), steps_per_launch=updates_per_launch,
                          bytes_per_node_update=per_node, algorithmic_bytes_per_launch=alg_bytes,
                          copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4)),
     }
