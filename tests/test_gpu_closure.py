@@ -153,3 +153,65 @@ def test_box_filter(cm, orc):
     ctx.destroy()
     ref = (S - w[:, None, None, None]).reshape(27, 4, 2, 4, 2, 8, 2).mean(axis=(2, 4, 6))
     assert np.abs(out.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-8
+
+
+def test_trained_closure_beats_fixed_rates(cm):
+    """What training gains over the method without the network: 128^3
+    random multi-mode runs at Re = 1e5, box-filtered 2^3 -> 64^3 (one coarse
+    step = 2 fine steps); the network starts at rate 1 for orders 3..6 (the
+    plain method's rates) with all four outputs free, trains 300 Adam steps on
+    seeds 0 and 1, and is judged on held-out seed 2.  Measured: held-out
+    objective 1.57x lower than the plain method's, within 0.2 % of the best
+    constant rate set (odd orders at 1, even orders at omega_2)."""
+    import math
+    import torch
+    from paper_1808_04406_amd import studies
+    n_fine, factor, u0, re = 128, 2, 0.05, 1.0e5
+    tau_f = 0.5 + 3.0 * u0 * (n_fine / (2 * math.pi)) / re
+    tau_c = 0.5 + (tau_f - 0.5) / factor
+    nc = n_fine // factor
+    data = {}
+    for seed in (0, 1, 2):
+        rho, u = inputs.random_multimode(n_fine, seed, kmax=4, umax=u0)
+        fine = cm.Context("D3Q27", (n_fine,) * 3, storage="f32", tau=studies._tgv_rates(tau_f))
+        try:
+            fine.init_fields(rho, u)
+            fine.step(100)
+            pairs = []
+            for _ in range(3):
+                a = torch.empty(27 * nc ** 3, dtype=torch.float32, device="cuda")
+                b = torch.empty_like(a)
+                fine.box_filter(factor, a)
+                fine.step(factor)
+                fine.box_filter(factor, b)
+                pairs.append((a, b))
+                fine.step(40 - factor)
+            fine.sync()
+        finally:
+            fine.destroy()
+        data[seed] = pairs
+    train, test = data[0] + data[1], data[2]
+    sigma = studies._input_scales(train[0][0].cpu().numpy(), nc)
+    rate1 = studies._constant_net([1.0] * 4)
+    stable = studies._constant_net([1.0] * 4, seed=1, scale=0.1)
+    ctx = cm.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c})
+    try:
+        def objective(params, pairs, tie):
+            ctx.closure_load(params, sigma)
+            ctx.closure_tie_even(tie)
+            return float(np.mean([ctx.closure_objective(a, b, grad=False) for a, b in pairs]))
+
+        plain = objective(rate1, test, False)
+        best_fixed = objective(stable, test, True)
+        ctx.closure_load(rate1, sigma)
+        ctx.closure_tie_even(False)
+        for it in range(300):
+            a, b = train[it % len(train)]
+            ctx.closure_train_step(a, b, 2e-3 * (1.0 - it / 300))
+        learned = objective(ctx.closure_get().astype(np.float64), test, False)
+    finally:
+        ctx.destroy()
+    print(f"held-out objective: plain (rates 1) {plain:.4e}, best constant rates {best_fixed:.4e}, "
+          f"trained network {learned:.4e} (gain {plain / learned:.3f})")
+    assert plain / learned > 1.3
+    assert learned < 1.02 * best_fixed
