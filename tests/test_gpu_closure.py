@@ -160,7 +160,7 @@ def test_trained_closure_beats_fixed_rates(cm):
     random multi-mode runs at Re = 1e5, box-filtered 2^3 -> 64^3 (one coarse
     step = 2 fine steps); the network starts at rate 1 for orders 3..6 (the
     plain method's rates) with all four outputs free, trains 300 Adam steps on
-    seeds 0 and 1, and is judged on held-out seed 2.  Measured: held-out
+    seeds 0 and 1, and is evaluated on held-out seed 2.  Measured: held-out
     objective 1.57x lower than the plain method's, within 0.2 % of the best
     constant rate set (odd orders at 1, even orders at omega_2)."""
     import math
