@@ -232,3 +232,34 @@ def test_create_validation_matches_documented_ranges(cm):
             assert L.cmlb_create_error().decode()
 
     check()
+
+
+def test_run_config_validation(tmp_path):
+    """The configuration runner's parser: defaults, YAML, and the errors it names."""
+    from paper_1808_04406_amd.run import load_config
+    c = load_config({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 10, "init": {"kind": "tgv", "u0": 0.04},
+                     "tau": {"2": 0.6}})
+    assert c["grid"] == [8, 8, 8] and c["every"] == 10 and c["tau"] == {2: 0.6} and c["storage"] == "f32"
+    y = tmp_path / "run.yaml"
+    y.write_text("lattice: D2Q37\ngrid: [16, 12]\nthermal: true\nsteps: 5\nevery: 2\n"
+                 "init: {kind: waves, shear_amp: 0.001, thermal_amp: 0.001}\n")
+    c = load_config(str(y))
+    assert c["grid"] == [16, 12, 1] and c["thermal"] and c["init"]["kind"] == "waves"
+    bad = [
+        ({"lattice": "D3Q27", "grid": [8, 8, 8]}, "steps"),
+        ({"lattice": "D3Q19", "grid": [8, 8, 8], "steps": 1}, "lattice"),
+        ({"lattice": "D2Q9", "grid": [8, 8, 2], "steps": 1}, "2D"),
+        ({"lattice": "D3Q27", "grid": [8, 8], "steps": 1}, "nz"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 4], "steps": 1, "init": {"kind": "tgv"}}, "cubic"),
+        ({"lattice": "D2Q9", "grid": [8, 6], "steps": 1, "init": {"kind": "double_shear_layer"}}, "square"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 1, "init": {"kind": "waves"}}, "two-dimensional"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 1, "init": {"kind": "vortex"}}, "init.kind"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 1, "init": {"kind": "tgv", "amp": 1}}, "does not take"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 1, "tau": {"1": 0.6}}, "orders"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 1, "every": 0}, "every"),
+        ({"lattice": "D3Q27", "grid": [8, 8, 8], "steps": 1, "colour": "red"}, "unknown"),
+        ({"steps": 1, "init": {"kind": "checkpoint"}}, "path"),
+    ]
+    for cfg, word in bad:
+        with pytest.raises(ValueError, match=word):
+            load_config(cfg)
