@@ -100,6 +100,8 @@ typedef struct cmlb_globals {
     double kinetic_energy;
     double enstrophy;
     int64_t n_nonfinite;
+    double rho_min, rho_max; /* smallest and largest node density (finite nodes) */
+    double u_max;            /* largest |u| (lattice units, finite nodes) */
 } cmlb_globals;
 
 typedef struct cmlb_ctx cmlb_ctx;

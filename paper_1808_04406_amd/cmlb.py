@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
 class Globals(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3), ("energy", ctypes.c_double),
                 ("kinetic_energy", ctypes.c_double), ("enstrophy", ctypes.c_double),
-                ("n_nonfinite", ctypes.c_int64)]
+                ("n_nonfinite", ctypes.c_int64), ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
+                ("u_max", ctypes.c_double)]
 
 
 class Batch(ctypes.Structure):
@@ -291,7 +292,8 @@ class Context:
         if rc and not (allow_unstable and rc == EUNSTABLE):
             self._check(rc)
         return dict(mass=g.mass, momentum=np.array(list(g.momentum)), energy=g.energy,
-                    ke=g.kinetic_energy, enstrophy=g.enstrophy, nonfinite=g.n_nonfinite)
+                    ke=g.kinetic_energy, enstrophy=g.enstrophy, nonfinite=g.n_nonfinite,
+                    rho_min=g.rho_min, rho_max=g.rho_max, u_max=g.u_max)
 
     def state(self):
         p, n, s = ctypes.c_void_p(), ctypes.c_size_t(), ctypes.c_void_p()

@@ -677,14 +677,15 @@ int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
     const int nb = reduce_blocks(c->nodes);
     if (!c->red_u) {
         if ((e = hipMalloc(&c->red_u, c->nodes * 3 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_u = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
-        if ((e = hipMalloc(&c->red_p, (size_t)nb * 16 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_p = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
-        if ((e = hipMalloc(&c->red_out, 8 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_out = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+        if ((e = hipMalloc(&c->red_p, (size_t)nb * 2 * kRedVals * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_p = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+        if ((e = hipMalloc(&c->red_out, kRedVals * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_out = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
     }
     StepArgs a = base_args(c);
     a.src = c->f[c->cur];
-    launch_reduce(c->p.lattice, c->p.storage, a, c->red_u, c->red_p, c->red_p + (size_t)nb * 8, c->red_out, c->stream);
+    launch_reduce(c->p.lattice, c->p.storage, a, c->red_u, c->red_p, c->red_p + (size_t)nb * kRedVals, c->red_out,
+                  c->stream);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
-    double v[8];
+    double v[kRedVals];
     if ((e = hipMemcpyAsync(v, c->red_out, sizeof(v), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "reduce");
     double we2 = 0.0;
@@ -698,6 +699,9 @@ int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
     out->kinetic_energy = v[5];
     out->enstrophy = v[6];
     out->n_nonfinite = (int64_t)v[7];
+    out->rho_min = c->p.rho0 - v[8];
+    out->rho_max = c->p.rho0 + v[9];
+    out->u_max = std::sqrt(v[10]);
     if (out->n_nonfinite > 0) return fail(c, CMLB_EUNSTABLE, "non-finite populations in the state");
     return CMLB_OK;
 }

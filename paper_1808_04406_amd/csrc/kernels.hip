@@ -180,26 +180,42 @@ __global__ __launch_bounds__(256) void k_encode(CodecArgs c) {
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reductions
 // ---------------------------------------------------------------------------
-constexpr int kRedVals = 8;  // drho, jx, jy, jz, e2, ke, enstrophy, nonfinite
+// Values 0..7 are sums (drho, jx, jy, jz, e2, ke, enstrophy, nonfinite);
+// values 8..10 are maxima (-drho, drho, |u|^2), so the smallest and largest
+// density and the largest speed come out of the same passes.  fmax ignores
+// NaN: non-finite nodes are counted by value 7 instead.
+constexpr int kRedSums = 8;
+static_assert(kRedVals == 11, "eight sums and three maxima");
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// Block sum of kRedVals values; thread 0 writes the block's partial row.
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ void reset_acc(double (&acc)[kRedVals]) {
+    for (int k = 0; k < kRedVals; ++k) acc[k] = k < kRedSums ? 0.0 : -HUGE_VAL;
+}
+
+// Block reduction of kRedVals values; thread k < kRedVals writes value k of
+// the block's partial row.
 __device__ __forceinline__ void block_partials(double (&v)[kRedVals], double* partials) {
     __shared__ double lds[4][kRedVals];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < kRedVals; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 0; k < kRedVals; ++k) v[k] = k < kRedSums ? wave_sum(v[k]) : wave_max(v[k]);
     if (lane == 0)
         for (int k = 0; k < kRedVals; ++k) lds[wave][k] = v[k];
     __syncthreads();
     if (threadIdx.x < kRedVals) {
-        double s = 0.0;
+        const int k = threadIdx.x;
+        double s = k < kRedSums ? 0.0 : -HUGE_VAL;
         const int nw = blockDim.x >> 6;
-        for (int w = 0; w < nw; ++w) s += lds[w][threadIdx.x];
-        partials[(uint64_t)blockIdx.x * kRedVals + threadIdx.x] = s;
+        for (int w = 0; w < nw; ++w) s = k < kRedSums ? s + lds[w][k] : fmax(s, lds[w][k]);
+        partials[(uint64_t)blockIdx.x * kRedVals + k] = s;
     }
 }
 
@@ -207,7 +223,8 @@ template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, double* partials) {
     using T = typename Store<ST>::T;
     const T* src = static_cast<const T*>(a.src);
-    double acc[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kRedVals];
+    reset_acc(acc);
     for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
          n += (uint64_t)gridDim.x * blockDim.x) {
         double s0, j[3], e2;
@@ -220,8 +237,12 @@ __global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, do
         acc[2] += j[1];
         acc[3] += j[2];
         acc[4] += e2;
-        acc[5] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+        const double uu = ux * ux + uy * uy + uz * uz;
+        acc[5] += 0.5 * rho * uu;
         acc[7] += nf;
+        acc[8] = fmax(acc[8], -s0);
+        acc[9] = fmax(acc[9], s0);
+        acc[10] = fmax(acc[10], uu);
         uf[n] = ux;
         uf[a.g.plane + n] = uy;
         uf[2 * a.g.plane + n] = uz;
@@ -231,7 +252,8 @@ __global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, do
 
 // Enstrophy 1/2 |curl u|^2 with second-order central differences (periodic).
 __global__ __launch_bounds__(256) void k_reduce_vort(GridArgs g, int D, const double* uf, double* partials) {
-    double acc[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kRedVals];
+    reset_acc(acc);
     const uint64_t P = g.plane;
     for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < P;
          n += (uint64_t)gridDim.x * blockDim.x) {
@@ -264,10 +286,17 @@ __global__ __launch_bounds__(64 * kRedVals) void k_reduce_final(const double* p1
                                                                 double* out) {
     const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double* p = (k == 6) ? p2 : p1;
-    double s = 0.0;
-    for (int b = lane; b < nblocks; b += 64) s += p[(uint64_t)b * kRedVals + k];
-    s = wave_sum(s);
-    if (lane == 0) out[k] = s;
+    if (k < kRedSums) {
+        double s = 0.0;
+        for (int b = lane; b < nblocks; b += 64) s += p[(uint64_t)b * kRedVals + k];
+        s = wave_sum(s);
+        if (lane == 0) out[k] = s;
+    } else {
+        double m = -HUGE_VAL;
+        for (int b = lane; b < nblocks; b += 64) m = fmax(m, p[(uint64_t)b * kRedVals + k]);
+        m = wave_max(m);
+        if (lane == 0) out[k] = m;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -48,6 +48,8 @@ int launch_codec(int lattice, int storage, bool decode, void* stor, double* full
 // Reduction: uf holds 3 * plane doubles of scratch, p1 and p2 reduce_blocks(plane) * 8
 // doubles each, out 8 doubles (drho, jx, jy, jz, sum h|e|^2, ke, enstrophy, nonfinite).
 int reduce_blocks(uint64_t plane);
+// Values per partial row of the FP64 reductions (8 sums, 3 maxima).
+constexpr int kRedVals = 11;
 int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,
                   hipStream_t s);
 

@@ -33,7 +33,8 @@ Configuration keys (x first in ``grid``; defaults in brackets):
 
 Each record holds the step, wall time, MLUPS since the previous record and
 the FP64 reductions of the library (mass, momentum, energy, kinetic energy,
-enstrophy, count of non-finite populations).  A run that produces
+enstrophy, smallest and largest density, largest speed, count of
+non-finite populations).  A run that produces
 non-finite populations stops at that record with "diverged": true.
 """
 from __future__ import annotations
@@ -207,7 +208,8 @@ def run(source, output=None, stream=None) -> list:
             rec = {"step": int(ctx.step_count()), "time_s": now - start,
                    "mlups": nodes * k_steps / max(now - last, 1e-12) / 1e6 if k_steps else None,
                    "mass": g["mass"], "momentum": [float(v) for v in g["momentum"]], "energy": g["energy"],
-                   "ke": g["ke"], "enstrophy": g["enstrophy"], "nonfinite": int(g["nonfinite"])}
+                   "ke": g["ke"], "enstrophy": g["enstrophy"], "rho_min": g["rho_min"], "rho_max": g["rho_max"],
+                   "u_max": g["u_max"], "nonfinite": int(g["nonfinite"])}
             if g["nonfinite"]:
                 rec["diverged"] = True
             last = now

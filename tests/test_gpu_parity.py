@@ -286,6 +286,10 @@ def test_moments_and_reductions(cm, orc, kind, shape, thermal):
         assert g[key] == pytest.approx(ref[key], rel=1e-12, abs=1e-15), key
     assert np.allclose(g["momentum"][:len(ref["momentum"])], ref["momentum"], rtol=1e-12, atol=1e-13)
     assert g["nonfinite"] == 0
+    # range diagnostics: same node arithmetic as the moment readout
+    assert g["rho_min"] == g_rho.min() and g["rho_max"] == g_rho.max()
+    assert abs(g["rho_min"] - o_rho.min()) < 1e-14 and abs(g["rho_max"] - o_rho.max()) < 1e-14
+    assert g["u_max"] == pytest.approx(np.sqrt((o_u ** 2).sum(0)).max(), rel=1e-13)
 
 
 def test_nonfinite_detected(cm, orc):
@@ -296,7 +300,9 @@ def test_nonfinite_detected(cm, orc):
     with pytest.raises(cm.CmlbError) as ei:
         ctx.reduce()
     assert ei.value.code == cm.EUNSTABLE
-    assert ctx.reduce(allow_unstable=True)["nonfinite"] == 1
+    g = ctx.reduce(allow_unstable=True)
+    assert g["nonfinite"] == 1
+    assert np.isfinite(g["rho_min"]) and np.isfinite(g["u_max"])   # ranges over the finite nodes
     ctx.destroy()
 
 
