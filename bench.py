@@ -313,7 +313,12 @@ def run(torch, cmlb, inputs, stream, args):
     del bufs
     torch.cuda.empty_cache()
 
-    copy_gbs = copy_bandwidth(torch)
+    torch_copy_gbs = copy_bandwidth(torch)   # also the reference of the HBM counter calibration
+    # achievable ceilings with the library's copy kernel: one 4 GiB plane, and
+    # 27 planes of 2^24 FP32 values (the step's access pattern and state size;
+    # planes whose size is not a multiple of 128 B copy markedly slower)
+    copy1_gbs = cmlb.copy_bandwidth(4 << 30, planes=1)
+    copy_gbs = cmlb.copy_bandwidth(27 * 4 * (1 << 24), planes=27)
 
     value = nodes * args.steps / wall / 1e6
     per_node = 2 * q * sb
@@ -367,7 +372,10 @@ def run(torch, cmlb, inputs, stream, args):
         "roofline": dict(roof, kernel=kernel, kernel_ms=round(kernel_ms, 5),
                          kernel_ms_median_of_5_segments=round(kernel_ms_median, 5), steps_per_launch=updates_per_launch,
                          bytes_per_node_update=per_node, algorithmic_bytes_per_launch=alg_bytes,
-                         copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4)),
+                         copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4),
+                         copy_note="copy_GBps: streaming copy of 27 FP32 planes (the step's pattern); "
+                                   "copy1_GBps: one plane; torch_copy_GBps: torch's device copy",
+                         copy1_GBps=round(copy1_gbs, 1), torch_copy_GBps=round(torch_copy_gbs, 1)),
     }
     return out
 

@@ -110,6 +110,17 @@ typedef struct cmlb_ctx cmlb_ctx;
  * pointer may be NULL.  Host-only; needs no device. */
 int cmlb_lattice_info(int lattice, int *D, int *Q, int *e, double *w, double *r);
 
+/* Achievable HBM bandwidth for the step's access pattern, the measured
+ * ceiling beside the 8 TB/s peak (a measurement aid; the paper has no
+ * counterpart).  Copies `planes`
+ * (1 or 27) FP32 planes filling `bytes` from one device buffer to another,
+ * one element of every plane per thread as the step kernels do, `reps`
+ * times after one warm-up copy, and writes (read + written bytes) / time in
+ * GB/s to *gbps.  Allocates and frees its two buffers and its stream;
+ * synchronises.  CMLB_EINVAL for bad arguments, CMLB_ENOMEM if the buffers
+ * do not fit, CMLB_EDEVICE on a device error. */
+int cmlb_copy_bandwidth(int device, uint64_t bytes, int planes, int reps, double *gbps);
+
 /* Create a context: validates p, allocates two population buffers of
  * Q * nx*ny*nz elements of the storage type on p->device.  The state is
  * undefined until cmlb_init_fields or cmlb_set_populations.  On failure

@@ -85,6 +85,7 @@ def lib():
         L.cmlb_set_step_fusion.argtypes = [vp, c_int]
         L.cmlb_set_graph_steps.argtypes = [vp, c_int]
         L.cmlb_step_batch.argtypes = [P(vp), c_int, c_i64]
+        L.cmlb_copy_bandwidth.argtypes = [c_int, ctypes.c_uint64, c_int, c_int, dp]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
         L.cmlb_get_moments_device.argtypes = [vp, vp, vp, vp]
@@ -162,6 +163,15 @@ def _stream_handle(stream):
         raise ValueError("pass a non-default stream (e.g. torch.cuda.Stream()); the default stream "
                          "does not order with the library's own stream")
     return h
+
+
+def copy_bandwidth(nbytes=4 << 30, planes=27, reps=10, device=0):
+    """cmlb_copy_bandwidth: GB/s of a streaming copy of `planes` FP32 planes."""
+    g = ctypes.c_double()
+    rc = lib().cmlb_copy_bandwidth(int(device), int(nbytes), int(planes), int(reps), ctypes.byref(g))
+    if rc:
+        raise CmlbError(rc, "copy bandwidth measurement failed")
+    return g.value
 
 
 def step_batch(ctxs, n=1):

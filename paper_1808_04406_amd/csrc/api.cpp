@@ -327,6 +327,43 @@ int cmlb_lattice_info(int lattice, int* D, int* Q, int* e, double* w, double* r)
     return CMLB_OK;
 }
 
+int cmlb_copy_bandwidth(int device, uint64_t bytes, int planes, int reps, double* gbps) {
+    if (!gbps || reps < 1 || (planes != 1 && planes != 27)) return CMLB_EINVAL;
+    uint64_t plane = bytes / (4ull * (uint64_t)planes);
+    if (planes == 1) plane -= plane % 4;   // whole 16-byte groups
+    if (plane == 0) return CMLB_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return CMLB_EDEVICE;
+    const size_t n = (size_t)plane * planes * sizeof(float);
+    float *src = nullptr, *dst = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = CMLB_OK;
+    float ms = 0.0f;
+    if (hipMalloc(&src, n) != hipSuccess || hipMalloc(&dst, n) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = CMLB_ENOMEM;
+    } else if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = CMLB_EDEVICE;
+    } else {
+        bool ok = hipMemsetAsync(src, 0, n, s) == hipSuccess &&
+                  launch_stream_copy(planes, src, dst, plane, s) == 0;       // warm-up
+        ok = ok && hipEventRecord(e0, s) == hipSuccess;
+        for (int r = 0; ok && r < reps; ++r) ok = launch_stream_copy(planes, src, dst, plane, s) == 0;
+        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!ok || !(ms > 0.0f)) rc = CMLB_EDEVICE;
+        else *gbps = 2.0 * (double)n * reps / (ms * 1e-3) / 1e9;
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (src) (void)hipFree(src);
+    if (dst) (void)hipFree(dst);
+    return rc;
+}
+
 int cmlb_create(const cmlb_params* p, cmlb_ctx** out) { return create_impl(p, nullptr, nullptr, out); }
 
 int cmlb_create_external(const cmlb_params* p, void* f_a, void* f_b, cmlb_ctx** out) {

@@ -447,6 +447,57 @@ int launch_box_filter(int storage, const StepArgs& a, int factor, float* dst, hi
     return -1;
 }
 
+// ---------------------------------------------------------------------------
+// Streaming copy, the achievable-bandwidth reference of the step kernels:
+// P planes of `plane` FP32 values, one element of every plane per thread, as
+// the step reads and writes its P = Q population planes.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_stream_copy(const float* __restrict__ src, float* __restrict__ dst,
+                                                     uint64_t plane) {
+    const uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (n >= plane) return;
+    float v[P];   // all loads in flight before the first store, as in the step
+    static_for<0, P>([&](auto I) { v[decltype(I)::value] = src[(uint64_t)decltype(I)::value * plane + n]; });
+    static_for<0, P>([&](auto I) {
+        constexpr int p = decltype(I)::value;
+        __builtin_nontemporal_store(v[p], dst + (uint64_t)p * plane + n);
+    });
+}
+
+// One plane: 16-byte accesses, four per thread (the best a plain copy does).
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy_wide(const v4f* __restrict__ src, v4f* __restrict__ dst,
+                                                          uint64_t n4) {
+    const uint64_t base = (blockIdx.x * (uint64_t)blockDim.x) * 4 + threadIdx.x;
+    v4f v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = base + (uint64_t)k * blockDim.x;
+        if (i < n4) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = base + (uint64_t)k * blockDim.x;
+        if (i < n4) __builtin_nontemporal_store(v[k], dst + i);
+    }
+}
+
+int launch_stream_copy(int planes, const float* src, float* dst, uint64_t plane, hipStream_t s) {
+    if (planes == 1) {
+        const uint64_t n4 = plane / 4;   // whole 16-byte groups
+        const uint64_t blocks = (n4 + 1023) / 1024;
+        if (blocks == 0 || blocks > 0x7fffffffull) return -1;
+        hipLaunchKernelGGL(k_stream_copy_wide, dim3((uint32_t)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const v4f*>(src), reinterpret_cast<v4f*>(dst), n4);
+        return 0;
+    }
+    const uint64_t blocks = (plane + 255) / 256;
+    if (planes != 27 || blocks == 0 || blocks > 0x7fffffffull) return -1;
+    hipLaunchKernelGGL((k_stream_copy<27>), dim3((uint32_t)blocks), dim3(256), 0, s, src, dst, plane);
+    return 0;
+}
+
 int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,
                   hipStream_t s) {
     dim3 grid = flat_grid(a.g.plane), block(256);

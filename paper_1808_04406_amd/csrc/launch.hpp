@@ -48,6 +48,9 @@ int launch_codec(int lattice, int storage, bool decode, void* stor, double* full
 // Reduction: uf holds 3 * plane doubles of scratch, p1 and p2 reduce_blocks(plane) * 8
 // doubles each, out 8 doubles (drho, jx, jy, jz, sum h|e|^2, ke, enstrophy, nonfinite).
 int reduce_blocks(uint64_t plane);
+// Copy of `planes` (1 or 27) FP32 planes of `plane` values, one element of
+// each plane per thread (kernels.hip).
+int launch_stream_copy(int planes, const float* src, float* dst, uint64_t plane, hipStream_t s);
 // Values per partial row of the FP64 reductions (8 sums, 3 maxima).
 constexpr int kRedVals = 11;
 int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,

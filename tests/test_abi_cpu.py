@@ -64,6 +64,11 @@ def test_null_context_is_rejected(cm):
     assert L.cmlb_step_batch((ctypes.c_void_p * 1)(None), 1, 1) == cm.EINVAL
     assert L.cmlb_step_batch((ctypes.c_void_p * 1)(None), 0, 1) == cm.EINVAL
     assert L.cmlb_sync(None) == cm.EINVAL
+    g = ctypes.c_double()
+    assert L.cmlb_copy_bandwidth(0, 1 << 20, 5, 1, ctypes.byref(g)) == cm.EINVAL     # planes 1 or 27
+    assert L.cmlb_copy_bandwidth(0, 1 << 20, 27, 0, ctypes.byref(g)) == cm.EINVAL    # reps >= 1
+    assert L.cmlb_copy_bandwidth(0, 64, 27, 1, ctypes.byref(g)) == cm.EINVAL         # not one value per plane
+    assert L.cmlb_copy_bandwidth(0, 1 << 20, 27, 1, None) == cm.EINVAL
     assert L.cmlb_step_count(None) == -1
     L.cmlb_destroy(None)
 
