@@ -241,7 +241,8 @@ def setup_workload(name, torch, cmlb, inputs, stream):
     nodes = 1
     for s_ in shape:
         nodes *= s_
-    bufs = [torch.empty(q * nodes * sb, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    nbytes = cmlb.state_bytes(lattice, shape, storage)   # x-rows padded to the library's pitch
+    bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
     theta = None
     if lattice == "D3Q27":
         n = shape[0]

@@ -121,8 +121,26 @@ int cmlb_lattice_info(int lattice, int *D, int *Q, int *e, double *w, double *r)
  * do not fit, CMLB_EDEVICE on a device error. */
 int cmlb_copy_bandwidth(int device, uint64_t bytes, int planes, int reps, double *gbps);
 
+/* Layout of the population state (device memory, storage type): structure
+ * of arrays, population i of node (x, y, z) at
+ *     i * plane + (z * ny + y) * pitch + x,    plane = pitch * ny * nz,
+ * where pitch is nx rounded up to a multiple of 128 bytes, or nx itself when
+ * that would add more than one eighth (so every x-row of a large grid starts
+ * on a 128-byte line, which the pulls need to stream at full rate).  D3Q27
+ * FP32 states whose rows are already a multiple of 32 bytes (nx % 8 == 0)
+ * are not padded: their default two-step kernel streams such rows at full
+ * rate.  Entries with x >= nx are never read.  cmlb_state_bytes gives the
+ * buffer size.
+ * Host-side arrays (fields, cmlb_get/set_populations, training batches, the
+ * box filter's output) are unpadded, [component][z][y][x]. */
+
+/* Bytes of one population buffer for parameters p (validated as by
+ * cmlb_create; host only, no device needed).  Sizes the buffers of
+ * cmlb_create_external. */
+int cmlb_state_bytes(const cmlb_params *p, size_t *bytes);
+
 /* Create a context: validates p, allocates two population buffers of
- * Q * nx*ny*nz elements of the storage type on p->device.  The state is
+ * cmlb_state_bytes bytes on p->device.  The state is
  * undefined until cmlb_init_fields or cmlb_set_populations.  On failure
  * *out is NULL and cmlb_create_error() describes the reason: CMLB_EINVAL
  * for parameters outside the ranges documented in cmlb_params (checked
@@ -131,9 +149,8 @@ int cmlb_create(const cmlb_params *p, cmlb_ctx **out);
 
 /* As cmlb_create, but the population buffers f_a and f_b are device memory
  * owned by the caller (for example PyTorch tensors), each at least
- * Q * nx*ny*nz elements of the storage type, 256-byte aligned and not
- * overlapping (a step reads one and writes the other); CMLB_EINVAL
- * otherwise. */
+ * cmlb_state_bytes bytes, 256-byte aligned and not overlapping (a step reads
+ * one and writes the other); CMLB_EINVAL otherwise. */
 int cmlb_create_external(const cmlb_params *p, void *f_a, void *f_b, cmlb_ctx **out);
 
 /* Reason for the last failed create on this thread. */
@@ -247,8 +264,9 @@ int cmlb_get_tau(const cmlb_ctx *ctx, double *tau);
 int cmlb_get_scale(const cmlb_ctx *ctx, double *scale);
 
 /* Copy the current population buffer to / from device memory in the
- * context's own layout and storage type (Q * nx*ny*nz elements).  Loading
- * marks the state initialised and resets the step count. */
+ * context's own layout and storage type (cmlb_state_bytes bytes, rows
+ * padded to the pitch).  Loading marks the state initialised and resets the
+ * step count. */
 int cmlb_store_state_device(cmlb_ctx *ctx, void *dst);
 int cmlb_load_state_device(cmlb_ctx *ctx, const void *src);
 
@@ -288,7 +306,8 @@ int cmlb_closure_tie_even(cmlb_ctx *ctx, int on);
 int cmlb_closure_get(cmlb_ctx *ctx, float *params);
 
 /* A training batch: n_pairs consecutive (state, target) pairs in device
- * memory, each Q * nx*ny*nz FP32 deviations in the context's layout.  The
+ * memory, each Q * nx*ny*nz FP32 deviations, unpadded [i][z][y][x] (the
+ * box filter's output layout).  The
  * state is pulled (streamed) and collided with the network's rates; the
  * objective is the mean over all nodes of sum_i (f*_i - fbar_i)^2 / w_i
  * against the target.  nx must be a multiple of 64. */

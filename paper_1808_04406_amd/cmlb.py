@@ -86,6 +86,7 @@ def lib():
         L.cmlb_set_graph_steps.argtypes = [vp, c_int]
         L.cmlb_step_batch.argtypes = [P(vp), c_int, c_i64]
         L.cmlb_copy_bandwidth.argtypes = [c_int, ctypes.c_uint64, c_int, c_int, dp]
+        L.cmlb_state_bytes.argtypes = [P(Params), P(ctypes.c_size_t)]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
         L.cmlb_get_moments_device.argtypes = [vp, vp, vp, vp]
@@ -163,6 +164,17 @@ def _stream_handle(stream):
         raise ValueError("pass a non-default stream (e.g. torch.cuda.Stream()); the default stream "
                          "does not order with the library's own stream")
     return h
+
+
+def state_bytes(lattice, shape, storage="f32", **kw):
+    """cmlb_state_bytes: bytes of one population buffer (x-rows padded to the
+    pitch); the size of each external buffer."""
+    p = make_params(lattice, shape, storage, **kw)
+    n = ctypes.c_size_t()
+    rc = lib().cmlb_state_bytes(ctypes.byref(p), ctypes.byref(n))
+    if rc:
+        raise CmlbError(rc, lib().cmlb_create_error().decode())
+    return n.value
 
 
 def copy_bandwidth(nbytes=4 << 30, planes=27, reps=10, device=0):

@@ -123,6 +123,15 @@ bool host_lattice(int kind, HostLattice& L) {
 
 size_t storage_bytes(int st) { return st == CMLB_F64 ? 8 : st == CMLB_F32 ? 4 : 2; }
 
+int lattice_q(int lattice) { return lattice == CMLB_D2Q9 ? 9 : (lattice == CMLB_D3Q27 ? 27 : 37); }
+
+// Bytes of one population buffer: Q planes of pitch * ny * nz elements.
+size_t state_bytes_of(const cmlb_params* p) {
+    const size_t e = storage_bytes(p->storage);
+    const uint64_t pitch = cmlb::state_pitch(p->lattice, p->storage, (uint32_t)p->nx);
+    return (size_t)lattice_q(p->lattice) * pitch * (uint64_t)p->ny * (uint64_t)p->nz * e;
+}
+
 }  // namespace
 
 static_assert(CMLB_MAX_BATCH == cmlb::kMaxBatch, "batch size limit");
@@ -186,7 +195,8 @@ void graph_drop(cmlb_ctx* c) {
 StepArgs base_args(const cmlb_ctx* c) {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.g = make_grid((uint32_t)c->p.nx, (uint32_t)c->p.ny, (uint32_t)c->p.nz);
+    a.pitch = state_pitch(c->p.lattice, c->p.storage, (uint32_t)c->p.nx);
+    a.g = make_grid((uint32_t)c->p.nx, (uint32_t)c->p.ny, (uint32_t)c->p.nz, a.pitch);
     a.rho0 = c->p.rho0;
     a.theta0 = c->p.theta0;
     for (int n = 0; n < 8; ++n) a.omega[n] = c->omega[n];
@@ -276,7 +286,7 @@ int create_impl(const cmlb_params* p, void* fa, void* fb, cmlb_ctx** out) {
         if (e != hipSuccess) { g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e); delete c; return CMLB_EDEVICE; }
         c->own_stream = true;
     }
-    const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(p->storage);
+    const size_t bytes = state_bytes_of(p);
     if (fa || fb) {
         const uintptr_t a0 = (uintptr_t)fa, b0 = (uintptr_t)fb;
         const bool overlap = a0 < b0 + bytes && b0 < a0 + bytes;   // the step reads one and writes the other
@@ -362,6 +372,14 @@ int cmlb_copy_bandwidth(int device, uint64_t bytes, int planes, int reps, double
     if (src) (void)hipFree(src);
     if (dst) (void)hipFree(dst);
     return rc;
+}
+
+int cmlb_state_bytes(const cmlb_params* p, size_t* bytes) {
+    if (!bytes) return CMLB_EINVAL;
+    const std::string why = validate(p);
+    if (!why.empty()) { g_create_error = why; return CMLB_EINVAL; }
+    *bytes = state_bytes_of(p);
+    return CMLB_OK;
 }
 
 int cmlb_create(const cmlb_params* p, cmlb_ctx** out) { return create_impl(p, nullptr, nullptr, out); }
@@ -746,7 +764,7 @@ int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
 int cmlb_state(cmlb_ctx* c, void** f_cur, size_t* bytes, void** stream) {
     if (!c) return CMLB_EINVAL;
     if (f_cur) *f_cur = c->f[c->cur];
-    if (bytes) *bytes = (size_t)c->nodes * c->L.Q * storage_bytes(c->p.storage);
+    if (bytes) *bytes = state_bytes_of(&c->p);
     if (stream) *stream = (void*)c->stream;
     return CMLB_OK;
 }
@@ -771,7 +789,7 @@ int cmlb_store_state_device(cmlb_ctx* c, void* dst) {
     if (!dst) return fail(c, CMLB_EINVAL, "dst is NULL");
     if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
     if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
-    const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(c->p.storage);
+    const size_t bytes = state_bytes_of(&c->p);
     hipError_t e = hipMemcpyAsync(dst, c->f[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "store state");
     return CMLB_OK;
@@ -781,7 +799,7 @@ int cmlb_load_state_device(cmlb_ctx* c, const void* src) {
     if (!c) return CMLB_EINVAL;
     if (!src) return fail(c, CMLB_EINVAL, "src is NULL");
     if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
-    const size_t bytes = (size_t)c->nodes * c->L.Q * storage_bytes(c->p.storage);
+    const size_t bytes = state_bytes_of(&c->p);
     hipError_t e = hipMemcpyAsync(c->f[c->cur], src, bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "load state");
     c->initialised = true;

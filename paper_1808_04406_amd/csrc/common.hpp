@@ -160,11 +160,41 @@ struct Store<kF16> {
 // ---------------------------------------------------------------------------
 // Kernel argument blocks (passed by value).
 // ---------------------------------------------------------------------------
+// The state is structure of arrays: population i of node (x, y, z) sits at
+// i * plane + (z * ny + y) * pitch + x.  Rows are padded from nx to pitch
+// (StepArgs::pitch) so that every row starts on a 128-byte line (see
+// row_pitch); x >= nx is never read or written by the steps.
 struct GridArgs {
     uint32_t nx, ny, nz;
     uint32_t nchunks;   // x chunks of blockDim.x per row
-    uint64_t plane;     // nx * ny * nz
+    uint64_t plane;     // population-plane stride in elements: pitch * ny * nz
 };
+
+__host__ __device__ inline uint64_t nodes_of(const GridArgs& g) { return (uint64_t)g.nx * g.ny * g.nz; }
+
+// Row stride for nx elements of `elem` bytes: nx rounded up to a multiple of
+// 128 bytes, unless that adds more than one eighth (short rows stay unpadded).
+__host__ __device__ inline uint32_t row_pitch(uint32_t nx, uint32_t elem) {
+    const uint32_t unit = 128u / elem;
+    const uint32_t padded = (nx + unit - 1) / unit * unit;
+    return (uint64_t)(padded - nx) * 8u <= nx ? padded : nx;
+}
+
+// Row stride of a state.  D3Q27 FP32 states are stepped two steps per launch
+// by default, and that kernel, which moves 64-node tile rows, streams rows
+// aligned to 32 bytes as fast as padded ones (padding them measured slower),
+// so such rows stay unpadded; every other state takes row_pitch.
+__host__ __device__ inline uint32_t state_pitch(int lattice, int storage, uint32_t nx) {
+    const uint32_t elem = storage == kF64 ? 8u : (storage == kF32 ? 4u : 2u);
+    if (lattice == kD3Q27 && storage == kF32 && nx % 8u == 0) return nx;
+    return row_pitch(nx, elem);
+}
+
+// Padded offset of node n (flat index over nx * ny * nz, below 2^32).
+__host__ __device__ inline uint64_t node_offset(uint32_t nx, uint32_t pitch, uint64_t n) {
+    const uint32_t m = (uint32_t)n;
+    return (uint64_t)(m / nx) * pitch + m % nx;
+}
 
 struct StepArgs {
     const void* src;
@@ -178,6 +208,8 @@ struct StepArgs {
     double r;           // D2Q37 abscissa scale
     double wcls[8];     // D2Q37 weight per |e|^2 class
     int thermal;
+    uint32_t pitch;     // row stride of the state in elements (>= g.nx); fills the
+                        // struct's tail padding, so the argument block keeps its size
 };
 
 // Several lattices of one configuration stepped by one launch: blockIdx.y

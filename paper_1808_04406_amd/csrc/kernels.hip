@@ -24,14 +24,15 @@ __global__ __launch_bounds__(256) void k_init_tp(StepArgs a, FieldArgs fa) {
     using T = typename S::T;
     constexpr int Q = TP<D>::Q;
     T* dst = static_cast<T*>(a.dst);
-    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < nodes_of(a.g);
          n += (uint64_t)gridDim.x * blockDim.x) {
-        double u[3] = {fa.u[n], fa.u[a.g.plane + n], D == 3 ? fa.u[2 * a.g.plane + n] : 0.0};
+        double u[3] = {fa.u[n], fa.u[nodes_of(a.g) + n], D == 3 ? fa.u[2 * nodes_of(a.g) + n] : 0.0};
         double h[Q];
         tp_equilibrium<D, double>(h, fa.rho[n] - a.rho0, a.rho0, u);
+        const uint64_t off = node_offset(a.g.nx, a.pitch, n);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            dst[(uint64_t)i * a.g.plane + n] = S::from_double(h[i] * (double)a.s[i]);
+            dst[(uint64_t)i * a.g.plane + off] = S::from_double(h[i] * (double)a.s[i]);
         });
     }
 }
@@ -43,15 +44,16 @@ __global__ __launch_bounds__(256) void k_init_d37(StepArgs a, FieldArgs fa) {
     T* dst = static_cast<T*>(a.dst);
     double wc[8];
     for (int k = 0; k < 8; ++k) wc[k] = a.wcls[k];
-    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < nodes_of(a.g);
          n += (uint64_t)gridDim.x * blockDim.x) {
         const double th = fa.theta ? fa.theta[n] : a.theta0;
         double h[37];
-        d37_equilibrium<double>(h, fa.rho[n] - a.rho0, a.rho0, a.r * fa.u[n], a.r * fa.u[a.g.plane + n],
+        const uint64_t off = node_offset(a.g.nx, a.pitch, n);
+        d37_equilibrium<double>(h, fa.rho[n] - a.rho0, a.rho0, a.r * fa.u[n], a.r * fa.u[nodes_of(a.g) + n],
                                 th - 1.0, a.r, wc);
         static_for<0, 37>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            dst[(uint64_t)i * a.g.plane + n] = S::from_double(h[i] * (double)a.s[i]);
+            dst[(uint64_t)i * a.g.plane + off] = S::from_double(h[i] * (double)a.s[i]);
         });
     }
 }
@@ -115,18 +117,18 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, FieldArgs fa) {
     const double r2 = a.r * a.r;
     // sum_i w_i |e_i|^2 = D / r^2 (second moment of the quadrature)
     const double w_e2 = L::D / r2;
-    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < nodes_of(a.g);
          n += (uint64_t)gridDim.x * blockDim.x) {
         double s0, j[3], e2;
         int nf;
-        node_sums<LAT, ST>(src, a.g.plane, n, a.inv_s, s0, j, e2, nf);
+        node_sums<LAT, ST>(src, a.g.plane, node_offset(a.g.nx, a.pitch, n), a.inv_s, s0, j, e2, nf);
         const double rho = a.rho0 + s0;
         const double ux = j[0] / rho, uy = j[1] / rho, uz = j[2] / rho;
         if (fa.out_rho) fa.out_rho[n] = rho;
         if (fa.out_u) {
             fa.out_u[n] = ux;
-            fa.out_u[a.g.plane + n] = uy;
-            if (L::D == 3) fa.out_u[2 * a.g.plane + n] = uz;
+            fa.out_u[nodes_of(a.g) + n] = uy;
+            if (L::D == 3) fa.out_u[2 * nodes_of(a.g) + n] = uz;
         }
         if (fa.out_theta) {
             // rho (|u|^2 + D theta) = sum f |xi|^2, xi = r e
@@ -137,9 +139,11 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, FieldArgs fa) {
 }
 
 struct CodecArgs {
-    void* stor;
-    double* full;       // [Q][node]
-    uint64_t plane;
+    void* stor;         // the state: [Q][plane], rows padded to the pitch
+    double* full;       // [Q][node], unpadded
+    GridArgs g;
+    uint32_t pitch;
+    uint64_t plane;     // nodes (the loop bound of the codecs)
     double rho0;
     double w[37];
     float s[37];
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(256) void k_decode(CodecArgs c) {
          n += (uint64_t)gridDim.x * blockDim.x) {
         static_for<0, LatInfo<LAT>::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            double v = S::to_double(src[(uint64_t)i * c.plane + n]);
+            double v = S::to_double(src[(uint64_t)i * c.g.plane + node_offset(c.g.nx, c.pitch, n)]);
             if constexpr (S::kScaled) v *= (double)c.inv_s[i];
             c.full[(uint64_t)i * c.plane + n] = v + c.w[i] * c.rho0;
         });
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(256) void k_encode(CodecArgs c) {
         static_for<0, LatInfo<LAT>::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double v = (c.full[(uint64_t)i * c.plane + n] - c.w[i] * c.rho0) * (double)c.s[i];
-            dst[(uint64_t)i * c.plane + n] = S::from_double(v);
+            dst[(uint64_t)i * c.g.plane + node_offset(c.g.nx, c.pitch, n)] = S::from_double(v);
         });
     }
 }
@@ -225,11 +229,11 @@ __global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, do
     const T* src = static_cast<const T*>(a.src);
     double acc[kRedVals];
     reset_acc(acc);
-    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < a.g.plane;
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < nodes_of(a.g);
          n += (uint64_t)gridDim.x * blockDim.x) {
         double s0, j[3], e2;
         int nf;
-        node_sums<LAT, ST>(src, a.g.plane, n, a.inv_s, s0, j, e2, nf);
+        node_sums<LAT, ST>(src, a.g.plane, node_offset(a.g.nx, a.pitch, n), a.inv_s, s0, j, e2, nf);
         const double rho = a.rho0 + s0;
         const double ux = j[0] / rho, uy = j[1] / rho, uz = j[2] / rho;
         acc[0] += s0;
@@ -244,8 +248,8 @@ __global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, do
         acc[9] = fmax(acc[9], s0);
         acc[10] = fmax(acc[10], uu);
         uf[n] = ux;
-        uf[a.g.plane + n] = uy;
-        uf[2 * a.g.plane + n] = uz;
+        uf[nodes_of(a.g) + n] = uy;
+        uf[2 * nodes_of(a.g) + n] = uz;
     }
     block_partials(acc, partials);
 }
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(256) void k_reduce_nodes(StepArgs a, double* uf, do
 __global__ __launch_bounds__(256) void k_reduce_vort(GridArgs g, int D, const double* uf, double* partials) {
     double acc[kRedVals];
     reset_acc(acc);
-    const uint64_t P = g.plane;
+    const uint64_t P = nodes_of(g);   // uf is unpadded
     for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < P;
          n += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t x = n % g.nx, y = (n / g.nx) % g.ny, z = n / ((uint64_t)g.nx * g.ny);
@@ -320,7 +324,8 @@ __global__ __launch_bounds__(256) void k_box_filter(StepArgs a, int factor, floa
         for (int dz = 0; dz < factor; ++dz)
             for (int dy = 0; dy < factor; ++dy) {
                 const uint64_t rowb = (uint64_t)i * a.g.plane +
-                                      (((uint64_t)(Z * factor + dz) * a.g.ny + (Y * factor + dy)) * a.g.nx) + X * factor;
+                                      (((uint64_t)(Z * factor + dz) * a.g.ny + (Y * factor + dy)) * a.pitch) +
+                                      X * factor;
                 for (int dx = 0; dx < factor; ++dx) sum += S::to_double(src[rowb + dx]);
             }
         double v = sum * inv;
@@ -332,14 +337,14 @@ __global__ __launch_bounds__(256) void k_box_filter(StepArgs a, int factor, floa
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz) {
+GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t pitch) {
     GridArgs g;
     g.nx = nx;
     g.ny = ny;
     g.nz = nz;
     uint32_t bs = nx >= 256 ? 256u : ((nx + 63u) / 64u) * 64u;
     g.nchunks = (nx + bs - 1) / bs;
-    g.plane = (uint64_t)nx * ny * nz;
+    g.plane = (uint64_t)pitch * ny * nz;
     return g;
 }
 
@@ -365,7 +370,7 @@ int launch_step_batch(int lattice, int storage, int model, const BatchArgs& A, i
 
 template <int ST>
 static int launch_init_st(int lattice, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
-    dim3 grid = flat_grid(a.g.plane), block(256);
+    dim3 grid = flat_grid(nodes_of(a.g)), block(256);
     if (lattice == kD2Q9) hipLaunchKernelGGL((k_init_tp<2, ST>), grid, block, 0, s, a, f);
     else if (lattice == kD3Q27) hipLaunchKernelGGL((k_init_tp<3, ST>), grid, block, 0, s, a, f);
     else if (lattice == kD2Q37) hipLaunchKernelGGL((k_init_d37<ST>), grid, block, 0, s, a, f);
@@ -401,7 +406,7 @@ int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f,
     }
 
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
-    dim3 grid = flat_grid(a.g.plane), block(256);
+    dim3 grid = flat_grid(nodes_of(a.g)), block(256);
 #define L_MOM(L, S) hipLaunchKernelGGL((k_moments<L, S>), grid, block, 0, s, a, f)
     CMLB_DISPATCH(L_MOM)
 #undef L_MOM
@@ -413,14 +418,16 @@ int launch_codec(int lattice, int storage, bool decode, void* stor, double* full
     CodecArgs c;
     c.stor = stor;
     c.full = full;
-    c.plane = a.g.plane;
+    c.g = a.g;
+    c.pitch = a.pitch;
+    c.plane = nodes_of(a.g);
     c.rho0 = a.rho0;
     for (int i = 0; i < 37; ++i) {
         c.w[i] = w[i];
         c.s[i] = a.s[i];
         c.inv_s[i] = a.inv_s[i];
     }
-    dim3 grid = flat_grid(a.g.plane), block(256);
+    dim3 grid = flat_grid(nodes_of(a.g)), block(256);
 #define L_DEC(L, S) hipLaunchKernelGGL((k_decode<L, S>), grid, block, 0, s, c)
 #define L_ENC(L, S) hipLaunchKernelGGL((k_encode<L, S>), grid, block, 0, s, c)
     if (decode) {
@@ -500,7 +507,7 @@ int launch_stream_copy(int planes, const float* src, float* dst, uint64_t plane,
 
 int launch_reduce(int lattice, int storage, const StepArgs& a, double* uf, double* p1, double* p2, double* out,
                   hipStream_t s) {
-    dim3 grid = flat_grid(a.g.plane), block(256);
+    dim3 grid = flat_grid(nodes_of(a.g)), block(256);
 #define L_RED(L, S) hipLaunchKernelGGL((k_reduce_nodes<L, S>), grid, block, 0, s, a, uf, p1)
     CMLB_DISPATCH(L_RED)
 #undef L_RED

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_step_closure(StepArgs a, const ClosureN
     static_for<0, 27>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
-        const char* rowp = src + i * plane_bytes + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * nx * 4;
+        const char* rowp = src + i * plane_bytes + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * a.pitch * 4;
         h[i] = *reinterpret_cast<const T*>(rowp + xoff[ex + 1]);
     });
     const float rho0 = (float)a.rho0;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_step_closure(StepArgs a, const ClosureN
     tp_relax<3, float>(h, m.drho, rho0, m.u, om);
     tp_inverse<3, float>(h, m.u);
     if (!active) return;
-    char* outrow = dst + ((uint64_t)z * ny + y) * nx * 4;
+    char* outrow = dst + ((uint64_t)z * ny + y) * a.pitch * 4;
     static_for<0, 27>([&](auto I) {
         constexpr int i = decltype(I)::value;
         Store<kF32>::store(reinterpret_cast<T*>(outrow + i * plane_bytes + xoff[1]), h[i]);
@@ -113,13 +113,13 @@ __global__ __launch_bounds__(256) void k_step_closure(StepArgs a, const ClosureN
 // tile, and each lane accumulates 34 fixed gradient entries over its tiles.
 // ---------------------------------------------------------------------------
 struct TrainArgs {
-    const float* state;   // [pair][27][plane]
-    const float* target;  // [pair][27][plane]
+    const float* state;   // [pair][27][nodes], rows unpadded
+    const float* target;  // [pair][27][nodes]
     GridArgs g;
     int64_t n_pairs;
     float rho0;
     float omega2;
-    float inv_count;      // 1 / (n_pairs * plane)
+    float inv_count;      // 1 / (n_pairs * nodes)
 };
 
 constexpr int kGradPerLane = 34;   // 14 (W1, b1) + 17 (W2, b2) + 3 (W3, b3) entries of 64 lanes
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
     __shared__ float ACC[kGradPerLane][64];
     const int lane = threadIdx.x;
     const uint32_t nx = t.g.nx, ny = t.g.ny, nz = t.g.nz;
-    const uint64_t plane = t.g.plane;
+    const uint64_t plane = nodes_of(t.g);   // the batch arrays are unpadded
     const uint64_t tiles_per_pair = plane / 64;
     const uint64_t ntiles = tiles_per_pair * (uint64_t)t.n_pairs;
     for (int q = 0; q < kGradPerLane; ++q) ACC[q][lane] = 0.0f;
@@ -332,7 +332,7 @@ void launch_closure_train(const float* state, const float* target, int64_t n_pai
     t.n_pairs = n_pairs;
     t.rho0 = rho0;
     t.omega2 = omega2;
-    t.inv_count = (float)(1.0 / ((double)n_pairs * (double)g.plane));
+    t.inv_count = (float)(1.0 / ((double)n_pairs * (double)nodes_of(g)));
     hipLaunchKernelGGL(k_closure_train, dim3(nblocks), dim3(64), 0, s, t, static_cast<const ClosureNet*>(net),
                        partials);
     hipLaunchKernelGGL(k_closure_reduce, dim3((kPartialStride + 255) / 256), dim3(256), 0, s, partials, nblocks,

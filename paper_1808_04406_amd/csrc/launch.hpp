@@ -5,7 +5,7 @@
 
 namespace cmlb {
 
-GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz);
+GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t pitch);
 
 // Step-kernel launch shape: one block per x-segment of each of `rows` rows,
 // segments of up to max_block nodes (a whole row when it fits, so that the

@@ -12,7 +12,8 @@ namespace cmlb {
 // ---------------------------------------------------------------------------
 // Hot path: D2Q37 stream + collide (order-4 Hermite truncation)
 // ---------------------------------------------------------------------------
-template <int ST, int MODEL>
+// PAD: x-rows padded to the pitch (otherwise the row stride is nx).
+template <int ST, int MODEL, bool PAD>
 __device__ __forceinline__ void step_d37_body(const StepArgs& a) {
     using S = Store<ST>;
     using R = typename S::R;
@@ -33,7 +34,7 @@ __device__ __forceinline__ void step_d37_body(const StepArgs& a) {
         constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
         const uint32_t ys = wrap_sub(y, ey, ny);                       // block-uniform
         const uint32_t xo = wrap_sub(x, ex, nx) * (uint32_t)sizeof(T);  // lane byte offset
-        const char* rowp = src + i * plane_bytes + (uint64_t)ys * nx * sizeof(T);
+        const char* rowp = src + i * plane_bytes + (uint64_t)ys * (PAD ? a.pitch : nx) * sizeof(T);
         R v = S::load(reinterpret_cast<const T*>(rowp + xo));
         if constexpr (S::kScaled) v *= R(a.inv_s[i]);
         h[i] = v;
@@ -45,7 +46,7 @@ __device__ __forceinline__ void step_d37_body(const StepArgs& a) {
     static_for<0, 8>([&](auto N) { wc[decltype(N)::value] = R(a.wcls[decltype(N)::value]); });
     d37_collide<MODEL, R>(h, R(a.rho0), om, R(a.r), wc, a.thermal != 0, R(a.theta0));
 
-    char* outrow = dst + (uint64_t)y * nx * sizeof(T);
+    char* outrow = dst + (uint64_t)y * (PAD ? a.pitch : nx) * sizeof(T);
     const uint32_t xo = x * (uint32_t)sizeof(T);
     static_for<0, 37>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -55,15 +56,15 @@ __device__ __forceinline__ void step_d37_body(const StepArgs& a) {
     });
 }
 
-template <int ST, int MODEL>
+template <int ST, int MODEL, bool PAD>
 __global__ __launch_bounds__(512) void k_step_d37(StepArgs a) {
-    step_d37_body<ST, MODEL>(a);
+    step_d37_body<ST, MODEL, PAD>(a);
 }
 
 // One step of each lattice of a batch (blockIdx.y = lattice).
-template <int ST, int MODEL>
+template <int ST, int MODEL, bool PAD>
 __global__ __launch_bounds__(512) void k_step_d37_batch(BatchArgs A) {
-    step_d37_body<ST, MODEL>(batch_member(A));
+    step_d37_body<ST, MODEL, PAD>(batch_member(A));
 }
 
 // ---------------------------------------------------------------------------
@@ -73,7 +74,8 @@ template <int ST, int MODEL>
 static void launch_d37(StepArgs a, hipStream_t s) {
     dim3 grid, block;
     step_shape(a, grid, block, a.g.ny, 512);   // FP64 needs up to 142 VGPRs: at most 512 threads
-    hipLaunchKernelGGL((k_step_d37<ST, MODEL>), grid, block, 0, s, a);
+    if (a.pitch != a.g.nx) hipLaunchKernelGGL((k_step_d37<ST, MODEL, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step_d37<ST, MODEL, false>), grid, block, 0, s, a);
 }
 
 template <int ST, int MODEL>
@@ -81,7 +83,8 @@ static void launch_d37_batch(BatchArgs A, int count, hipStream_t s) {
     dim3 grid, block;
     step_shape(A.a, grid, block, A.a.g.ny, 512);
     grid.y = count;
-    hipLaunchKernelGGL((k_step_d37_batch<ST, MODEL>), grid, block, 0, s, A);
+    if (A.a.pitch != A.a.g.nx) hipLaunchKernelGGL((k_step_d37_batch<ST, MODEL, true>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_step_d37_batch<ST, MODEL, false>), grid, block, 0, s, A);
 }
 
 int launch_step_d37_batch(int storage, int model, const BatchArgs& A, int count, hipStream_t s) {

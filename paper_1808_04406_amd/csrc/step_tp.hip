@@ -15,13 +15,16 @@ namespace cmlb {
 // ---------------------------------------------------------------------------
 // Hot path: D2Q9 / D3Q27 stream + collide
 // ---------------------------------------------------------------------------
-template <int D, int ST>
+// PAD: x-rows padded to the pitch (otherwise the row stride is nx, which
+// keeps one scalar register free in the common, unpadded case).
+template <int D, int ST, bool PAD>
 __device__ __forceinline__ void step_tp_body(const StepArgs& a) {
     using S = Store<ST>;
     using R = typename S::R;
     using T = typename S::T;
     constexpr int Q = TP<D>::Q;
     const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const uint32_t pitch = PAD ? a.pitch : nx;
     const uint32_t blk = xcd_block(a.g.nchunks);
     const uint32_t chunk = blk % a.g.nchunks;
     const uint32_t row = blk / a.g.nchunks;
@@ -42,7 +45,7 @@ __device__ __forceinline__ void step_tp_body(const StepArgs& a) {
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = TP<D>::ex(i), ey = TP<D>::ey(i), ez = TP<D>::ez(i);
-        const char* rowp = src + i * plane_bytes + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * nx * sizeof(T);
+        const char* rowp = src + i * plane_bytes + ((uint64_t)zsrc[ez + 1] * ny + ysrc[ey + 1]) * pitch * sizeof(T);
         R v = S::load(reinterpret_cast<const T*>(rowp + xoff[ex + 1]));
         if constexpr (S::kScaled) v *= R(a.inv_s[i]);
         h[i] = v;
@@ -52,7 +55,7 @@ __device__ __forceinline__ void step_tp_body(const StepArgs& a) {
     static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
     tp_collide<D, R>(h, R(a.rho0), om);
 
-    char* outrow = dst + ((uint64_t)z * ny + y) * nx * sizeof(T);
+    char* outrow = dst + ((uint64_t)z * ny + y) * pitch * sizeof(T);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         R v = h[i];
@@ -61,15 +64,15 @@ __device__ __forceinline__ void step_tp_body(const StepArgs& a) {
     });
 }
 
-template <int D, int ST>
+template <int D, int ST, bool PAD>
 __global__ __launch_bounds__(1024) void k_step_tp(StepArgs a) {
-    step_tp_body<D, ST>(a);
+    step_tp_body<D, ST, PAD>(a);
 }
 
 // One step of each lattice of a batch (blockIdx.y = lattice).
-template <int D, int ST>
+template <int D, int ST, bool PAD>
 __global__ __launch_bounds__(1024) void k_step_tp_batch(BatchArgs A) {
-    step_tp_body<D, ST>(batch_member(A));
+    step_tp_body<D, ST, PAD>(batch_member(A));
 }
 
 // ---------------------------------------------------------------------------
@@ -79,7 +82,8 @@ template <int D, int ST>
 static void launch_tp(StepArgs a, hipStream_t s) {
     dim3 grid, block;
     step_shape(a, grid, block, a.g.ny * a.g.nz, 1024);
-    hipLaunchKernelGGL((k_step_tp<D, ST>), grid, block, 0, s, a);
+    if (a.pitch != a.g.nx) hipLaunchKernelGGL((k_step_tp<D, ST, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step_tp<D, ST, false>), grid, block, 0, s, a);
 }
 
 template <int D, int ST>
@@ -87,7 +91,8 @@ static void launch_tp_batch(BatchArgs A, int count, hipStream_t s) {
     dim3 grid, block;
     step_shape(A.a, grid, block, A.a.g.ny * A.a.g.nz, 1024);
     grid.y = count;
-    hipLaunchKernelGGL((k_step_tp_batch<D, ST>), grid, block, 0, s, A);
+    if (A.a.pitch != A.a.g.nx) hipLaunchKernelGGL((k_step_tp_batch<D, ST, true>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_step_tp_batch<D, ST, false>), grid, block, 0, s, A);
 }
 
 int launch_step_tp_batch(int lattice, int storage, const BatchArgs& A, int count, hipStream_t s) {

@@ -46,7 +46,8 @@ struct Step2Args {
     uint32_t cz;         // planes per z chunk
 };
 
-template <int ST>
+// PAD: x-rows padded to the pitch (otherwise the row stride is nx).
+template <int ST, bool PAD>
 __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
     using S = Store<ST>;
     using T = typename S::T;
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
     const char* __restrict__ src = static_cast<const char*>(a.src);
     char* __restrict__ dst = static_cast<char*>(a.dst);
     const uint64_t plane_bytes = a.g.plane * sizeof(T);
-    const uint32_t rowb = nx * (uint32_t)sizeof(T);
+    const uint32_t rowb = (PAD ? a.pitch : nx) * (uint32_t)sizeof(T);
 
     // First step: region node r of this thread, its pulled x offsets and y rows.
     const bool act1 = t < RN;
@@ -224,10 +225,11 @@ int launch_step2_tp(int lattice, int storage, const StepArgs& a, bool force, hip
     if (a.g.plane * 4 >= (1ull << 31)) return -1;
     const Step2Plan P = step2_plan(a);
     if (!force) {
-        const double single_us = kLaunchUs + (double)a.g.plane * kStepPsPerNode * 1e-6;
+        const double single_us = kLaunchUs + (double)nodes_of(a.g) * kStepPsPerNode * 1e-6;
         if (P.cost_us >= 2.0 * single_us) return -1;
     }
-    hipLaunchKernelGGL((k_step2_tp<kF32>), dim3(P.blocks), dim3(kTbThreads), 0, s, P.A);
+    if (a.pitch != a.g.nx) hipLaunchKernelGGL((k_step2_tp<kF32, true>), dim3(P.blocks), dim3(kTbThreads), 0, s, P.A);
+    else hipLaunchKernelGGL((k_step2_tp<kF32, false>), dim3(P.blocks), dim3(kTbThreads), 0, s, P.A);
     return 0;
 }
 

@@ -268,3 +268,31 @@ def test_run_config_validation(tmp_path):
     for cfg, word in bad:
         with pytest.raises(ValueError, match=word):
             load_config(cfg)
+
+
+def test_state_bytes_pitch_rule(cm):
+    """x-rows are padded to a multiple of 128 bytes when that adds at most one
+    eighth, except D3Q27 FP32 rows that are a multiple of 32 bytes (cmlb.h,
+    layout of the state); host-only query."""
+    cases = [  # lattice, shape (nz, ny, nx), storage, expected pitch
+        ("D3Q27", (250, 250, 250), "f32", 256),
+        ("D3Q27", (4, 6, 252), "f32", 256),      # 1008-byte rows: 16-byte aligned
+        ("D3Q27", (4, 6, 248), "f32", 248),      # 992-byte rows: 32-byte aligned
+        ("D3Q27", (4, 6, 240), "f32", 240),
+        ("D3Q27", (4, 6, 248), "bf16", 256),     # the exception is FP32 only
+        ("D3Q27", (4, 6, 300), "f32", 320),
+        ("D3Q27", (5, 7, 37), "f32", 37),        # padding to 64 would add 73 %
+        ("D3Q27", (8, 8, 256), "f32", 256),
+        ("D3Q27", (4, 6, 250), "f64", 256),
+        ("D3Q27", (4, 6, 250), "bf16", 256),
+        ("D2Q37", (5, 260), "f64", 272),
+        ("D2Q37", (5, 260), "bf16", 260),        # 320 would add 23 %
+        ("D2Q9", (19, 70), "f32", 70),
+    ]
+    elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+    Q = {"D2Q9": 9, "D3Q27": 27, "D2Q37": 37}
+    for lattice, shape, storage, pitch in cases:
+        rows = int(np.prod(shape[:-1]))
+        assert cm.state_bytes(lattice, shape, storage) == Q[lattice] * rows * pitch * elem[storage], (lattice, shape)
+    with pytest.raises(cm.CmlbError):
+        cm.state_bytes("D3Q27", (0, 8, 8))

@@ -35,9 +35,9 @@ def near_eq_state(orc, shape, seed, eps=0.03):
     return S * inputs.perturbation(S.shape, seed + 1, eps)
 
 
-@pytest.mark.parametrize("tie", [False, True])
-def test_closure_step_matches_oracle(cm, orc, tie):
-    shape = (3, 5, 128)
+@pytest.mark.parametrize("tie,shape", [(False, (3, 5, 128)), (True, (3, 5, 128)),
+                                       (False, (2, 3, 300))])   # the last has padded rows
+def test_closure_step_matches_oracle(cm, orc, tie, shape):
     S = near_eq_state(orc, shape, 50)
     S = (S - orc.lattice("D3Q27")["w"][:, None, None, None]).astype(np.float32).astype(np.float64) \
         + orc.lattice("D3Q27")["w"][:, None, None, None]
@@ -140,18 +140,19 @@ def test_training_learns_the_rates(cm, orc):
     assert last < 0.2 * first
 
 
-def test_box_filter(cm, orc):
+@pytest.mark.parametrize("shape", [(8, 8, 16), (4, 2, 300)])   # the second has padded rows
+def test_box_filter(cm, orc, shape):
     import torch
-    shape = (8, 8, 16)
+    nz, ny, nx = shape
     S = near_eq_state(orc, shape, 80)
     w = orc.lattice("D3Q27")["w"]
     ctx = cm.Context("D3Q27", shape, storage="f64")
     ctx.set_populations(S)
-    out = torch.empty(27 * 4 * 4 * 8, dtype=torch.float32, device="cuda")
+    out = torch.empty(27 * (nz // 2) * (ny // 2) * (nx // 2), dtype=torch.float32, device="cuda")
     ctx.box_filter(2, out)
     torch.cuda.synchronize()
     ctx.destroy()
-    ref = (S - w[:, None, None, None]).reshape(27, 4, 2, 4, 2, 8, 2).mean(axis=(2, 4, 6))
+    ref = (S - w[:, None, None, None]).reshape(27, nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(2, 4, 6))
     assert np.abs(out.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-8
 
 

@@ -41,14 +41,19 @@ def tgv512():
 
 
 def sampled_state(ctx, storage, nodes, scale, w):
-    """Stored populations of the given nodes, decoded (f = g / s + w rho0) on the host."""
+    """Stored populations of the given nodes, decoded (f = g / s + w rho0) on the host.
+    The state's x-rows are padded to a pitch (header: layout of the state)."""
     import torch
     _, nbytes, _ = ctx.state()
+    nz, ny, nx = ctx.shape
+    elem = {"f32": 4, "bf16": 2, "f16": 2}[storage]
+    pitch = nbytes // (27 * ny * nz * elem)
     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     ctx.store_state_device(buf)
     ctx.sync()
     g = buf.view(getattr(torch, TORCH_DTYPE[storage])).view(27, -1)
-    sel = g[:, torch.from_numpy(nodes).cuda()].double().cpu().numpy()
+    offs = (nodes // nx) * pitch + nodes % nx
+    sel = g[:, torch.from_numpy(offs).cuda()].double().cpu().numpy()
     del buf, g
     torch.cuda.empty_cache()
     return (sel / scale[:, None] + w[:, None]).T

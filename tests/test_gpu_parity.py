@@ -268,7 +268,8 @@ def test_determinism(cm):
 
 
 @pytest.mark.parametrize("kind,shape,thermal", [("D3Q27", (9, 10, 11), False), ("D2Q37", (12, 13), True),
-                                                ("D2Q9", (20, 17), False)])
+                                                ("D2Q9", (20, 17), False),
+                                                ("D3Q27", (3, 4, 300), False)])   # padded rows
 def test_moments_and_reductions(cm, orc, kind, shape, thermal):
     from oracle.analysis import globals_of_state
     S = random_state(orc, kind, shape, 44, thermal)
@@ -325,16 +326,17 @@ def test_error_paths(cm):
     ctx.destroy()
 
 
-def test_external_buffers_match_internal(cm):
+@pytest.mark.parametrize("shape", [(16, 16, 16), (4, 6, 250)])   # the second has padded rows
+def test_external_buffers_match_internal(cm, shape):
     import torch
-    n = 16
-    rho, u = inputs.tgv3d(n, 0.05)
-    nbytes = 27 * n ** 3 * 4
+    rho, u = inputs.random_fields(shape, 3, drho=0.02, umax=0.04)[:2]
+    nbytes = cm.state_bytes("D3Q27", shape, "f32")
+    assert nbytes >= 27 * int(np.prod(shape)) * 4
     bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    a = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.7}, external=bufs, stream=stream)
-    b = cm.Context("D3Q27", (n, n, n), storage="f32", tau={2: 0.7})
+    a = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.7}, external=bufs, stream=stream)
+    b = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.7})
     for c in (a, b):
         c.init_fields(rho, u)
         c.step(7)
@@ -343,7 +345,7 @@ def test_external_buffers_match_internal(cm):
     assert ptr in (bufs[0].data_ptr(), bufs[1].data_ptr()) and size == nbytes
     assert s == stream.cuda_stream
     with pytest.raises(ValueError):
-        cm.Context("D3Q27", (n, n, n), stream=torch.cuda.default_stream())
+        cm.Context("D3Q27", shape, stream=torch.cuda.default_stream())
     a.destroy()
     b.destroy()
 
@@ -367,6 +369,36 @@ def test_device_fields_on_torch_stream(cm, orc):
     orc.run(cfg, S, 3)
     _, o_u, _ = orc.moments("D3Q27", S)
     assert np.abs(g_u - o_u).max() < 1e-13
+
+
+@pytest.mark.parametrize("kind,shape,storage,thermal", [("D3Q27", (2, 3, 300), "f32", False),
+                                                        ("D2Q37", (4, 260), "f64", True)])
+def test_init_fields_on_padded_rows(cm, orc, kind, shape, storage, thermal):
+    """Equilibrium initialisation, moments and one step on a state whose
+    x-rows are padded to the pitch (header: layout of the state)."""
+    rho, u, th = inputs.random_fields(shape, 47, drho=0.03, umax=0.05, dtheta=0.03 if thermal else 0.0)
+    elem = {"f64": 8, "f32": 4}[storage]
+    assert cm.state_bytes(kind, shape, storage) > orc.lattice(kind)["Q"] * int(np.prod(shape)) * elem
+    ctx = cm.Context(kind, shape, storage=storage, thermal=thermal, tau={2: 0.7, 3: 0.9, 4: 0.8})
+    try:
+        ctx.init_fields(rho, u, th if thermal else None)
+        S0 = ctx.get_populations()
+        g_rho, g_u, g_th = ctx.get_moments()
+        ctx.step(1)
+        S1 = ctx.get_populations()
+    finally:
+        ctx.destroy()
+    cfg = orc.Cfg(lattice=kind, tau={2: 0.7, 3: 0.9, 4: 0.8}, thermal=thermal)
+    ref = orc.init_equilibrium(cfg, rho, u, th if thermal else None)
+    w = orc.lattice(kind)["w"].reshape((-1,) + (1,) * len(shape))
+    dev = np.abs(ref - w).max()
+    assert np.abs(S0 - ref).max() <= TOL[storage] * dev
+    o_rho, o_u, o_th = orc.moments(kind, S0)
+    assert np.abs(g_rho - o_rho).max() < 1e-13 and np.abs(g_u - o_u).max() < 1e-13
+    if thermal:
+        assert np.abs(g_th - o_th).max() < 1e-12
+    orc.run(cfg, S0, 1)
+    assert np.abs(S1 - S0).max() <= TOL[storage] * dev
 
 
 def test_set_tau_changes_rates(cm, orc):
@@ -584,6 +616,8 @@ BATCH_CASES = [
     ("D3Q27", (6, 10, 70), "f32", "cm", False),
     ("D3Q27", (5, 7, 37), "bf16", "cm", False),
     ("D2Q9", (19, 70), "f32", "cm", False),
+    ("D3Q27", (3, 4, 300), "f32", "cm", False),    # padded rows
+    ("D2Q37", (5, 260), "f32", "cm", True),        # padded rows
 ]
 
 
