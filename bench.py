@@ -184,7 +184,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
-                    help="2: pairs of D3Q27 steps in one launch where supported (default); 1: one launch per step")
+                    help="2: pairs of FP32 steps (D3Q27, D2Q37) in one launch (default); 1: one launch per step")
     ap.add_argument("--workload", default="tgv256_f32", choices=sorted(WORKLOADS),
                     help="default: the D3Q27 256^3 FP32 Taylor-Green benchmark; others report the precision "
                          "form and the thermal lattice with the same JSON fields")
@@ -275,8 +275,8 @@ def run(torch, cmlb, inputs, stream, args):
     ctx, bufs, mass0, taus, desc, nodes, q, sb = setup_workload(args.workload, torch, cmlb, inputs, stream)
     lattice, shape, storage, _ = WORKLOADS[args.workload]
     closure = args.workload.endswith("closure_f32")
-    # pairs of D3Q27 steps run as one launch (intermediate state on chip)
-    fused = lattice == "D3Q27" and storage == "f32" and not closure and args.steps_per_launch == 2
+    # pairs of FP32 steps run as one launch (intermediate state on chip)
+    fused = storage == "f32" and not closure and args.steps_per_launch == 2
     ctx.set_step_fusion(args.steps_per_launch)
 
     ctx.step(args.warmup)
@@ -328,8 +328,10 @@ def run(torch, cmlb, inputs, stream, args):
     alg_bytes = per_node * nodes * updates_per_launch
     achieved = per_node * nodes * args.steps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     traffic = measured_traffic(alg_bytes) if (args.workload == "tgv256_f32" and fused) else None
-    if fused:
+    if fused and lattice == "D3Q27":
         kernel = "k_step2_tp<%s>" % STORAGE_TAG[storage]
+    elif fused:
+        kernel = "k_step2_d37<%s>" % MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")]
     elif lattice == "D3Q27":
         kernel = "k_step_tp<3, %s>" % STORAGE_TAG[storage]
     else:

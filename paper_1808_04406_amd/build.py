@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcmlb.so")
-SOURCES = ["step_tp.hip", "step_tp2.hip", "step_d37.hip", "kernels.hip", "kernels_closure.hip", "api.cpp"]
+SOURCES = ["step_tp.hip", "step_tp2.hip", "step_d37.hip", "step2_d37.hip", "kernels.hip", "kernels_closure.hip", "api.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -486,7 +486,7 @@ static int enqueue_steps(cmlb_ctx* c, int64_t n) {
         if (c->closure_on) {
             launch_step_closure(a, c->cl_net, c->stream);
         } else if (c->fuse != 1 && n - k >= 2 &&
-                   launch_step2_tp(c->p.lattice, c->p.storage, a, c->fuse == 2, c->stream) == 0) {
+                   launch_step2(c->p.lattice, c->p.storage, c->p.model, a, c->fuse == 2, c->stream) == 0) {
             adv = 2;
         } else if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream)) {
             return fail(c, CMLB_EINVAL, "unsupported configuration");

@@ -40,6 +40,10 @@ int launch_step_d37_batch(int storage, int model, const BatchArgs& A, int count,
 // configuration is not supported or, unless force is set, if two single-step
 // launches are expected to be faster.
 int launch_step2_tp(int lattice, int storage, const StepArgs& a, bool force, hipStream_t s);
+// Two steps in one launch on D2Q37 with FP32 storage (step2_d37.hip); same contract.
+int launch_step2_d37(int storage, int model, const StepArgs& a, bool force, hipStream_t s);
+// Two steps in one launch where supported (either of the above); same contract.
+int launch_step2(int lattice, int storage, int model, const StepArgs& a, bool force, hipStream_t s);
 int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_codec(int lattice, int storage, bool decode, void* stor, double* full, const StepArgs& a,

@@ -476,6 +476,42 @@ def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
         assert np.array_equal(out[1][1], out[k][1])
 
 
+D37_FUSION_CASES = [
+    ((13, 41), "cm", True),          # one segment, ragged; rows fewer than a chunk's lead-in
+    ((5, 260), "cm", True),          # three segments, padded rows
+    ((3, 3), "cm", True),            # smallest grid: every shift wraps more than once
+    ((130, 250), "raw_mrt", True),   # several segments, one-row chunks
+    ((301, 250), "cm", True),        # two-row chunks, the last one ragged
+    ((61, 122), "reg_bgk", False),   # one full segment, isothermal
+    ((24, 7), "cm", False),
+]
+
+
+@pytest.mark.parametrize("shape,model,thermal", D37_FUSION_CASES)
+def test_two_step_launch_equals_single_steps_d37(cm, orc, shape, model, thermal):
+    """Pairs of D2Q37 FP32 steps in one launch (first-step rows kept in LDS)
+    give bitwise the same populations as one launch per step, for each
+    collision model; odd counts end with a single step."""
+    S = random_state(orc, "D2Q37", shape, seed=sum(shape) + 5, thermal=thermal)
+    tau = taus("D2Q37", seed=shape[-1] + 1)
+    out = {}
+    for fuse in (1, 2, 0):
+        ctx = cm.Context("D2Q37", shape, storage="f32", model=model, thermal=thermal, tau=tau)
+        try:
+            ctx.set_step_fusion(fuse)
+            ctx.set_populations(S)
+            ctx.step(2)
+            a = ctx.get_populations()
+            ctx.step(5)
+            out[fuse] = (a, ctx.get_populations(), ctx.step_count())
+        finally:
+            ctx.destroy()
+    assert out[1][2] == out[2][2] == out[0][2] == 7
+    for k in (0, 2):
+        assert np.array_equal(out[1][0], out[k][0])
+        assert np.array_equal(out[1][1], out[k][1])
+
+
 @pytest.mark.parametrize("storage", ["f64", "bf16"])
 def test_two_step_launch_options(cm, storage):
     ctx = cm.Context("D3Q27", (4, 4, 4), storage=storage, tau={2: 0.6})
