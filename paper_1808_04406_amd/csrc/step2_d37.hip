@@ -62,7 +62,10 @@ constexpr D37Ring make_d37_ring() {
 }
 inline constexpr D37Ring kRing37 = make_d37_ring();
 static_assert(kRing37.total == kD2Rows, "D2Q37 ring rows");
-static_assert(2 * kD2Rows * kD2Threads * 4 <= 160 * 1024, "two workgroups share a CU's LDS");
+// Workgroups that share a CU's 160 KB of LDS, and the workgroups of one full round.
+constexpr int kD2PerCU = (160 * 1024) / (kD2Rows * kD2Threads * 4);
+constexpr uint32_t kD2Slots = 256u * kD2PerCU;
+static_assert(kD2PerCU >= 1, "one workgroup fits a CU's LDS");
 
 struct Step2D37Args {
     StepArgs a;
@@ -228,8 +231,8 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
 // ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
-// Two 128-thread workgroups share a CU's LDS, so a launch of B workgroups
-// runs in ceil(B / 512) rounds of (cy + 6) iterations.  The row chunking
+// kD2PerCU workgroups share a CU's LDS, so a launch of B workgroups runs in
+// ceil(B / kD2Slots) rounds of (cy + 6) iterations.  The row chunking
 // is the one with the lowest modelled time; the model also decides, in
 // automatic mode, between this kernel and two single steps.
 constexpr double kD2ItUs = 3.8, kD2LaunchUs = 3.0, kD2StepPsPerNode = 52.0;
@@ -258,7 +261,7 @@ Step2D37Plan step2_d37_plan(const StepArgs& a) {
     for (uint32_t nc = 1; nc <= a.g.ny && nc <= 8192; ++nc) {
         const uint32_t cy = (a.g.ny + nc - 1) / nc;
         if ((a.g.ny + cy - 1) / cy != nc) continue;   // the same chunking as a smaller count
-        const double rounds = (double)(((uint64_t)P.A.ntx * nc + 511) / 512);
+        const double rounds = (double)(((uint64_t)P.A.ntx * nc + kD2Slots - 1) / kD2Slots);
         const double tm = rounds * (cy + 6) * kD2ItUs;
         if (nc == 1 || tm < best) { best = tm; best_cy = cy; }
     }

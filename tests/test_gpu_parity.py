@@ -594,7 +594,7 @@ def test_checkpoint_resume_is_bitwise(cm, orc, tmp_path, kind, shape, storage, t
 
 @pytest.mark.parametrize("kind,shape,thermal,closure", [
     ("D3Q27", (12, 10, 70), False, False),   # two steps per launch
-    ("D2Q37", (24, 40), True, False),
+    ("D2Q37", (24, 40), True, False),        # two steps per launch
     ("D3Q27", (4, 8, 64), False, True),      # learned closure, one step per launch
 ])
 def test_graph_replay_equals_direct_launches(cm, orc, kind, shape, thermal, closure):
@@ -607,7 +607,7 @@ def test_graph_replay_equals_direct_launches(cm, orc, kind, shape, thermal, clos
     ctxs = [cm.Context(kind, shape, storage="f32", thermal=thermal, tau=tau) for _ in range(2)]
     try:
         for c in ctxs:
-            c.set_step_fusion(2)   # two-step launches on D3Q27 without the closure
+            c.set_step_fusion(2)   # two-step launches where supported (FP32, closure off)
         ctxs[1].set_graph_steps(8)
         P = 0.3 * np.random.default_rng(4).normal(size=cm.CLOSURE_NPARAM)
         for c in ctxs:
