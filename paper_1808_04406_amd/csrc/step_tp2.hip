@@ -33,6 +33,8 @@
 
 #include "collide_tp.hpp"
 
+#include <algorithm>
+
 namespace cmlb {
 
 constexpr int kTbTX = 64, kTbTY = 8, kTbThreads = 704;
@@ -173,9 +175,14 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
 // 3.55 us and a second-step one 2.75 us; half of that time scales with the
 // fraction of tile nodes inside the grid (ragged tiles move less data); a
 // launch costs 3 us.  The z chunking is the one with the lowest modelled
-// time.  A single step costs 3 us plus 38 ps per node (its HBM rate), which
-// decides, in automatic mode, between this kernel and two single steps.
+// time among chunks of at most 128 planes: at 512^3 longer chunks ran
+// slower than the model predicts (one chunk of 512 planes: 36,600 MLUPS;
+// four of 128: 39,100; eight of 64: 39,800), while at 256^3 the model's
+// two chunks of 128 planes are the fastest.  A single step costs 3 us plus
+// 38 ps per node (its HBM rate), which decides, in automatic mode, between
+// this kernel and two single steps.
 constexpr double kTb1Us = 3.55, kTb2Us = 2.75, kLaunchUs = 3.0, kStepPsPerNode = 38.0;
+constexpr uint32_t kTbMaxChunk = 128;
 
 namespace {
 struct Step2Plan {
@@ -200,15 +207,21 @@ Step2Plan step2_plan(const StepArgs& a) {
     const uint64_t tiles = (uint64_t)P.A.ntx * P.A.nty;
     const double fill = (double)a.g.nx * a.g.ny / ((double)tiles * kTbTX * kTbTY);
     const double scale = 0.5 + 0.5 * fill;
-    double best = 0.0;
-    uint32_t best_cz = a.g.nz;
-    // beyond 4096 chunks every count needs more rounds than it saves planes
-    for (uint32_t nzc = 1; nzc <= a.g.nz && nzc <= 4096; ++nzc) {
+    auto model_us = [&](uint32_t cz) {
+        const uint64_t nzc = (a.g.nz + cz - 1) / cz;
+        const double rounds = (double)((tiles * nzc + 255) / 256);
+        return rounds * ((cz + 2) * kTb1Us + cz * kTb2Us) * scale;
+    };
+    // counts from the fewest chunks of at most kTbMaxChunk planes; beyond
+    // 4096 chunks every count needs more rounds than it saves planes
+    const uint32_t nzc0 = std::min(std::min((a.g.nz + kTbMaxChunk - 1) / kTbMaxChunk, a.g.nz), 4096u);
+    uint32_t best_cz = (a.g.nz + nzc0 - 1) / nzc0;
+    double best = model_us(best_cz);
+    for (uint32_t nzc = nzc0 + 1; nzc <= a.g.nz && nzc <= 4096; ++nzc) {
         const uint32_t cz = (a.g.nz + nzc - 1) / nzc;
         if ((a.g.nz + cz - 1) / cz != nzc) continue;   // the same chunking as a smaller count
-        const double rounds = (double)((tiles * nzc + 255) / 256);
-        const double t = rounds * ((cz + 2) * kTb1Us + cz * kTb2Us) * scale;
-        if (nzc == 1 || t < best) { best = t; best_cz = cz; }
+        const double t = model_us(cz);
+        if (t < best) { best = t; best_cz = cz; }
     }
     P.A.cz = best_cz;
     P.blocks = (uint32_t)(tiles * ((a.g.nz + best_cz - 1) / best_cz));
