@@ -65,7 +65,12 @@ __device__ __forceinline__ void closure_rates(const ClosureNet* net, const float
 // the network (the matrix instructions need full wavefronts), lanes past the
 // end of a row compute on a clamped node and do not store.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_step_closure(StepArgs a, const ClosureNet* __restrict__ net) {
+// Four waves per SIMD: the compiler then keeps the MFMA accumulators in
+// VGPRs (128, two of them spilled) instead of 84 VGPRs and 48 AGPRs at three
+// waves, which removes 80 accumulator reads per wave; measured 5 % faster at
+// 128^3.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_step_closure(StepArgs a, const ClosureNet* __restrict__ net) {
     using T = float;
     __shared__ __bf16 xs_all[4][64 * 40];
     const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
