@@ -135,6 +135,61 @@ def test_thermal_waves_1024_two_steps(cm, orc):
     assert err <= 2 * TOL["f32"] * dev
 
 
+def test_thermal_two_step_past_2gib(cm, orc):
+    """D2Q37 4096^2 FP32 (a 2.48 GB state, so population offsets pass 2^31
+    in the two-step kernel's 32-bit buffer addressing): two steps in one
+    launch equal two single-step launches bitwise, compared on the device;
+    a few nodes are also checked against the oracle's step."""
+    import torch
+    n, amp = 4096, 0.01
+    r = cm.lattice_info("D2Q37")["r"]
+    tau = {2: 0.6, 3: 0.55, 4: 0.6}
+    rho, u, th = inputs.waves2d(n, n, shear_amp=amp / r, thermal_amp=amp, k=(3, 1), background=(0.0, 0.1))
+    nbytes = cm.state_bytes("D2Q37", (n, n), "f32")
+    assert nbytes >= 2 ** 31
+    out = []
+    for fuse in (1, 2):
+        ctx = cm.Context("D2Q37", (n, n), storage="f32", thermal=True, tau=tau)
+        try:
+            ctx.set_step_fusion(fuse)
+            ctx.init_fields(rho, u, th)
+            ctx.step(2)
+            buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            ctx.store_state_device(buf)
+            ctx.sync()
+            out.append(buf)
+        finally:
+            ctx.destroy()
+    assert torch.equal(out[0], out[1])
+    # the last population planes (offsets past 2^31) against the oracle at sampled nodes
+    g = out[1].view(torch.float32).view(37, -1)
+    nodes = np.array([0, n - 1, n * n // 2 + 17, n * n - 1, 12345678], dtype=np.int64)
+    got = g[:, torch.from_numpy(nodes).cuda()].double().cpu().numpy().T
+    del out, g, buf
+    torch.cuda.empty_cache()
+    cfg = orc.Cfg(lattice="D2Q37", tau=tau, thermal=True)
+    w = orc.lattice("D2Q37")["w"]
+    e = orc.lattice("D2Q37")["e"][:, :2]
+    # FP32-stored state after one step at the 7 x 7 neighbourhoods, then the second step
+    pos = np.stack([nodes % n, nodes // n], 1)
+    ref = []
+    for x, y in pos:
+        xs = (x + np.arange(-6, 7)) % n
+        ys = (y + np.arange(-6, 7)) % n
+        S0 = orc.init_equilibrium(cfg, rho[np.ix_(ys, xs)], u[:, ys][:, :, xs], th[np.ix_(ys, xs)])
+        S0 = quantise(S0 - w[:, None, None], "f32") + w[:, None, None]
+        S1 = S0.copy()
+        orc.run(cfg, S1, 1)
+        S1 = quantise(S1 - w[:, None, None], "f32") + w[:, None, None]
+        orc.run(cfg, S1, 1)
+        ref.append(S1[:, 6, 6])
+    ref = np.array(ref)
+    err = np.abs(got + w[None, :] - ref).max()
+    dev = np.abs(ref - w[None, :]).max()
+    print(f"D2Q37 4096^2 two steps, sampled: max|df| = {err:.3e} (deviation scale {dev:.3e})")
+    assert err <= 2 * TOL["f32"] * dev
+
+
 def test_closure_128_sampled(cm, orc):
     n, u0, re = 128, 0.05, 1.0e5
     rho, u = inputs.tgv3d(n, u0)
