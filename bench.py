@@ -184,7 +184,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
-                    help="2: pairs of FP32 steps (D3Q27, D2Q37) in one launch (default); 1: one launch per step")
+                    help="2: pairs of steps in one launch where supported (D3Q27 FP32/FP64, D2Q37 FP32; default); "
+                         "1: one launch per step")
     ap.add_argument("--workload", default="tgv256_f32", choices=sorted(WORKLOADS),
                     help="default: the D3Q27 256^3 FP32 Taylor-Green benchmark; others report the precision "
                          "form and the thermal lattice with the same JSON fields")
@@ -275,8 +276,10 @@ def run(torch, cmlb, inputs, stream, args):
     ctx, bufs, mass0, taus, desc, nodes, q, sb = setup_workload(args.workload, torch, cmlb, inputs, stream)
     lattice, shape, storage, _ = WORKLOADS[args.workload]
     closure = args.workload.endswith("closure_f32")
-    # pairs of FP32 steps run as one launch (intermediate state on chip)
-    fused = storage == "f32" and not closure and args.steps_per_launch == 2
+    # pairs of steps run as one launch (intermediate state on chip): D3Q27
+    # FP32 and FP64, D2Q37 FP32
+    fused = (storage == "f32" or (lattice == "D3Q27" and storage == "f64")) and not closure \
+        and args.steps_per_launch == 2
     ctx.set_step_fusion(args.steps_per_launch)
 
     ctx.step(args.warmup)

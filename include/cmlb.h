@@ -175,15 +175,17 @@ int cmlb_init_fields(cmlb_ctx *ctx, const double *rho, const double *u, const do
 int cmlb_init_fields_device(cmlb_ctx *ctx, const double *rho, const double *u, const double *theta);
 
 /* Enqueue n stream-and-collide steps on the context stream (asynchronous).
- * On D3Q27 and D2Q37 with FP32 storage (learned closure off) pairs of steps
- * run as one launch that keeps the intermediate state on chip; the result is
- * identical to single steps (see cmlb_set_step_fusion). */
+ * On D3Q27 with FP32 or FP64 storage and on D2Q37 with FP32 storage
+ * (learned closure off) pairs of steps run as one launch that keeps the
+ * intermediate state on chip; the result is identical to single steps (see
+ * cmlb_set_step_fusion). */
 int cmlb_step(cmlb_ctx *ctx, int64_t n);
 
 /* Steps per kernel launch for cmlb_step.  Two steps per launch are
- * supported with FP32 storage on D3Q27 (learned closure off) and on D2Q37
- * (every collision model, state below 4 GiB); elsewhere every value
- * launches one kernel per step.
+ * supported on D3Q27 with FP32 or FP64 storage (learned closure off,
+ * population planes below 2 GiB) and on D2Q37 with FP32 storage (every
+ * collision model, state below 4 GiB); elsewhere every value launches one
+ * kernel per step.
  *   0 (default)  automatic: two steps per launch where supported, unless a
  *                cost model of the grid's launch shape expects two single
  *                launches to be faster (small grids);

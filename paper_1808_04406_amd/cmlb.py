@@ -270,7 +270,7 @@ class Context:
         self._check(lib().cmlb_set_graph_steps(self.h, int(steps)))
 
     def set_step_fusion(self, steps_per_launch):
-        """0 (default): automatic; 1: one launch per step; 2: pairs of FP32 steps (D3Q27, D2Q37) in one launch."""
+        """0 (default): automatic; 1: one launch per step; 2: pairs of steps in one launch (D3Q27 FP32/FP64, D2Q37 FP32)."""
         self._check(lib().cmlb_set_step_fusion(self.h, int(steps_per_launch)))
 
     def sync(self):

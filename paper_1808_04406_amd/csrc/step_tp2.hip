@@ -25,10 +25,11 @@
 // arithmetic is the single-step kernel's, node by node, so the result equals
 // two single steps exactly.
 //
-// Only FP32 storage takes this path. With 16-bit storage one step per launch
-// moves 108 B per update and is faster than this kernel, whose rate is set by
-// its arithmetic and barriers rather than by HBM (measured at 256^3 and
-// 512^3: about 46,000 MLUPS against 27,000-31,000).
+// FP32 and FP64 storage take this path (FP64 with a 32 x 8 tile, whose 54
+// doubles per region node fill the same LDS). With 16-bit storage one step
+// per launch moves 108 B per update and is faster than this kernel, whose
+// rate is set by its arithmetic and barriers rather than by HBM (measured at
+// 256^3 and 512^3: about 46,000 MLUPS against 27,000-31,000).
 #include "launch.hpp"
 
 #include "collide_tp.hpp"
@@ -37,10 +38,27 @@
 
 namespace cmlb {
 
-constexpr int kTbTX = 64, kTbTY = 8, kTbThreads = 704;
-constexpr int kTbRX = kTbTX + 2, kTbRY = kTbTY + 2, kTbRN = kTbRX * kTbRY;
-static_assert(kTbThreads >= kTbRN && kTbThreads >= kTbTX * kTbTY && kTbThreads % 64 == 0, "tile threads");
-static_assert(54 * kTbRN * 4 <= 160 * 1024, "LDS of one CU");
+// Tile of one workgroup by storage: TX x TY nodes, a region of
+// (TX + 2) x (TY + 2), 54 values per region node in LDS.  FP32: 64 x 8 in
+// 142,560 B; FP64: 32 x 8 in 146,880 B.
+template <int ST>
+struct Tb2Geom;
+template <>
+struct Tb2Geom<kF32> {
+    static constexpr int TX = 64, TY = 8, Threads = 704;
+};
+template <>
+struct Tb2Geom<kF64> {
+    static constexpr int TX = 32, TY = 8, Threads = 384;
+};
+template <int ST>
+struct Tb2Tile : Tb2Geom<ST> {
+    using G = Tb2Geom<ST>;
+    static constexpr int RX = G::TX + 2, RY = G::TY + 2, RN = RX * RY;
+    static constexpr int LdsBytes = 54 * RN * (int)sizeof(typename Store<ST>::R);
+    static_assert(G::Threads >= RN && G::Threads >= G::TX * G::TY && G::Threads % 64 == 0, "tile threads");
+    static_assert(LdsBytes <= 160 * 1024, "LDS of one CU");
+};
 
 struct Step2Args {
     StepArgs a;
@@ -50,15 +68,17 @@ struct Step2Args {
 
 // PAD: x-rows padded to the pitch (otherwise the row stride is nx).
 template <int ST, bool PAD>
-__global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
+__global__ __launch_bounds__(Tb2Geom<ST>::Threads) void k_step2_tp(Step2Args A) {
     using S = Store<ST>;
     using T = typename S::T;
-    static_assert(!S::kScaled && sizeof(typename S::R) == 4, "unscaled FP32 arithmetic only");
-    constexpr int TX = kTbTX, TY = kTbTY, RX = kTbRX, RN = kTbRN;
-    __shared__ float lds[54 * RN];
-    float* sD = lds;             // [9][RN]     e_z = -1 group, plane q
-    float* sM = lds + 9 * RN;    // [2][9][RN]  e_z =  0 group, planes q, q - 1
-    float* sU = lds + 27 * RN;   // [3][9][RN]  e_z = +1 group, planes q, q - 1, q - 2
+    using R = typename S::R;
+    using Tile = Tb2Tile<ST>;
+    static_assert(!S::kScaled && sizeof(R) == sizeof(T), "unscaled storage of the arithmetic type only");
+    constexpr int TX = Tile::TX, TY = Tile::TY, RX = Tile::RX, RN = Tile::RN;
+    __shared__ R lds[54 * RN];
+    R* sD = lds;             // [9][RN]     e_z = -1 group, plane q
+    R* sM = lds + 9 * RN;    // [2][9][RN]  e_z =  0 group, planes q, q - 1
+    R* sU = lds + 27 * RN;   // [3][9][RN]  e_z = +1 group, planes q, q - 1, q - 2
     const StepArgs& a = A.a;
     const uint32_t nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
 
@@ -90,11 +110,11 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
     const bool act2 = in2 && gx2 < nx && gy2 < ny;
     const int rc2 = (iy + 1) * RX + (ix + 1);
 
-    float om[8];
-    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = (float)a.omega[decltype(N)::value]; });
-    const float rho0 = (float)a.rho0;
+    R om[8];
+    static_for<0, 8>([&](auto N) { om[decltype(N)::value] = R(a.omega[decltype(N)::value]); });
+    const R rho0 = R(a.rho0);
 
-    auto load_state = [&](float (&h)[27], uint32_t qz) {
+    auto load_state = [&](R (&h)[27], uint32_t qz) {
         const uint32_t zs[3] = {wrap_inc(qz, nz), qz, wrap_dec(qz, nz)};
         static_for<0, 27>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -106,39 +126,38 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
     const int J = (int)(zend - z0) + 1;   // iterations j = 0..J: first step at plane z0 - 1 + j
     // Iteration j: first step of plane z0 - 1 + j from h (then h <- the state
     // pulled for plane z0 + 1 + j), second step of plane z0 - 2 + j.
-    auto iteration = [&](int j, float (&h)[27], uint32_t qz_ahead) {
+    auto iteration = [&](int j, R (&h)[27], uint32_t qz_ahead) {
         if (act1) {
-            tp_collide<3, float>(h, rho0, om);
-            float* pM = sM + (j & 1) * 9 * RN;
-            float* pU = sU + (j % 3) * 9 * RN;
+            tp_collide<3, R>(h, rho0, om);
+            R* pM = sM + (j & 1) * 9 * RN;
+            R* pU = sU + (j % 3) * 9 * RN;
             static_for<0, 27>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                float v = h[i];
+                R v = h[i];
                 v = S::round(v);
-                float* slot = i < 9 ? sD : (i < 18 ? pM : pU);
+                R* slot = i < 9 ? sD : (i < 18 ? pM : pU);
                 slot[(i % 9) * RN + r] = v;
             });
             if (j + 2 <= J) load_state(h, qz_ahead);
         }
         __syncthreads();
         if (j >= 2 && in2) {
-            const float* pM = sM + ((j - 1) & 1) * 9 * RN;
-            const float* pU = sU + ((j - 2) % 3) * 9 * RN;
-            float g[27];
+            const R* pM = sM + ((j - 1) & 1) * 9 * RN;
+            const R* pU = sU + ((j - 2) % 3) * 9 * RN;
+            R g[27];
             static_for<0, 27>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
-                const float* slot = ez == -1 ? sD : (ez == 0 ? pM : pU);
+                const R* slot = ez == -1 ? sD : (ez == 0 ? pM : pU);
                 g[i] = slot[(i % 9) * RN + rc2 - ey * RX - ex];
             });
-            tp_collide<3, float>(g, rho0, om);
+            tp_collide<3, R>(g, rho0, om);
             if (act2) {
                 const uint32_t p = z0 + (uint32_t)j - 2;
                 const uint32_t off = (p * ny + gy2) * rowb + gx2 * (uint32_t)sizeof(T);
                 static_for<0, 27>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    float v = g[i];
-                    S::store(reinterpret_cast<T*>(dst + i * plane_bytes + off), v);
+                    S::store(reinterpret_cast<T*>(dst + i * plane_bytes + off), g[i]);
                 });
             }
         }
@@ -147,7 +166,7 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
 
     // Two register sets alternate so that the state for iteration j + 2 is in
     // flight during iteration j + 1.
-    float ha[27], hb[27];
+    R ha[27], hb[27];
     const uint32_t q0 = (z0 + nz - 1) % nz, q1 = wrap_inc(q0, nz);
     if (act1) {
         load_state(ha, q0);
@@ -165,8 +184,8 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
 // ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
-// One 704-thread workgroup fills a CU's LDS, so a launch of B workgroups runs
-// in ceil(B / 256) rounds.  A workgroup whose chunk has cz planes makes
+// One workgroup (704 threads for FP32, 384 for FP64) fills a CU's LDS, so a
+// launch of B workgroups runs in ceil(B / 256) rounds.  A workgroup whose chunk has cz planes makes
 // cz + 2 first-step iterations (its first step starts one plane below the
 // chunk and ends one plane above it) and cz second-step iterations.
 //
@@ -180,8 +199,15 @@ __global__ __launch_bounds__(kTbThreads) void k_step2_tp(Step2Args A) {
 // four of 128: 39,100; eight of 64: 39,800), while at 256^3 the model's
 // two chunks of 128 planes are the fastest.  A single step costs 3 us plus
 // 38 ps per node (its HBM rate), which decides, in automatic mode, between
-// this kernel and two single steps.
-constexpr double kTb1Us = 3.55, kTb2Us = 2.75, kLaunchUs = 3.0, kStepPsPerNode = 38.0;
+// this kernel and two single steps.  FP64 (32 x 8 tiles): 4.6 and 2.8 us per
+// iteration, 84 ps per node for a single step.
+struct Tb2Cost {
+    double it1_us, it2_us;     // first- and second-step iteration of a full round
+    double step_ps_per_node;   // one single-step launch, per node
+};
+constexpr Tb2Cost kTbCostF32 = {3.55, 2.75, 38.0};
+constexpr Tb2Cost kTbCostF64 = {4.6, 2.8, 84.0};   // fitted at 256^3 and 512^3
+constexpr double kLaunchUs = 3.0;
 constexpr uint32_t kTbMaxChunk = 128;
 
 namespace {
@@ -191,7 +217,9 @@ struct Step2Plan {
     double cost_us;   // model time of the launch
 };
 
-Step2Plan step2_plan(const StepArgs& a) {
+template <int ST>
+Step2Plan step2_plan(const StepArgs& a, const Tb2Cost& cost) {
+    using Tile = Tb2Tile<ST>;
     // the plan depends on the grid only; callers step one grid many times
     thread_local uint32_t key[3] = {0, 0, 0};
     thread_local Step2Plan last;
@@ -202,15 +230,15 @@ Step2Plan step2_plan(const StepArgs& a) {
     }
     Step2Plan P;
     P.A.a = a;
-    P.A.ntx = (a.g.nx + kTbTX - 1) / kTbTX;
-    P.A.nty = (a.g.ny + kTbTY - 1) / kTbTY;
+    P.A.ntx = (a.g.nx + Tile::TX - 1) / Tile::TX;
+    P.A.nty = (a.g.ny + Tile::TY - 1) / Tile::TY;
     const uint64_t tiles = (uint64_t)P.A.ntx * P.A.nty;
-    const double fill = (double)a.g.nx * a.g.ny / ((double)tiles * kTbTX * kTbTY);
+    const double fill = (double)a.g.nx * a.g.ny / ((double)tiles * Tile::TX * Tile::TY);
     const double scale = 0.5 + 0.5 * fill;
     auto model_us = [&](uint32_t cz) {
         const uint64_t nzc = (a.g.nz + cz - 1) / cz;
         const double rounds = (double)((tiles * nzc + 255) / 256);
-        return rounds * ((cz + 2) * kTb1Us + cz * kTb2Us) * scale;
+        return rounds * ((cz + 2) * cost.it1_us + cz * cost.it2_us) * scale;
     };
     // counts from the fewest chunks of at most kTbMaxChunk planes; beyond
     // 4096 chunks every count needs more rounds than it saves planes
@@ -230,20 +258,28 @@ Step2Plan step2_plan(const StepArgs& a) {
     last = P;
     return P;
 }
+
+template <int ST>
+int launch2(const StepArgs& a, const Tb2Cost& cost, bool force, hipStream_t s) {
+    // lane byte offsets within a population plane are 32-bit
+    if (a.g.plane * sizeof(typename Store<ST>::T) >= (1ull << 31)) return -1;
+    const Step2Plan P = step2_plan<ST>(a, cost);
+    if (!force) {
+        const double single_us = kLaunchUs + (double)nodes_of(a.g) * cost.step_ps_per_node * 1e-6;
+        if (P.cost_us >= 2.0 * single_us) return -1;
+    }
+    constexpr int threads = Tb2Geom<ST>::Threads;
+    if (a.pitch != a.g.nx) hipLaunchKernelGGL((k_step2_tp<ST, true>), dim3(P.blocks), dim3(threads), 0, s, P.A);
+    else hipLaunchKernelGGL((k_step2_tp<ST, false>), dim3(P.blocks), dim3(threads), 0, s, P.A);
+    return 0;
+}
 }  // namespace
 
 int launch_step2_tp(int lattice, int storage, const StepArgs& a, bool force, hipStream_t s) {
-    if (lattice != kD3Q27 || storage != kF32) return -1;
-    // lane byte offsets within a population plane are 32-bit
-    if (a.g.plane * 4 >= (1ull << 31)) return -1;
-    const Step2Plan P = step2_plan(a);
-    if (!force) {
-        const double single_us = kLaunchUs + (double)nodes_of(a.g) * kStepPsPerNode * 1e-6;
-        if (P.cost_us >= 2.0 * single_us) return -1;
-    }
-    if (a.pitch != a.g.nx) hipLaunchKernelGGL((k_step2_tp<kF32, true>), dim3(P.blocks), dim3(kTbThreads), 0, s, P.A);
-    else hipLaunchKernelGGL((k_step2_tp<kF32, false>), dim3(P.blocks), dim3(kTbThreads), 0, s, P.A);
-    return 0;
+    if (lattice != kD3Q27) return -1;
+    if (storage == kF32) return launch2<kF32>(a, kTbCostF32, force, s);
+    if (storage == kF64) return launch2<kF64>(a, kTbCostF64, force, s);
+    return -1;
 }
 
 }  // namespace cmlb

@@ -448,12 +448,13 @@ def test_two_step_launch_ragged_z_chunks(cm, orc):
     test_two_step_launch_equals_single_steps(cm, orc, (31, 128, 512), "f32")
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16", "f16"])
 @pytest.mark.parametrize("shape", FUSION_SHAPES)
 def test_two_step_launch_equals_single_steps(cm, orc, shape, storage):
-    """Pairs of D3Q27 FP32 steps in one launch (intermediate state on chip)
-    give bitwise the same populations as one launch per step; odd counts end
-    with a single step.  16-bit storage keeps one step per launch either way."""
+    """Pairs of D3Q27 FP32 or FP64 steps in one launch (intermediate state on
+    chip) give bitwise the same populations as one launch per step; odd
+    counts end with a single step.  16-bit storage keeps one step per launch
+    either way."""
     L = orc.lattice("D3Q27")
     S = random_state(orc, "D3Q27", shape, seed=sum(shape) + 3)
     tau = taus("D3Q27", seed=len(shape) + shape[-1])
@@ -512,14 +513,14 @@ def test_two_step_launch_equals_single_steps_d37(cm, orc, shape, model, thermal)
         assert np.array_equal(out[1][1], out[k][1])
 
 
-@pytest.mark.parametrize("storage", ["f64", "bf16"])
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_two_step_launch_options(cm, storage):
     ctx = cm.Context("D3Q27", (4, 4, 4), storage=storage, tau={2: 0.6})
     try:
         for bad in (3, -1):
             with pytest.raises(cm.CmlbError):
                 ctx.set_step_fusion(bad)
-        for v in (0, 2):         # not FP32: one step per launch, silently
+        for v in (0, 2):         # 16-bit storage: one step per launch, silently
             ctx.set_step_fusion(v)
         ctx.init_fields(np.ones((4, 4, 4)), np.zeros((3, 4, 4, 4)))
         ctx.step(3)
