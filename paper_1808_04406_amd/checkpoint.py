@@ -35,7 +35,7 @@ def save(ctx, path):
     import torch
     p = ctx.params
     _, nbytes, _ = ctx.state()
-    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{p.device}")
     ctx.store_state_device(buf)
     ctx.sync()
     header = {
@@ -87,7 +87,7 @@ def load(path, stream=None, device=0):
         data = np.fromfile(path, dtype=np.uint8, offset=offset)
         if data.size != h["bytes"]:
             raise ValueError(f"{path}: {data.size} population bytes, expected {h['bytes']}")
-        buf = torch.from_numpy(data).to("cuda")
+        buf = torch.from_numpy(data).to(f"cuda:{device}")
         ctx.load_state_device(buf)
         ctx.sync()
         ctx.set_step_count(h["steps"])

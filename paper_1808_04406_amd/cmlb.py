@@ -198,6 +198,25 @@ def step_batch(ctxs, n=1):
         raise CmlbError(rc, lib().cmlb_last_error(ctxs[0].h).decode() if ctxs[0].h else "invalid batch")
 
 
+def _device_ptr(t, what, device, dtype=None, numel=None, min_bytes=None):
+    """Device address of a contiguous CUDA tensor on `device`, after checking
+    its dtype and size: the kernels trust the sizes the header states, so a
+    short or mistyped tensor is refused here rather than read or written past
+    its end on the GPU."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous CUDA tensor")
+    if t.device.index != device:
+        raise ValueError(f"{what}: tensor on cuda:{t.device.index}, context on cuda:{device}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what}: expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
+    if min_bytes is not None and t.numel() * t.element_size() < min_bytes:
+        raise ValueError(f"{what}: expected at least {min_bytes} bytes, got {t.numel() * t.element_size()}")
+    return t.data_ptr()
+
+
 class Context:
     """One simulation context (cmlb_ctx*).  Methods mirror the C entry points."""
 
@@ -216,7 +235,11 @@ class Context:
         if external is None:
             rc = lib().cmlb_create(ctypes.byref(self.params), ctypes.byref(h))
         else:
-            fa, fb = (t.data_ptr() if hasattr(t, "data_ptr") else int(t) for t in external)
+            # tensors are checked against the state size; plain integers are
+            # device addresses the caller vouches for (cmlb_create_external)
+            need = state_bytes(lattice, shape, storage)
+            fa, fb = (_device_ptr(t, "external buffer", device, min_bytes=need) if hasattr(t, "data_ptr")
+                      else int(t) for t in external)
             rc = lib().cmlb_create_external(ctypes.byref(self.params), fa, fb, ctypes.byref(h))
         if rc:
             raise CmlbError(rc, lib().cmlb_create_error().decode())
@@ -259,8 +282,13 @@ class Context:
 
     def init_fields_device(self, rho, u, theta=None):
         """Fields as float64 device tensors (torch) of nodes / D*nodes elements."""
-        ptr = lambda t: None if t is None else t.data_ptr()
-        self._check(lib().cmlb_init_fields_device(self.h, ptr(rho), ptr(u), ptr(theta)))
+        import torch
+        dev = self.params.device
+
+        def ptr(t, what, n):
+            return None if t is None else _device_ptr(t, what, dev, torch.float64, n)
+        self._check(lib().cmlb_init_fields_device(self.h, ptr(rho, "rho", self.nodes), ptr(u, "u", self.D * self.nodes),
+                                                  ptr(theta, "theta", self.nodes)))
 
     def step(self, n=1):
         self._check(lib().cmlb_step(self.h, int(n)))
@@ -289,15 +317,11 @@ class Context:
         be None), ordered on the context stream."""
         import torch
 
-        def ptr(t, n):
-            if t is None:
-                return None
-            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
-                raise ValueError("expected a contiguous float64 CUDA tensor of %d elements" % n)
-            return t.data_ptr()
-        nodes = int(np.prod(self.shape))
-        self._check(lib().cmlb_get_moments_device(self.h, ptr(rho, nodes), ptr(u, self.D * nodes),
-                                                  ptr(theta, nodes)))
+        def ptr(t, what, n):
+            return None if t is None else _device_ptr(t, what, self.params.device, torch.float64, n)
+        nodes = self.nodes
+        self._check(lib().cmlb_get_moments_device(self.h, ptr(rho, "rho", nodes), ptr(u, "u", self.D * nodes),
+                                                  ptr(theta, "theta", nodes)))
 
     def get_populations(self):
         f = np.zeros((self.Q,) + self.shape)
@@ -341,15 +365,26 @@ class Context:
 
     # -- device-side state transfer and coarse-graining ---------------------
     def store_state_device(self, dst):
-        """Copy the current populations into a device tensor (storage layout)."""
-        self._check(lib().cmlb_store_state_device(self.h, dst.data_ptr()))
+        """Copy the current populations into a device tensor (storage layout,
+        at least state_bytes(...) bytes)."""
+        need = self.state()[1]
+        self._check(lib().cmlb_store_state_device(self.h, _device_ptr(dst, "dst", self.params.device,
+                                                                      min_bytes=need)))
 
     def load_state_device(self, src):
-        self._check(lib().cmlb_load_state_device(self.h, src.data_ptr()))
+        need = self.state()[1]
+        self._check(lib().cmlb_load_state_device(self.h, _device_ptr(src, "src", self.params.device,
+                                                                     min_bytes=need)))
 
     def box_filter(self, factor, dst):
         """Mean over factor^3 blocks into an FP32 device tensor (coarse layout)."""
-        self._check(lib().cmlb_box_filter(self.h, int(factor), dst.data_ptr()))
+        import torch
+        f = int(factor)
+        if f < 1 or any(n % f for n in self.shape):
+            raise ValueError("the filter factor must divide every grid size")
+        coarse = self.Q * int(np.prod([n // f for n in self.shape]))
+        self._check(lib().cmlb_box_filter(self.h, f, _device_ptr(dst, "dst", self.params.device, torch.float32,
+                                                                 coarse)))
 
     # -- learned closure -----------------------------------------------------
     def closure_load(self, params, sigma):
@@ -376,9 +411,12 @@ class Context:
         self._check(lib().cmlb_closure_get(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return p
 
-    @staticmethod
-    def _batch(state, target, n_pairs):
-        return Batch(state.data_ptr(), target.data_ptr(), int(n_pairs))
+    def _batch(self, state, target, n_pairs):
+        import torch
+        n = int(n_pairs) * 27 * self.nodes
+        dev = self.params.device
+        return Batch(_device_ptr(state, "state", dev, torch.float32, n),
+                     _device_ptr(target, "target", dev, torch.float32, n), int(n_pairs))
 
     def closure_objective(self, state, target, n_pairs=1, grad=True):
         fp = ctypes.POINTER(ctypes.c_float)

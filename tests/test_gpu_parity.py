@@ -350,6 +350,49 @@ def test_external_buffers_match_internal(cm, shape):
     b.destroy()
 
 
+def test_device_tensor_checks(cm):
+    """Device tensors handed to the binding are checked for placement, dtype
+    and size before any kernel sees their address."""
+    import torch
+    shape = (4, 4, 8)
+    n = 4 * 4 * 8
+    f64 = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")
+    ctx = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.7})
+    try:
+        with pytest.raises(ValueError, match="elements"):
+            ctx.init_fields_device(f64(n), f64(3 * n - 1))
+        with pytest.raises(ValueError, match="float64"):
+            ctx.init_fields_device(f64(n).float(), f64(3 * n))
+        with pytest.raises(ValueError, match="CUDA"):
+            ctx.init_fields_device(torch.zeros(n, dtype=torch.float64), f64(3 * n))
+        with pytest.raises(ValueError, match="contiguous"):
+            ctx.init_fields_device(f64(2 * n)[::2], f64(3 * n))
+        ctx.init_fields_device(torch.ones(n, dtype=torch.float64, device="cuda"), f64(3 * n))
+        nbytes = ctx.state()[1]
+        with pytest.raises(ValueError, match="bytes"):
+            ctx.store_state_device(torch.empty(nbytes - 1, dtype=torch.uint8, device="cuda"))
+        with pytest.raises(ValueError, match="bytes"):
+            ctx.load_state_device(torch.empty(nbytes // 4 - 1, dtype=torch.float32, device="cuda"))
+        with pytest.raises(ValueError, match="elements"):
+            ctx.box_filter(2, torch.empty(27 * n // 8 + 1, dtype=torch.float32, device="cuda"))
+        with pytest.raises(ValueError, match="divide"):
+            ctx.box_filter(3, torch.empty(27, dtype=torch.float32, device="cuda"))
+        st = torch.zeros(27 * n, dtype=torch.float32, device="cuda")
+        ctx.closure_load(np.zeros(cm.CLOSURE_NPARAM), np.full(27, 0.01))
+        with pytest.raises(ValueError, match="elements"):
+            ctx.closure_objective(st, st, n_pairs=2)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        ctx.store_state_device(buf)       # the right sizes pass
+        ctx.load_state_device(buf)
+        ctx.sync()
+    finally:
+        ctx.destroy()
+    with pytest.raises(ValueError, match="bytes"):
+        short = [torch.empty(cm.state_bytes("D3Q27", shape, "f32") - 4, dtype=torch.uint8, device="cuda")
+                 for _ in range(2)]
+        cm.Context("D3Q27", shape, storage="f32", external=short)
+
+
 def test_device_fields_on_torch_stream(cm, orc):
     """Fields handed over as device tensors on the caller's stream."""
     import torch
