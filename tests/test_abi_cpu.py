@@ -296,3 +296,30 @@ def test_state_bytes_pitch_rule(cm):
         assert cm.state_bytes(lattice, shape, storage) == Q[lattice] * rows * pitch * elem[storage], (lattice, shape)
     with pytest.raises(cm.CmlbError):
         cm.state_bytes("D3Q27", (0, 8, 8))
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_workloads_are_well_formed():
+    """Every workload the bench lists names a known lattice, a storage type, a
+    grid of the lattice's dimension and a description."""
+    import importlib
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    bench = importlib.import_module("bench")
+    elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+    for name, (lattice, shape, storage, desc) in bench.WORKLOADS.items():
+        assert lattice in bench.QS and storage in elem, name
+        assert len(shape) == (3 if lattice == "D3Q27" else 2), name
+        assert desc, name
