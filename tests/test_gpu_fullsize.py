@@ -1,10 +1,10 @@
 """Parity at the full sizes of the paper-shaped workloads, on sampled outputs.
 
 * D3Q27 512^3 Taylor-Green vortex at Re = 1e5 (u0 = 0.05), the precision
-  form: BF16 and FP16 deviation storage (FP32 arithmetic) and FP32 storage,
-  two steps.  Population byte offsets reach 14 GB, so 64-bit addressing of
-  the population planes is exercised; the FP32 pair of steps runs in one
-  launch of the two-step kernel.  The oracle computes the two steps at each
+  form: BF16 and FP16 deviation storage (FP32 arithmetic), FP32 and FP64
+  storage, two steps.  Population byte offsets reach 14 GB (29 GB in
+  FP64), so 64-bit addressing of the population planes is exercised; the
+  FP32 and FP64 pairs of steps run in one launch of the two-step kernel.  The oracle computes the two steps at each
   sampled node from the equilibrium of the initial fields on its 5^3
   neighbourhood, rounding the intermediate state through the storage codec
   as the stored state is rounded.
@@ -28,7 +28,7 @@ from test_gpu_closure import params
 
 pytestmark = pytest.mark.gpu
 
-TORCH_DTYPE = {"f32": "float32", "bf16": "bfloat16", "f16": "float16"}
+TORCH_DTYPE = {"f64": "float64", "f32": "float32", "bf16": "bfloat16", "f16": "float16"}
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +46,7 @@ def sampled_state(ctx, storage, nodes, scale, w):
     import torch
     _, nbytes, _ = ctx.state()
     nz, ny, nx = ctx.shape
-    elem = {"f32": 4, "bf16": 2, "f16": 2}[storage]
+    elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[storage]
     pitch = nbytes // (27 * ny * nz * elem)
     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     ctx.store_state_device(buf)
@@ -59,7 +59,7 @@ def sampled_state(ctx, storage, nodes, scale, w):
     return (sel / scale[:, None] + w[:, None]).T
 
 
-@pytest.mark.parametrize("storage", ["bf16", "f16", "f32"])
+@pytest.mark.parametrize("storage", ["bf16", "f16", "f32", "f64"])
 def test_precision_form_512_two_steps_sampled(cm, orc, tgv512, storage):
     import torch
     n, rho, u, tau = tgv512
