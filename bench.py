@@ -37,6 +37,7 @@ RE = 1600.0
 Q = 27
 STORAGE_BYTES = 4
 PEAK_HBM_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20   # MI355X last-level (MALL) cache
 KERNEL = "k_step2_tp<kF32>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d3q27_256_f32.json")
 KERNEL_SOURCES = ["paper_1808_04406_amd/csrc/step_tp2.hip", "paper_1808_04406_amd/csrc/collide_tp.hpp",
@@ -341,6 +342,10 @@ def run(torch, cmlb, inputs, stream, args):
         kernel = "k_step_d37<%s, %s>" % (STORAGE_TAG[storage], MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+    # both population buffers inside the 256 MB Infinity Cache: the rate may
+    # then exceed what HBM alone allows
+    state_bytes = cmlb.state_bytes(lattice, shape, storage)
+    roof["fits_infinity_cache"] = 2 * state_bytes <= INFINITY_CACHE_BYTES
     if traffic is not None:
         # bytes the launch actually moves (rocprofv3 counters) per unit time
         moved = traffic / (kernel_ms * 1e-3) / 1e9
