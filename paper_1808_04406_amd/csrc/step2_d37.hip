@@ -15,7 +15,8 @@
 // With 3, 5, 7, 7, 7, 5, 3 populations at e_y = -3..3 that is
 // sum (4 + e_y,i) = 148 population rows of 128 columns: 75,776 bytes, so two
 // workgroups share a CU.  The stored state for the first step of iteration
-// j + 2 is fetched into registers during iteration j + 1.
+// j + 2 is fetched into registers during iteration j, right after the first
+// step of iteration j has consumed its own.
 //
 // Each population is read from HBM about (tx + 6) / tx times per two node
 // updates (plus the chunk's six lead-in rows) and written once, against
@@ -234,7 +235,12 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
 // kD2PerCU workgroups share a CU's LDS, so a launch of B workgroups runs in
 // ceil(B / kD2Slots) rounds of (cy + 6) iterations.  The row chunking
 // is the one with the lowest modelled time; the model also decides, in
-// automatic mode, between this kernel and two single steps.
+// automatic mode, between this kernel and two single steps.  Constants
+// from MI355X measurements: an iteration of a full round takes about 3.8 us
+// (3.9 at 1024^2, 4.2-4.5 at 2048^2), a single step 3 us plus 52 ps per node;
+// the model then prefers single steps up to 512^2, where the lead-in rows
+// dominate (measured: two steps per launch slower there, faster from
+// 1000^2 on).
 constexpr double kD2ItUs = 3.8, kD2LaunchUs = 3.0, kD2StepPsPerNode = 52.0;
 
 namespace {
