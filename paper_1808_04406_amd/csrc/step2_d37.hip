@@ -233,15 +233,15 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
 // Launcher
 // ---------------------------------------------------------------------------
 // kD2PerCU workgroups share a CU's LDS, so a launch of B workgroups runs in
-// ceil(B / kD2Slots) rounds of (cy + 6) iterations.  The row chunking
-// is the one with the lowest modelled time; the model also decides, in
-// automatic mode, between this kernel and two single steps.  Constants
-// from MI355X measurements: an iteration of a full round takes about 3.8 us
-// (3.9 at 1024^2, 4.2-4.5 at 2048^2), a single step 3 us plus 52 ps per node;
-// the model then prefers single steps up to 512^2, where the lead-in rows
-// dominate (measured: two steps per launch slower there, faster from
-// 1000^2 on).
-constexpr double kD2ItUs = 3.8, kD2LaunchUs = 3.0, kD2StepPsPerNode = 52.0;
+// ceil(B / kD2Slots) rounds of cy + 6 iterations, the first six of which
+// (the lead-in rows) compute only first steps and cost about half.  The row
+// chunking is the one with the lowest modelled time; the model also
+// decides, in automatic mode, between this kernel and two single steps.
+// Constants from MI355X measurements from 384^2 to 2048^2: a full iteration
+// of a round takes 3.9-4.7 us (4.3 here), a single step 3 us plus 54-86 ps
+// per node (58 here).  The model then picks the faster path at every size
+// measured: single steps up to 512^2, two steps per launch from 640^2 on.
+constexpr double kD2ItUs = 4.3, kD2LaunchUs = 3.0, kD2StepPsPerNode = 58.0;
 
 namespace {
 struct Step2D37Plan {
@@ -268,7 +268,7 @@ Step2D37Plan step2_d37_plan(const StepArgs& a) {
         const uint32_t cy = (a.g.ny + nc - 1) / nc;
         if ((a.g.ny + cy - 1) / cy != nc) continue;   // the same chunking as a smaller count
         const double rounds = (double)(((uint64_t)P.A.ntx * nc + kD2Slots - 1) / kD2Slots);
-        const double tm = rounds * (cy + 6) * kD2ItUs;
+        const double tm = rounds * (cy + 3) * kD2ItUs;   // six half-cost lead-in iterations
         if (nc == 1 || tm < best) { best = tm; best_cy = cy; }
     }
     P.A.cy = best_cy;
