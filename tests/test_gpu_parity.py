@@ -528,6 +528,8 @@ D37_FUSION_CASES = [
     ((301, 250), "cm", True),        # two-row chunks, the last one ragged
     ((61, 122), "reg_bgk", False),   # one full segment, isothermal
     ((24, 7), "cm", False),
+    ((2000, 130), "cm", True),       # tall: two segments, many short row chunks
+    ((130, 2000), "raw_mrt", True),  # wide: 17 segments
 ]
 
 
