@@ -141,7 +141,20 @@ int cmlb_state_bytes(const cmlb_params *p, size_t *bytes);
 
 /* Create a context: validates p, allocates two population buffers of
  * cmlb_state_bytes bytes on p->device.  The state is
- * undefined until cmlb_init_fields or cmlb_set_populations.  On failure
+ * undefined until cmlb_init_fields or cmlb_set_populations.
+ * What the parameters fix, and where the paper defines it:
+ *  - p->lattice: the abscissas xi_i and weights w_i of an on-lattice
+ *    quadrature rule (Sec. II.A, eq:quad), on which eq:an and eq:fi are an
+ *    exact transform between populations and Hermite coefficients;
+ *  - p->tau[n]: the relaxation time of central-moment order n, omega_n =
+ *    1 / tau_n (Sec. II.C, eq:omega; eq:mrt spells it out for n <= 4);
+ *  - p->thermal: whether theta follows from the populations or stays at
+ *    p->theta0 in the equilibrium (the isothermal runs of Sec. III.B);
+ *  - p->model: the central-moment operator, or the raw-moment MRT and
+ *    regularised BGK operators it is compared with (Sec. II.B-C, eq:regnmrt,
+ *    eq:lbgk-reg).
+ * The truncation orders are fixed per lattice (N = M = 4 on D2Q37 as in all
+ * of Sec. III; the complete basis on D2Q9 and D3Q27).  On failure
  * *out is NULL and cmlb_create_error() describes the reason: CMLB_EINVAL
  * for parameters outside the ranges documented in cmlb_params (checked
  * before any device call), CMLB_EDEVICE or CMLB_ENOMEM from the device. */
@@ -162,7 +175,11 @@ void cmlb_destroy(cmlb_ctx *ctx);
 /* Description of the last error on ctx ("" if none). */
 const char *cmlb_last_error(const cmlb_ctx *ctx);
 
-/* Replace tau_n for orders 2 .. 2+n-1 (tau_by_order[k] is tau of order k+2). */
+/* Replace tau_n for orders 2 .. 2+n-1 (tau_by_order[k] is tau of order k+2;
+ * host array of n values, 1 <= n <= 6, each > 0 and finite, else
+ * CMLB_EINVAL).  Central moments of order n relax at omega_n = 1 / tau_n
+ * (Sec. II.C, eq:omega, required there for every order n); orders 0 and 1
+ * are conserved and have no rate.  Takes effect at the next cmlb_step. */
 int cmlb_set_tau(cmlb_ctx *ctx, const double *tau_by_order, int n);
 
 /* Set the state to the discrete equilibrium of the given fields (host FP64,
@@ -175,7 +192,12 @@ int cmlb_init_fields(cmlb_ctx *ctx, const double *rho, const double *u, const do
 int cmlb_init_fields_device(cmlb_ctx *ctx, const double *rho, const double *u, const double *theta);
 
 /* Enqueue n stream-and-collide steps on the context stream (asynchronous).
- * On D3Q27 with FP32 or FP64 storage and on D2Q37 with FP32 storage
+ * One step is the update of Sec. II.C (its final equation,
+ * f_i(x + xi_i, t + 1) = f^_i + Omega_i, with f^ the projection of eq:reg
+ * and Omega the central-moment relaxation of eq:omega / eq:mrt) on the
+ * periodic grid, written as a pull: every node gathers f_i(x - e_i) and
+ * collides.  n >= 0 (n = 0 does nothing); CMLB_ESTATE before the state is
+ * initialised.  Divergence is not checked here (see cmlb_reduce).  On D3Q27 with FP32 or FP64 storage and on D2Q37 with FP32 storage
  * (learned closure off) pairs of steps run as one launch that keeps the
  * intermediate state on chip; the result is identical to single steps (see
  * cmlb_set_step_fusion). */
@@ -230,7 +252,12 @@ int cmlb_step_batch(cmlb_ctx *const *ctxs, int count, int64_t n);
 int cmlb_sync(cmlb_ctx *ctx);
 
 /* Read rho[node], u[D][node] (lattice units) and theta[node] of the state
- * (host FP64; any pointer may be NULL).  Synchronises. */
+ * (host FP64; any pointer may be NULL).  Synchronises.  These are the
+ * leading moments of Sec. II.A (the equation after eq:fi): rho = sum f_i,
+ * rho u = sum f_i xi_i, rho (u^2 + D theta) = sum f_i xi_i^2 with
+ * xi_i = r e_i; u is returned divided by r (cells per step).  On
+ * isothermal contexts theta is theta0.  Caller-owned arrays of nx*ny*nz
+ * (rho, theta) and D*nx*ny*nz (u) doubles. */
 int cmlb_get_moments(cmlb_ctx *ctx, double *rho, double *u, double *theta);
 
 /* As cmlb_get_moments into caller-owned device arrays (FP64, same layout;
