@@ -63,6 +63,10 @@ def lib():
         L.orc_closure_inputs.argtypes = [ctypes.c_int, d, d, d]
         L.orc_collide_closure.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, ctypes.c_int, d, d]
         L.orc_closure_loss_grad.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, ctypes.c_int, d, d]
+        L.orc_closure_loss_offsets.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, ctypes.c_int, d, d]
+        L.orc_closure_eval_rounded.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, d, d, d, d, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_double, d, d, d, d, d, d, d, d, d]
+        L.orc_round_sig.argtypes = [ctypes.c_int, d, ctypes.c_int, d]
         L.orc_gather_nodes.argtypes = [ctypes.c_int, l, l, l, d, l, ctypes.POINTER(ctypes.c_int64), d]
         _lib = L
     return _lib
@@ -304,6 +308,64 @@ def closure_loss_grad(cfg: Cfg, f, fbar, params, norm, tie_even=False):
     if rc:
         raise RuntimeError("closure loss needs a D3Q27 CM configuration")
     return loss.value, grad
+
+
+MLP_NQ = 27 + 2 * 32   # rounded quantities per node: inputs x, activations h1, h2
+
+
+def round_sig(v, bits=8):
+    """Nearest values with `bits` significant bits, ties to even (8 = BF16)."""
+    v = np.ascontiguousarray(np.atleast_1d(v), np.float64)
+    out = np.zeros_like(v)
+    lib().orc_round_sig(v.size, _p(v), int(bits), _p(out))
+    return out
+
+
+def closure_eval_rounded(cfg: Cfg, f, fbar, params, norm, tie_even=False, bits=8, rho0=1.0,
+                         err=(0.0, 0.0, 0.0)):
+    """The closure network with its weights, inputs and hidden activations
+    rounded to `bits` significant bits (the library's BF16 operands), in FP64
+    otherwise.  fbar=None evaluates the collision only.  err = (ex, eh_rel,
+    eh_sum) models the pre-rounding errors of another evaluation of the same
+    network (see orc_closure_eval_rounded); returns a dict with f* [n, 27],
+    omega [n, 4], and with fbar the objective, its gradient, per-entry bounds
+    ``bound_grad`` (2084 entries, then the objective) and ``abs_grad``
+    (sum over nodes of |node share|), ``bound_fs`` [n, 27] and the rounding
+    ``offsets`` [n, MLP_NQ]."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    n = f.shape[0]
+    fb = None if fbar is None else np.ascontiguousarray(np.atleast_2d(fbar), np.float64)
+    r = dict(fs=np.zeros((n, 27)), omega=np.zeros((n, 4)), bound_fs=np.zeros((n, 27)),
+             offsets=np.zeros((n, MLP_NQ)))
+    loss = ctypes.c_double()
+    grad, bg, ag = np.zeros(MLP_NPARAM), np.zeros(MLP_NPARAM + 1), np.zeros(MLP_NPARAM + 1)
+    errv = np.ascontiguousarray(err, np.float64)
+    rc = lib().orc_closure_eval_rounded(ctypes.byref(cfg.c()), n, _p(f), None if fb is None else _p(fb),
+                                        _p(np.ascontiguousarray(params, np.float64)),
+                                        _p(np.ascontiguousarray(norm, np.float64)), 1 if tie_even else 0,
+                                        int(bits), float(rho0), _p(errv), _p(r["fs"]), _p(r["omega"]),
+                                        ctypes.byref(loss), _p(grad), _p(r["bound_fs"]), _p(bg), _p(ag),
+                                        _p(r["offsets"]))
+    if rc:
+        raise RuntimeError("rounded closure evaluation needs a D3Q27 CM configuration")
+    if fb is not None:
+        r.update(loss=loss.value, grad=grad, bound_grad=bg, abs_grad=ag)
+    return r
+
+
+def closure_loss_offsets(cfg: Cfg, f, fbar, params, norm, offsets, tie_even=False):
+    """Objective of the network whose rounded operands are replaced by the
+    exact values plus constant offsets [n, MLP_NQ] (weights as given)."""
+    f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
+    fbar = np.ascontiguousarray(np.atleast_2d(fbar), np.float64)
+    loss = ctypes.c_double()
+    rc = lib().orc_closure_loss_offsets(ctypes.byref(cfg.c()), f.shape[0], _p(f), _p(fbar),
+                                        _p(np.ascontiguousarray(params, np.float64)),
+                                        _p(np.ascontiguousarray(norm, np.float64)), 1 if tie_even else 0,
+                                        _p(np.ascontiguousarray(offsets, np.float64)), ctypes.byref(loss))
+    if rc:
+        raise RuntimeError("closure loss needs a D3Q27 CM configuration")
+    return loss.value
 
 
 def gather_nodes(kind: str, S: np.ndarray, nodes) -> np.ndarray:

@@ -955,6 +955,7 @@ int orc_moments(int kind, long n_nodes, const double *S, double *rho, double *u,
 #define MLP_NH 32
 #define MLP_NOUT 4
 #define MLP_NPARAM (MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NOUT * MLP_NH + MLP_NOUT)
+#define MLP_NQ (MLP_NIN + 2 * MLP_NH)   /* rounded quantities of one node: x, h1, h2 */
 
 static double gelu(double a) { return 0.5 * a * (1.0 + erf(a / sqrt(2.0))); }
 static double gelu_grad(double a)
@@ -964,27 +965,110 @@ static double gelu_grad(double a)
 }
 static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
-typedef struct { double a1[MLP_NH], h1[MLP_NH], a2[MLP_NH], h2[MLP_NH], z[MLP_NOUT]; } mlp_trace;
+/* Optional rounding of the network's operands.  The library evaluates the
+ * network with BF16 weights, inputs and hidden activations (8 significant
+ * bits, round to nearest with ties to even).  With bits = 8 the oracle
+ * rounds the same quantities: the weights W1, W2, W3, the inputs x and the
+ * activations h1 = GELU(a1), h2 = GELU(a2); biases, pre-activations and
+ * everything downstream of z stay exact.  The derivative of the objective
+ * passes through a rounding unchanged (the rounding error is a constant of
+ * the evaluation), so the backward pass uses the rounded weights and the
+ * rounded activations.
+ *   flip:   per rounded quantity, take the other of the two representable
+ *           values around it (used to bound the effect of a rounding that a
+ *           slightly different evaluation could take the other way);
+ *   offset: per rounded quantity, add this constant instead of rounding, with
+ *           the weights as given (the network whose exact gradient the
+ *           rounded network's gradient is). */
+typedef struct {
+    int bits;
+    const unsigned char *flip;
+    const double *offset;
+} mlp_round;
 
-static void mlp_forward(const double *P, const double *x, mlp_trace *t)
+/* Nearest value with `bits` significant bits, ties to even; *lo and *hi
+ * receive the two such values bracketing v (equal if v is one). */
+static double round_sig(double v, int bits, double *lo, double *hi)
+{
+    if (v == 0.0 || !isfinite(v)) {
+        if (lo) *lo = v;
+        if (hi) *hi = v;
+        return v;
+    }
+    int e;
+    const double m = frexp(fabs(v), &e);      /* |v| = m 2^e, 0.5 <= m < 1 */
+    const double sc = ldexp(m, bits);         /* in [2^(bits-1), 2^bits) */
+    const double fl = floor(sc), sign = v < 0 ? -1.0 : 1.0;
+    const double a = sign * ldexp(fl, e - bits), b = sign * ldexp(fl == sc ? fl : fl + 1.0, e - bits);
+    if (lo) *lo = a;
+    if (hi) *hi = b;
+    const double frac = sc - fl;
+    if (frac < 0.5) return a;
+    if (frac > 0.5) return b;
+    return fmod(fl, 2.0) == 0.0 ? a : b;
+}
+
+static double mlp_weight(const mlp_round *q, double w)
+{
+    return (q && !q->offset && q->bits > 0) ? round_sig(w, q->bits, NULL, NULL) : w;
+}
+
+static double mlp_q(const mlp_round *q, int k, double v)
+{
+    if (!q) return v;
+    if (q->offset) return v + q->offset[k];
+    if (q->bits <= 0) return v;
+    double lo, hi;
+    double r = round_sig(v, q->bits, &lo, &hi);
+    if (q->flip && q->flip[k]) r = (r == lo) ? hi : lo;
+    return r;
+}
+
+/* pre-rounding values (x, h1, h2), the values used (xr, h1r, h2r), the
+ * pre-activations and the logits of one node */
+typedef struct {
+    double x[MLP_NIN], xr[MLP_NIN];
+    double a1[MLP_NH], h1[MLP_NH], h1r[MLP_NH], s1[MLP_NH];
+    double a2[MLP_NH], h2[MLP_NH], h2r[MLP_NH], s2[MLP_NH];
+    double z[MLP_NOUT];
+} mlp_trace;
+
+/* s1, s2: |b| + sum |W in| of each pre-activation (the scale of its sum) */
+static void mlp_forward(const double *P, const double *x, const mlp_round *q, mlp_trace *t)
 {
     const double *W1 = P, *b1 = W1 + MLP_NH * MLP_NIN, *W2 = b1 + MLP_NH, *b2 = W2 + MLP_NH * MLP_NH;
     const double *W3 = b2 + MLP_NH, *b3 = W3 + MLP_NOUT * MLP_NH;
-    for (int j = 0; j < MLP_NH; ++j) {
-        double s = b1[j];
-        for (int k = 0; k < MLP_NIN; ++k) s += W1[j * MLP_NIN + k] * x[k];
-        t->a1[j] = s;
-        t->h1[j] = gelu(s);
+    for (int k = 0; k < MLP_NIN; ++k) {
+        t->x[k] = x[k];
+        t->xr[k] = mlp_q(q, k, x[k]);
     }
     for (int j = 0; j < MLP_NH; ++j) {
-        double s = b2[j];
-        for (int k = 0; k < MLP_NH; ++k) s += W2[j * MLP_NH + k] * t->h1[k];
+        double s = b1[j], m = fabs(b1[j]);
+        for (int k = 0; k < MLP_NIN; ++k) {
+            const double term = mlp_weight(q, W1[j * MLP_NIN + k]) * t->xr[k];
+            s += term;
+            m += fabs(term);
+        }
+        t->a1[j] = s;
+        t->s1[j] = m;
+        t->h1[j] = gelu(s);
+        t->h1r[j] = mlp_q(q, MLP_NIN + j, t->h1[j]);
+    }
+    for (int j = 0; j < MLP_NH; ++j) {
+        double s = b2[j], m = fabs(b2[j]);
+        for (int k = 0; k < MLP_NH; ++k) {
+            const double term = mlp_weight(q, W2[j * MLP_NH + k]) * t->h1r[k];
+            s += term;
+            m += fabs(term);
+        }
         t->a2[j] = s;
+        t->s2[j] = m;
         t->h2[j] = gelu(s);
+        t->h2r[j] = mlp_q(q, MLP_NIN + MLP_NH + j, t->h2[j]);
     }
     for (int j = 0; j < MLP_NOUT; ++j) {
         double s = b3[j];
-        for (int k = 0; k < MLP_NH; ++k) s += W3[j * MLP_NH + k] * t->h2[k];
+        for (int k = 0; k < MLP_NH; ++k) s += mlp_weight(q, W3[j * MLP_NH + k]) * t->h2r[k];
         t->z[j] = s;
     }
 }
@@ -997,9 +1081,15 @@ int orc_mlp_forward(const double *params, int n, const double *x, double *omega)
 {
     for (int k = 0; k < n; ++k) {
         mlp_trace t;
-        mlp_forward(params, x + (size_t)k * MLP_NIN, &t);
+        mlp_forward(params, x + (size_t)k * MLP_NIN, NULL, &t);
         for (int j = 0; j < MLP_NOUT; ++j) omega[(size_t)k * MLP_NOUT + j] = rate_from_logit(t.z[j]);
     }
+    return 0;
+}
+
+int orc_round_sig(int n, const double *in, int bits, double *out)
+{
+    for (int k = 0; k < n; ++k) out[k] = round_sig(in[k], bits, NULL, NULL);
     return 0;
 }
 
@@ -1033,6 +1123,80 @@ int orc_closure_inputs(int n, const double *f, const double *norm, double *x)
     return 0;
 }
 
+/* One node of the closure collision.  f: pulled populations; fbar: target
+ * (NULL for the collision alone); inv_n: weight of the node in the mean.
+ * Outputs f* (fs), the rates omega_3..6 (om), the node's share of the
+ * objective (*loss) and of its gradient (grad, accumulated; NULL to skip).
+ *
+ * Objective: L = (1/n) sum_nodes sum_i (f*_i - fbar_i)^2 / w_i.  f* is
+ * affine in each omega_m (kappa* = kappa + omega_{|p|} (kappa_eq - kappa)),
+ * so the derivative of f* with respect to omega_m is the difference of two
+ * collisions with omega_m = 1 and omega_m = 0; the rest is the chain rule
+ * through the sigmoid map and the two GELU layers. */
+static void closure_node(const orc_lattice *L, const orc_cfg *cfg, const double *f, const double *fbar,
+                         const double *P, const double *norm, int tie_even, double inv_n, const mlp_round *q,
+                         mlp_trace *t, double *fs, double *om, double *loss, double *grad)
+{
+    double x[27];
+    closure_inputs(L, f, norm, x);
+    mlp_forward(P, x, q, t);
+    orc_cfg c = *cfg;
+    for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t->z[j]);
+    if (tie_even) c.omega[4] = c.omega[6] = cfg->omega[2];
+    if (om)
+        for (int j = 0; j < MLP_NOUT; ++j) om[j] = c.omega[3 + j];
+    collide_tp(L, &c, f, fs);
+    if (!fbar) return;
+    double r[27], l = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        const double e = fs[i] - fbar[i];
+        l += e * e / L->w[i] * inv_n;
+        r[i] = 2.0 * e / L->w[i] * inv_n;
+    }
+    *loss = l;
+    if (!grad) return;
+    const double *W2 = P + MLP_NH * MLP_NIN + MLP_NH;
+    const double *W3 = W2 + MLP_NH * MLP_NH + MLP_NH;
+    double dz[MLP_NOUT];
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        if (tie_even && (j == 1 || j == 3)) { dz[j] = 0.0; continue; }
+        orc_cfg c1 = c, c0 = c;
+        c1.omega[3 + j] = 1.0;
+        c0.omega[3 + j] = 0.0;
+        double g1[27], g0[27], dw = 0.0;
+        collide_tp(L, &c1, f, g1);
+        collide_tp(L, &c0, f, g0);
+        for (int i = 0; i < 27; ++i) dw += r[i] * (g1[i] - g0[i]);
+        const double s = sigmoid(t->z[j]);
+        dz[j] = dw * 1.45 * s * (1.0 - s);
+    }
+    double *gW1 = grad, *gb1 = gW1 + MLP_NH * MLP_NIN, *gW2 = gb1 + MLP_NH, *gb2 = gW2 + MLP_NH * MLP_NH;
+    double *gW3 = gb2 + MLP_NH, *gb3 = gW3 + MLP_NOUT * MLP_NH;
+    double da2[MLP_NH], da1[MLP_NH];
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        gb3[j] += dz[j];
+        for (int m = 0; m < MLP_NH; ++m) gW3[j * MLP_NH + m] += dz[j] * t->h2r[m];
+    }
+    for (int m = 0; m < MLP_NH; ++m) {
+        double dh = 0.0;
+        for (int j = 0; j < MLP_NOUT; ++j) dh += mlp_weight(q, W3[j * MLP_NH + m]) * dz[j];
+        da2[m] = dh * gelu_grad(t->a2[m]);
+    }
+    for (int j = 0; j < MLP_NH; ++j) {
+        gb2[j] += da2[j];
+        for (int m = 0; m < MLP_NH; ++m) gW2[j * MLP_NH + m] += da2[j] * t->h1r[m];
+    }
+    for (int m = 0; m < MLP_NH; ++m) {
+        double dh = 0.0;
+        for (int j = 0; j < MLP_NH; ++j) dh += mlp_weight(q, W2[j * MLP_NH + m]) * da2[j];
+        da1[m] = dh * gelu_grad(t->a1[m]);
+    }
+    for (int j = 0; j < MLP_NH; ++j) {
+        gb1[j] += da1[j];
+        for (int m = 0; m < MLP_NIN; ++m) gW1[j * MLP_NIN + m] += da1[j] * t->xr[m];
+    }
+}
+
 /* Collision with the network's rates for orders 3..6 (omega_2 from cfg).
  * With tie_even, orders 4 and 6 relax at omega_2 instead (the network's
  * outputs for them are unused). */
@@ -1042,92 +1206,148 @@ int orc_collide_closure(const orc_cfg *cfg, int n, const double *f, const double
     const orc_lattice *L = lattice(ORC_D3Q27);
     if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM) return -1;
     for (int k = 0; k < n; ++k) {
-        double x[27];
         mlp_trace t;
-        closure_inputs(L, f + (size_t)k * 27, norm, x);
-        mlp_forward(params, x, &t);
-        orc_cfg c = *cfg;
-        for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t.z[j]);
-        if (tie_even) c.omega[4] = c.omega[6] = cfg->omega[2];
-        if (omega_out)
-            for (int j = 0; j < MLP_NOUT; ++j) omega_out[(size_t)k * MLP_NOUT + j] = c.omega[3 + j];
-        collide_tp(L, &c, f + (size_t)k * 27, out + (size_t)k * 27);
+        closure_node(L, cfg, f + (size_t)k * 27, NULL, params, norm, tie_even, 0.0, NULL, &t,
+                     out + (size_t)k * 27, omega_out ? omega_out + (size_t)k * MLP_NOUT : NULL, NULL, NULL);
     }
     return 0;
 }
 
-/* Training objective and its gradient.  For pulled pre-collision states f
- * and targets fbar (n nodes each, [node][i]):
- *   L = (1/n) sum_nodes sum_i (f*_i - fbar_i)^2 / w_i,
- * f* the collision with the network's rates.  f* is affine in each omega_m
- * (kappa* = kappa + omega_{|p|} (kappa_eq - kappa)), so the derivative of f*
- * with respect to omega_m is the
- * difference of two collisions with omega_m = 1 and omega_m = 0; the rest is
- * the chain rule through the sigmoid map and the two GELU layers. */
+/* Training objective and its gradient for pulled pre-collision states f and
+ * targets fbar (n nodes each, [node][i]), the network in FP64. */
 int orc_closure_loss_grad(const orc_cfg *cfg, int n, const double *f, const double *fbar, const double *params,
                           const double *norm, int tie_even, double *loss_out, double *grad)
 {
     const orc_lattice *L = lattice(ORC_D3Q27);
     if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM || n < 1) return -1;
-    const double *W2 = params + MLP_NH * MLP_NIN + MLP_NH;
-    const double *W3 = W2 + MLP_NH * MLP_NH + MLP_NH;
     memset(grad, 0, sizeof(double) * MLP_NPARAM);
     double loss = 0.0;
     for (int k = 0; k < n; ++k) {
-        const double *fk = f + (size_t)k * 27, *tk = fbar + (size_t)k * 27;
-        double x[27], fs[27], r[27];
         mlp_trace t;
-        closure_inputs(L, fk, norm, x);
-        mlp_forward(params, x, &t);
-        orc_cfg c = *cfg;
-        for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t.z[j]);
-        if (tie_even) c.omega[4] = c.omega[6] = cfg->omega[2];
-        collide_tp(L, &c, fk, fs);
-        for (int i = 0; i < 27; ++i) {
-            double e = fs[i] - tk[i];
-            loss += e * e / L->w[i] / n;
-            r[i] = 2.0 * e / L->w[i] / n;
-        }
-        double dz[MLP_NOUT];
-        for (int j = 0; j < MLP_NOUT; ++j) {
-            if (tie_even && (j == 1 || j == 3)) { dz[j] = 0.0; continue; }
-            orc_cfg c1 = c, c0 = c;
-            c1.omega[3 + j] = 1.0;
-            c0.omega[3 + j] = 0.0;
-            double g1[27], g0[27], dw = 0.0;
-            collide_tp(L, &c1, fk, g1);
-            collide_tp(L, &c0, fk, g0);
-            for (int i = 0; i < 27; ++i) dw += r[i] * (g1[i] - g0[i]);
-            double s = sigmoid(t.z[j]);
-            dz[j] = dw * 1.45 * s * (1.0 - s);
-        }
-        double *gW1 = grad, *gb1 = gW1 + MLP_NH * MLP_NIN, *gW2 = gb1 + MLP_NH, *gb2 = gW2 + MLP_NH * MLP_NH;
-        double *gW3 = gb2 + MLP_NH, *gb3 = gW3 + MLP_NOUT * MLP_NH;
-        double da2[MLP_NH], da1[MLP_NH];
-        for (int j = 0; j < MLP_NOUT; ++j) {
-            gb3[j] += dz[j];
-            for (int m = 0; m < MLP_NH; ++m) gW3[j * MLP_NH + m] += dz[j] * t.h2[m];
-        }
-        for (int m = 0; m < MLP_NH; ++m) {
-            double dh = 0.0;
-            for (int j = 0; j < MLP_NOUT; ++j) dh += W3[j * MLP_NH + m] * dz[j];
-            da2[m] = dh * gelu_grad(t.a2[m]);
-        }
-        for (int j = 0; j < MLP_NH; ++j) {
-            gb2[j] += da2[j];
-            for (int m = 0; m < MLP_NH; ++m) gW2[j * MLP_NH + m] += da2[j] * t.h1[m];
-        }
-        for (int m = 0; m < MLP_NH; ++m) {
-            double dh = 0.0;
-            for (int j = 0; j < MLP_NH; ++j) dh += W2[j * MLP_NH + m] * da2[j];
-            da1[m] = dh * gelu_grad(t.a1[m]);
-        }
-        for (int j = 0; j < MLP_NH; ++j) {
-            gb1[j] += da1[j];
-            for (int m = 0; m < MLP_NIN; ++m) gW1[j * MLP_NIN + m] += da1[j] * x[m];
-        }
+        double fs[27], l;
+        closure_node(L, cfg, f + (size_t)k * 27, fbar + (size_t)k * 27, params, norm, tie_even, 1.0 / n, NULL,
+                     &t, fs, NULL, &l, grad);
+        loss += l;
     }
     *loss_out = loss;
+    return 0;
+}
+
+/* The objective of the network whose operands are shifted by constant
+ * offsets instead of rounded (offsets[k * MLP_NQ + q] for node k: x, h1, h2),
+ * with the weights as given.  At offsets equal to the rounding errors of a
+ * rounded evaluation it takes the same value, and its exact gradient is the
+ * gradient the rounded evaluation reports. */
+int orc_closure_loss_offsets(const orc_cfg *cfg, int n, const double *f, const double *fbar, const double *params,
+                             const double *norm, int tie_even, const double *offsets, double *loss_out)
+{
+    const orc_lattice *L = lattice(ORC_D3Q27);
+    if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM || n < 1) return -1;
+    double loss = 0.0;
+    for (int k = 0; k < n; ++k) {
+        mlp_round q = {0, NULL, offsets + (size_t)k * MLP_NQ};
+        mlp_trace t;
+        double fs[27], l;
+        closure_node(L, cfg, f + (size_t)k * 27, fbar + (size_t)k * 27, params, norm, tie_even, 1.0 / n, &q, &t,
+                     fs, NULL, &l, NULL);
+        loss += l;
+    }
+    *loss_out = loss;
+    return 0;
+}
+
+/* The closure collision (and, with fbar, the objective and its gradient)
+ * with the network's operands rounded to `bits` significant bits, plus
+ * per-element bounds on how far an evaluation of the same network may land
+ * from these values when it computes the quantities before each rounding
+ * with small errors of its own: where such a quantity lies closer to the
+ * midpoint between its two representable neighbours than that error, the
+ * other evaluation may round it the other way.  For every such quantity
+ * the node is evaluated again with that one rounding flipped, and the
+ * absolute changes of f*, of the objective and of the node's gradient share
+ * are summed into bound_fs, bound_grad[MLP_NPARAM] (objective) and
+ * bound_grad[0..]; abs_grad accumulates |node share| per entry (the scale of
+ * the sums' own rounding).  The error model err[3] of the other
+ * evaluation's pre-rounding values:
+ *   x_p:  err[0] * sum_i |f_i - w_i rho0| / (rho sigma_p)
+ *   h:    err[1] * |a| + err[2] * (|b| + sum |W in|)   (a the pre-activation).
+ * offsets (optional, [n][MLP_NQ]) receives the rounding errors used. */
+int orc_closure_eval_rounded(const orc_cfg *cfg, int n, const double *f, const double *fbar, const double *params,
+                             const double *norm, int tie_even, int bits, double rho0, const double *err,
+                             double *fs_out, double *omega_out, double *loss_out, double *grad,
+                             double *bound_fs, double *bound_grad, double *abs_grad, double *offsets)
+{
+    const orc_lattice *L = lattice(ORC_D3Q27);
+    if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM || n < 1 || bits < 1) return -1;
+    const int ng = MLP_NPARAM + 1;
+    if (grad) memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    if (bound_grad) memset(bound_grad, 0, sizeof(double) * ng);
+    if (abs_grad) memset(abs_grad, 0, sizeof(double) * ng);
+    double *g0 = (double *)malloc(sizeof(double) * ng), *g1 = (double *)malloc(sizeof(double) * ng);
+    if (!g0 || !g1) { free(g0); free(g1); return -2; }
+    double loss = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double *fk = f + (size_t)k * 27, *tk = fbar ? fbar + (size_t)k * 27 : NULL;
+        unsigned char flip[MLP_NQ];
+        memset(flip, 0, sizeof flip);
+        mlp_round q = {bits, flip, NULL};
+        mlp_trace t, t1;
+        double fs[27], fs1[27], l0 = 0.0, l1 = 0.0;
+        memset(g0, 0, sizeof(double) * ng);
+        closure_node(L, cfg, fk, tk, params, norm, tie_even, 1.0 / n, &q, &t, fs, omega_out + (size_t)k * MLP_NOUT,
+                     &l0, (tk && grad) ? g0 : NULL);
+        g0[MLP_NPARAM] = l0;
+        memcpy(fs_out + (size_t)k * 27, fs, sizeof fs);
+        loss += l0;
+        if (tk && grad)
+            for (int e = 0; e < MLP_NPARAM; ++e) grad[e] += g0[e];
+        if (tk && abs_grad)
+            for (int e = 0; e < ng; ++e) abs_grad[e] += fabs(g0[e]);
+        if (offsets) {
+            double *o = offsets + (size_t)k * MLP_NQ;
+            for (int m = 0; m < MLP_NIN; ++m) o[m] = t.xr[m] - t.x[m];
+            for (int m = 0; m < MLP_NH; ++m) {
+                o[MLP_NIN + m] = t.h1r[m] - t.h1[m];
+                o[MLP_NIN + MLP_NH + m] = t.h2r[m] - t.h2[m];
+            }
+        }
+        if (!bound_fs && !bound_grad) continue;
+        /* pre-rounding values and their error bounds */
+        double rho = 0.0, dev = 0.0;
+        for (int i = 0; i < 27; ++i) {
+            rho += fk[i];
+            dev += fabs(fk[i] - L->w[i] * rho0);
+        }
+        double val[MLP_NQ], tol[MLP_NQ];
+        for (int m = 0; m < MLP_NIN; ++m) {
+            val[m] = t.x[m];
+            tol[m] = err[0] * dev / (rho * norm[m]);
+        }
+        for (int m = 0; m < MLP_NH; ++m) {
+            val[MLP_NIN + m] = t.h1[m];
+            tol[MLP_NIN + m] = err[1] * fabs(t.a1[m]) + err[2] * t.s1[m];
+            val[MLP_NIN + MLP_NH + m] = t.h2[m];
+            tol[MLP_NIN + MLP_NH + m] = err[1] * fabs(t.a2[m]) + err[2] * t.s2[m];
+        }
+        for (int m = 0; m < MLP_NQ; ++m) {
+            double lo, hi;
+            round_sig(val[m], bits, &lo, &hi);
+            if (lo == hi || fabs(val[m] - 0.5 * (lo + hi)) >= tol[m]) continue;
+            flip[m] = 1;
+            memset(g1, 0, sizeof(double) * ng);
+            closure_node(L, cfg, fk, tk, params, norm, tie_even, 1.0 / n, &q, &t1, fs1, NULL, &l1,
+                         (tk && grad) ? g1 : NULL);
+            g1[MLP_NPARAM] = l1;
+            flip[m] = 0;
+            if (bound_fs)
+                for (int i = 0; i < 27; ++i) bound_fs[(size_t)k * 27 + i] += fabs(fs1[i] - fs[i]);
+            if (bound_grad && tk)
+                for (int e = 0; e < ng; ++e) bound_grad[e] += fabs(g1[e] - g0[e]);
+        }
+    }
+    if (loss_out) *loss_out = loss;
+    free(g0);
+    free(g1);
     return 0;
 }
 

@@ -130,3 +130,129 @@ def test_tie_even(orc):
         fd = (orc.closure_loss_grad(cfg, f, fbar, Pp, norm, True)[0]
               - orc.closure_loss_grad(cfg, f, fbar, Pm, norm, True)[0]) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-12), k
+
+
+# ---------------------------------------------------------------------------
+# The rounded evaluation (BF16 weights, inputs and activations, as the
+# library evaluates the network)
+# ---------------------------------------------------------------------------
+def bf16_bits(x32):
+    """BF16 round-to-nearest-even of FP32 values by bit manipulation."""
+    b = np.asarray(x32, np.float32).view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) & 0xFFFF
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def bf16_params(seed, scale=0.3):
+    return bf16_bits(random_params(seed, scale).astype(np.float32))
+
+
+def test_round_sig_is_bf16(orc):
+    """round_sig(., 8) is BF16 rounding: random FP32 values, and exact ties
+    (low 16 bits 0x8000) in both parities of the kept bit."""
+    rng = np.random.default_rng(20)
+    v = (rng.normal(size=4000) * np.exp(rng.uniform(-20, 20, 4000))).astype(np.float32)
+    mant = rng.integers(0, 1 << 7, 200, dtype=np.uint32) << 16      # the 7 kept fraction bits
+    expo = rng.integers(100, 150, 200, dtype=np.uint32) << 23
+    ties = (expo | mant | np.uint32(0x8000)).view(np.float32)
+    ties = np.concatenate([ties, -ties])
+    for arr in (v, ties):
+        assert np.array_equal(orc.round_sig(arr.astype(np.float64), 8), bf16_bits(arr))
+
+
+def unpack_r(orc, P):
+    return [orc.round_sig(a, 8).reshape(a.shape) if a.ndim == 2 else a for a in unpack(P)]
+
+
+def test_rounded_forward_matches_independent(orc):
+    """Independent forward pass of the rounded network (torch exact GELU,
+    rounding by round_sig): x, h1 and h2 rounded, weights rounded, biases
+    exact; rates and f* agree with the oracle's rounded evaluation."""
+    import torch
+    f = states(orc, 12, 21)
+    norm = np.random.default_rng(22).uniform(0.002, 0.02, 27)
+    P = random_params(23, 0.3)          # not BF16-exact: the weights must be rounded too
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
+    r = orc.closure_eval_rounded(cfg, f, None, P, norm)
+    W1, b1, W2, b2, W3, b3 = unpack_r(orc, P)
+    gelu = lambda a: torch.nn.functional.gelu(torch.from_numpy(a)).numpy()
+    x = orc.round_sig(orc.closure_inputs(f, norm), 8).reshape(-1, 27)
+    h1 = orc.round_sig(gelu(x @ W1.T + b1), 8).reshape(-1, 32)
+    h2 = orc.round_sig(gelu(h1 @ W2.T + b2), 8).reshape(-1, 32)
+    om = 0.5 + 1.45 / (1.0 + np.exp(-(h2 @ W3.T + b3)))
+    assert np.abs(r["omega"] - om).max() < 1e-13
+    ref = np.concatenate([orc.collide(orc.Cfg(lattice="D3Q27", tau={2: 0.6, **{n + 3: 1 / om[k, n] for n in range(4)}}),
+                                      f[k:k + 1]) for k in range(len(f))])
+    assert np.abs(r["fs"] - ref).max() < 1e-14
+    plain, _ = orc.collide_closure(cfg, f, P, norm)
+    assert np.abs(r["fs"] - plain).max() > 1e-7   # the rounding is really applied
+
+
+@pytest.mark.parametrize("tie", [False, True])
+def test_rounded_gradient_is_exact_gradient_of_offset_network(orc, tie):
+    """The rounded evaluation's gradient (with respect to the master weights,
+    the rounding passing derivatives unchanged) is the exact gradient of the
+    network that uses the rounded weights and whose rounded operands are the
+    exact values plus the (constant) rounding errors: equal objectives, and
+    central finite differences of the latter match every bias entry and a
+    sample of weights."""
+    f = states(orc, 9, 24)
+    fbar = states(orc, 9, 25)
+    norm = np.random.default_rng(26).uniform(0.002, 0.02, 27)
+    Pm = random_params(27, 0.3)        # master weights, not BF16 values
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.55})
+    r = orc.closure_eval_rounded(cfg, f, fbar, Pm, norm, tie_even=tie)
+    off = r["offsets"]
+    assert np.abs(off).max() > 0
+    # the weights the rounded network uses; biases stay as given
+    P = np.concatenate([a.reshape(-1) for a in unpack_r(orc, Pm)])
+    assert np.abs(P - Pm).max() > 0
+    L0 = orc.closure_loss_offsets(cfg, f, fbar, P, norm, off, tie_even=tie)
+    assert L0 == pytest.approx(r["loss"], rel=1e-14)
+    rng = np.random.default_rng(28)
+    idx = np.concatenate([rng.choice(864, 8, replace=False), 864 + np.arange(32),
+                          896 + rng.choice(1024, 8, replace=False), 1920 + np.arange(32),
+                          1952 + rng.choice(128, 8, replace=False), 2080 + np.arange(4)])
+    h = 1e-4
+    for k in idx:
+        Pp, Pn = P.copy(), P.copy()
+        Pp[k] += h
+        Pn[k] -= h
+        fd = (orc.closure_loss_offsets(cfg, f, fbar, Pp, norm, off, tie)
+              - orc.closure_loss_offsets(cfg, f, fbar, Pn, norm, off, tie)) / (2 * h)
+        assert r["grad"][k] == pytest.approx(fd, rel=1e-6, abs=1e-12), k
+
+
+def test_rounding_to_many_bits_is_the_fp64_network(orc):
+    """With 52 significant bits every rounding is the identity on these
+    values: f*, objective and gradient equal the unrounded oracle's."""
+    f = states(orc, 7, 29)
+    fbar = states(orc, 7, 30)
+    norm = np.random.default_rng(31).uniform(0.002, 0.02, 27)
+    P = random_params(32, 0.3)
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
+    r = orc.closure_eval_rounded(cfg, f, fbar, P, norm, bits=53)
+    L0, g = orc.closure_loss_grad(cfg, f, fbar, P, norm)
+    fs, om = orc.collide_closure(cfg, f, P, norm)
+    assert np.abs(r["fs"] - fs).max() < 1e-15 and np.abs(r["omega"] - om).max() < 1e-15
+    assert r["loss"] == pytest.approx(L0, rel=1e-13)
+    assert np.abs(r["grad"] - g).max() <= 1e-12 * np.abs(g).max()
+
+
+def test_flip_bound_counts_ambiguous_roundings(orc):
+    """With no error model nothing is ambiguous and the bounds vanish; with
+    one, each ambiguous rounding flipped alone changes the result by at most
+    its bound (the bound is the sum of those changes)."""
+    f = states(orc, 6, 33)
+    fbar = states(orc, 6, 34)
+    norm = np.random.default_rng(35).uniform(0.002, 0.02, 27)
+    P = bf16_params(36)
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
+    r0 = orc.closure_eval_rounded(cfg, f, fbar, P, norm)
+    assert not r0["bound_fs"].any() and not r0["bound_grad"].any()
+    r1 = orc.closure_eval_rounded(cfg, f, fbar, P, norm, err=(1e-3, 1e-3, 1e-3))
+    assert r1["bound_fs"].max() > 0 and r1["bound_grad"].max() > 0
+    assert np.array_equal(r1["grad"], r0["grad"]) and np.array_equal(r1["fs"], r0["fs"])
+    # the bound covers one, then two more bits of rounding of the same network
+    r9 = orc.closure_eval_rounded(cfg, f, fbar, P, norm, bits=9)
+    assert np.abs(r9["omega"] - r0["omega"]).max() < 0.05
