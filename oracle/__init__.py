@@ -322,16 +322,16 @@ def round_sig(v, bits=8):
 
 
 def closure_eval_rounded(cfg: Cfg, f, fbar, params, norm, tie_even=False, bits=8, rho0=1.0,
-                         err=(0.0, 0.0, 0.0)):
+                         err=(0.0, 0.0, 0.0, 0.0)):
     """The closure network with its weights, inputs and hidden activations
     rounded to `bits` significant bits (the library's BF16 operands), in FP64
     otherwise.  fbar=None evaluates the collision only.  err = (ex, eh_rel,
-    eh_sum) models the pre-rounding errors of another evaluation of the same
-    network (see orc_closure_eval_rounded); returns a dict with f* [n, 27],
-    omega [n, 4], and with fbar the objective, its gradient, per-entry bounds
-    ``bound_grad`` (2084 entries, then the objective) and ``abs_grad``
-    (sum over nodes of |node share|), ``bound_fs`` [n, 27] and the rounding
-    ``offsets`` [n, MLP_NQ]."""
+    eh_sum, egelu') models the errors of another evaluation of the same
+    network before each rounding (see orc_closure_eval_rounded); returns a
+    dict with f* [n, 27], omega [n, 4], ``bound_fs`` [n, 27] and the rounding
+    ``offsets`` [n, MLP_NQ], and with fbar the objective, its gradient,
+    per-entry bounds ``bound_grad`` (2084 entries, then the objective) and
+    ``abs_grad`` (sum over nodes of |node share|)."""
     f = np.ascontiguousarray(np.atleast_2d(f), np.float64)
     n = f.shape[0]
     fb = None if fbar is None else np.ascontiguousarray(np.atleast_2d(fbar), np.float64)

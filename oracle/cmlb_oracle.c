@@ -974,16 +974,15 @@ static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
  * passes through a rounding unchanged (the rounding error is a constant of
  * the evaluation), so the backward pass uses the rounded weights and the
  * rounded activations.
- *   flip:   per rounded quantity, take the other of the two representable
- *           values around it (used to bound the effect of a rounding that a
- *           slightly different evaluation could take the other way);
  *   offset: per rounded quantity, add this constant instead of rounding, with
  *           the weights as given (the network whose exact gradient the
- *           rounded network's gradient is). */
+ *           rounded network's gradient is);
+ *   xset:   the rounded inputs take these values (one of the roundings that
+ *           another evaluation may arrive at). */
 typedef struct {
     int bits;
-    const unsigned char *flip;
     const double *offset;
+    const double *xset;
 } mlp_round;
 
 /* Nearest value with `bits` significant bits, ties to even; *lo and *hi
@@ -1018,10 +1017,7 @@ static double mlp_q(const mlp_round *q, int k, double v)
     if (!q) return v;
     if (q->offset) return v + q->offset[k];
     if (q->bits <= 0) return v;
-    double lo, hi;
-    double r = round_sig(v, q->bits, &lo, &hi);
-    if (q->flip && q->flip[k]) r = (r == lo) ? hi : lo;
-    return r;
+    return round_sig(v, q->bits, NULL, NULL);
 }
 
 /* pre-rounding values (x, h1, h2), the values used (xr, h1r, h2r), the
@@ -1030,7 +1026,7 @@ typedef struct {
     double x[MLP_NIN], xr[MLP_NIN];
     double a1[MLP_NH], h1[MLP_NH], h1r[MLP_NH], s1[MLP_NH];
     double a2[MLP_NH], h2[MLP_NH], h2r[MLP_NH], s2[MLP_NH];
-    double z[MLP_NOUT];
+    double z[MLP_NOUT], s3[MLP_NOUT];
 } mlp_trace;
 
 /* s1, s2: |b| + sum |W in| of each pre-activation (the scale of its sum) */
@@ -1040,7 +1036,7 @@ static void mlp_forward(const double *P, const double *x, const mlp_round *q, ml
     const double *W3 = b2 + MLP_NH, *b3 = W3 + MLP_NOUT * MLP_NH;
     for (int k = 0; k < MLP_NIN; ++k) {
         t->x[k] = x[k];
-        t->xr[k] = mlp_q(q, k, x[k]);
+        t->xr[k] = (q && q->xset) ? q->xset[k] : mlp_q(q, k, x[k]);
     }
     for (int j = 0; j < MLP_NH; ++j) {
         double s = b1[j], m = fabs(b1[j]);
@@ -1067,9 +1063,14 @@ static void mlp_forward(const double *P, const double *x, const mlp_round *q, ml
         t->h2r[j] = mlp_q(q, MLP_NIN + MLP_NH + j, t->h2[j]);
     }
     for (int j = 0; j < MLP_NOUT; ++j) {
-        double s = b3[j];
-        for (int k = 0; k < MLP_NH; ++k) s += mlp_weight(q, W3[j * MLP_NH + k]) * t->h2r[k];
+        double s = b3[j], m = fabs(b3[j]);
+        for (int k = 0; k < MLP_NH; ++k) {
+            const double term = mlp_weight(q, W3[j * MLP_NH + k]) * t->h2r[k];
+            s += term;
+            m += fabs(term);
+        }
         t->z[j] = s;
+        t->s3[j] = m;
     }
 }
 
@@ -1245,7 +1246,7 @@ int orc_closure_loss_offsets(const orc_cfg *cfg, int n, const double *f, const d
     if (cfg->lattice != ORC_D3Q27 || cfg->model != ORC_CM || n < 1) return -1;
     double loss = 0.0;
     for (int k = 0; k < n; ++k) {
-        mlp_round q = {0, NULL, offsets + (size_t)k * MLP_NQ};
+        mlp_round q = {0, offsets + (size_t)k * MLP_NQ, NULL};
         mlp_trace t;
         double fs[27], l;
         closure_node(L, cfg, f + (size_t)k * 27, fbar + (size_t)k * 27, params, norm, tie_even, 1.0 / n, &q, &t,
@@ -1256,21 +1257,248 @@ int orc_closure_loss_offsets(const orc_cfg *cfg, int n, const double *f, const d
     return 0;
 }
 
+/* Deviation of a rounded quantity: the other evaluation computes v with an
+ * error of at most d, so its rounded value lies between the roundings of
+ * v - d and v + d; returns the largest distance of those from `used` (0 if
+ * both equal it). */
+static double rounding_spread(double v, double d, double used, int bits)
+{
+    const double lo = round_sig(v - d, bits, NULL, NULL), hi = round_sig(v + d, bits, NULL, NULL);
+    return fmax(fabs(lo - used), fabs(hi - used));
+}
+
+/* Bounds of one node's outputs when its rounded inputs may deviate by dx
+ * and the later operands follow the error model (see
+ * orc_closure_eval_rounded), by propagating deviation bounds through the
+ * rounded network and its backward pass: each product |a b| deviates by at
+ * most |da| |b| + |a| |db| + |da| |db|, each sum by the sum of |coefficient|
+ * times the deviations, a smooth map by its derivative times the deviation
+ * plus half its largest second derivative times the deviation squared
+ * (|GELU''| <= 0.8, |sigmoid''| <= 0.1).  f* is affine in each omega_j with
+ * slopes D_ij that do not depend on the rates, so its deviation is exactly
+ * sum_j |D_ij| |d omega_j|. */
+static void interval_bounds(const orc_lattice *L, const orc_cfg *cfg, const double *f, const double *fbar,
+                            const double *P, int tie_even, double inv_n, int bits, const double *err,
+                            const mlp_trace *t, const double *fs, const double *dx, double *bfs, double *bgrad)
+{
+    const double *W1 = P, *W2 = W1 + MLP_NH * MLP_NIN + MLP_NH, *W3 = W2 + MLP_NH * MLP_NH + MLP_NH;
+    const mlp_round q = {bits, NULL, NULL};
+    const double G2 = 0.8, S2 = 0.1;
+    /* layer 1 */
+    double da1[MLP_NH], dh1[MLP_NH];
+    for (int j = 0; j < MLP_NH; ++j) {
+        double s = 0.0;
+        for (int m = 0; m < MLP_NIN; ++m) s += fabs(mlp_weight(&q, W1[j * MLP_NIN + m])) * dx[m];
+        da1[j] = s;
+        const double d = fabs(gelu_grad(t->a1[j])) * s + 0.5 * G2 * s * s + err[1] * fabs(t->a1[j]) + err[2] * t->s1[j];
+        dh1[j] = rounding_spread(t->h1[j], d, t->h1r[j], bits);
+    }
+    /* layer 2 */
+    double da2[MLP_NH], dh2[MLP_NH];
+    for (int j = 0; j < MLP_NH; ++j) {
+        double s = 0.0;
+        for (int m = 0; m < MLP_NH; ++m) s += fabs(mlp_weight(&q, W2[j * MLP_NH + m])) * dh1[m];
+        da2[j] = s;
+        const double d = fabs(gelu_grad(t->a2[j])) * s + 0.5 * G2 * s * s + err[1] * fabs(t->a2[j]) + err[2] * t->s2[j];
+        dh2[j] = rounding_spread(t->h2[j], d, t->h2r[j], bits);
+    }
+    /* logits and rates */
+    double dz[MLP_NOUT], dom[MLP_NOUT], sg[MLP_NOUT];
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        double s = err[2] * t->s3[j];
+        for (int m = 0; m < MLP_NH; ++m) s += fabs(mlp_weight(&q, W3[j * MLP_NH + m])) * dh2[m];
+        dz[j] = s;
+        const double sj = sigmoid(t->z[j]);
+        sg[j] = sj * (1.0 - sj);
+        dom[j] = 1.45 * (sg[j] * s + 0.5 * S2 * s * s);
+        if (tie_even && (j == 1 || j == 3)) dom[j] = 0.0;
+    }
+    /* slopes of f* in each rate, and the deviation of f* */
+    orc_cfg c = *cfg;
+    for (int j = 0; j < MLP_NOUT; ++j) c.omega[3 + j] = rate_from_logit(t->z[j]);
+    if (tie_even) c.omega[4] = c.omega[6] = cfg->omega[2];
+    double D[MLP_NOUT][27], dfs[27];
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        orc_cfg c1 = c, c0 = c;
+        c1.omega[3 + j] = 1.0;
+        c0.omega[3 + j] = 0.0;
+        double g1[27], g0[27];
+        collide_tp(L, &c1, f, g1);
+        collide_tp(L, &c0, f, g0);
+        for (int i = 0; i < 27; ++i) D[j][i] = g1[i] - g0[i];
+    }
+    for (int i = 0; i < 27; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < MLP_NOUT; ++j) s += fabs(D[j][i]) * dom[j];
+        dfs[i] = s;
+        if (bfs) bfs[i] += s;
+    }
+    if (!fbar || !bgrad) return;
+    /* objective and residuals */
+    double r[27], dr[27], dl = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        const double e = fs[i] - fbar[i];
+        r[i] = 2.0 * e / L->w[i] * inv_n;
+        dr[i] = 2.0 * dfs[i] / L->w[i] * inv_n;
+        dl += (2.0 * fabs(e) * dfs[i] + dfs[i] * dfs[i]) / L->w[i] * inv_n;
+    }
+    bgrad[MLP_NPARAM] += dl;
+    /* backward: d objective / d z and its deviation */
+    double gz[MLP_NOUT], dgz[MLP_NOUT];
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        double G = 0.0, dG = 0.0;
+        for (int i = 0; i < 27; ++i) {
+            G += r[i] * D[j][i];
+            dG += dr[i] * fabs(D[j][i]);
+        }
+        const double s = 1.45 * sg[j], ds = 1.45 * S2 * dz[j];
+        gz[j] = G * s;
+        dgz[j] = dG * fabs(s) + fabs(G) * ds + dG * ds;
+        if (tie_even && (j == 1 || j == 3)) gz[j] = dgz[j] = 0.0;
+    }
+    double *bW1 = bgrad, *bb1 = bW1 + MLP_NH * MLP_NIN, *bW2 = bb1 + MLP_NH, *bb2 = bW2 + MLP_NH * MLP_NH;
+    double *bW3 = bb2 + MLP_NH, *bb3 = bW3 + MLP_NOUT * MLP_NH;
+    for (int j = 0; j < MLP_NOUT; ++j) {
+        bb3[j] += dgz[j];
+        for (int m = 0; m < MLP_NH; ++m)
+            bW3[j * MLP_NH + m] += dgz[j] * fabs(t->h2r[m]) + fabs(gz[j]) * dh2[m] + dgz[j] * dh2[m];
+    }
+    /* layer 2 backward */
+    double g2[MLP_NH], dg2[MLP_NH];
+    for (int m = 0; m < MLP_NH; ++m) {
+        double hsum = 0.0, dhsum = 0.0;
+        for (int j = 0; j < MLP_NOUT; ++j) {
+            const double w = mlp_weight(&q, W3[j * MLP_NH + m]);
+            hsum += w * gz[j];
+            dhsum += fabs(w) * dgz[j];
+        }
+        const double gp = gelu_grad(t->a2[m]), dgp = G2 * da2[m] + err[3];
+        g2[m] = hsum * gp;
+        dg2[m] = dhsum * fabs(gp) + fabs(hsum) * dgp + dhsum * dgp;
+    }
+    for (int j = 0; j < MLP_NH; ++j) {
+        bb2[j] += dg2[j];
+        for (int m = 0; m < MLP_NH; ++m)
+            bW2[j * MLP_NH + m] += dg2[j] * fabs(t->h1r[m]) + fabs(g2[j]) * dh1[m] + dg2[j] * dh1[m];
+    }
+    /* layer 1 backward */
+    double g1v[MLP_NH], dg1[MLP_NH];
+    for (int m = 0; m < MLP_NH; ++m) {
+        double hsum = 0.0, dhsum = 0.0;
+        for (int j = 0; j < MLP_NH; ++j) {
+            const double w = mlp_weight(&q, W2[j * MLP_NH + m]);
+            hsum += w * g2[j];
+            dhsum += fabs(w) * dg2[j];
+        }
+        const double gp = gelu_grad(t->a1[m]), dgp = G2 * da1[m] + err[3];
+        g1v[m] = hsum * gp;
+        dg1[m] = dhsum * fabs(gp) + fabs(hsum) * dgp + dhsum * dgp;
+    }
+    for (int j = 0; j < MLP_NH; ++j) {
+        bb1[j] += dg1[j];
+        for (int m = 0; m < MLP_NIN; ++m)
+            bW1[j * MLP_NIN + m] += dg1[j] * fabs(t->xr[m]) + fabs(g1v[j]) * dx[m] + dg1[j] * dx[m];
+    }
+}
+
+/* Bounds of one node's outputs under the error model.  The inputs x are
+ * where a different rounding moves the network most (one step of x moves
+ * every pre-activation of layer 1), so their alternatives are enumerated:
+ * every input whose error interval rounds to other values than x_r takes
+ * each of them in turn (all combinations, at most 3^5), the node is
+ * evaluated for each, and its bound is the largest of |change| plus the
+ * propagated bound of that evaluation.  With more ambiguous inputs the
+ * input deviations are propagated as intervals instead. */
+static void closure_node_bounds(const orc_lattice *L, const orc_cfg *cfg, const double *f, const double *fbar,
+                                const double *P, const double *norm, int tie_even, double inv_n, int bits,
+                                double rho0, const double *err, const mlp_trace *t, const double *fs,
+                                const double *g0, double *bfs, double *bgrad)
+{
+    const int ng = MLP_NPARAM + 1;
+    double rho = 0.0, dev = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        rho += f[i];
+        dev += fabs(f[i] - L->w[i] * rho0);
+    }
+    int amb[MLP_NIN], na = 0;
+    double alt[MLP_NIN][3];
+    int nalt[MLP_NIN];
+    double dx[MLP_NIN];
+    for (int m = 0; m < MLP_NIN; ++m) {
+        const double d = err[0] * dev / (rho * norm[m]);
+        dx[m] = rounding_spread(t->x[m], d, t->xr[m], bits);
+        if (dx[m] == 0.0) continue;
+        /* the representable values in the interval, the one used first */
+        const double lo = round_sig(t->x[m] - d, bits, NULL, NULL), hi = round_sig(t->x[m] + d, bits, NULL, NULL);
+        nalt[m] = 0;
+        alt[m][nalt[m]++] = t->xr[m];
+        if (lo != t->xr[m]) alt[m][nalt[m]++] = lo;
+        if (hi != t->xr[m] && hi != lo) alt[m][nalt[m]++] = hi;
+        amb[na++] = m;
+    }
+    double zero[MLP_NIN];
+    memset(zero, 0, sizeof zero);
+    int combos = 1;
+    for (int a = 0; a < na && combos <= 243; ++a) combos *= nalt[amb[a]];
+    if (na == 0 || combos > 243) {
+        interval_bounds(L, cfg, f, fbar, P, tie_even, inv_n, bits, err, t, fs, na ? dx : zero, bfs, bgrad);
+        return;
+    }
+    double *gc = (double *)calloc((size_t)ng, sizeof(double));
+    double *bgc = (double *)calloc((size_t)ng, sizeof(double));
+    double *worst = (double *)calloc((size_t)ng, sizeof(double));
+    if (!gc || !bgc || !worst) {   /* out of memory: fall back to the interval form */
+        free(gc); free(bgc); free(worst);
+        interval_bounds(L, cfg, f, fbar, P, tie_even, inv_n, bits, err, t, fs, dx, bfs, bgrad);
+        return;
+    }
+    double wfs[27];
+    memset(wfs, 0, sizeof wfs);
+    for (int c = 0; c < combos; ++c) {
+        double xs[MLP_NIN];
+        memcpy(xs, t->xr, sizeof xs);
+        for (int a = 0, rem = c; a < na; ++a) {
+            const int m = amb[a];
+            xs[m] = alt[m][rem % nalt[m]];
+            rem /= nalt[m];
+        }
+        const mlp_round q = {bits, NULL, xs};
+        mlp_trace tc;
+        double fsc[27], bfc[27], lc = 0.0;
+        memset(gc, 0, sizeof(double) * ng);
+        memset(bgc, 0, sizeof(double) * ng);
+        memset(bfc, 0, sizeof bfc);
+        closure_node(L, cfg, f, fbar, P, norm, tie_even, inv_n, &q, &tc, fsc, NULL, &lc, (fbar && bgrad) ? gc : NULL);
+        gc[MLP_NPARAM] = lc;
+        interval_bounds(L, cfg, f, fbar, P, tie_even, inv_n, bits, err, &tc, fsc, zero, bfc, (fbar && bgrad) ? bgc : NULL);
+        for (int i = 0; i < 27; ++i) wfs[i] = fmax(wfs[i], fabs(fsc[i] - fs[i]) + bfc[i]);
+        if (fbar && bgrad)
+            for (int e = 0; e < ng; ++e) worst[e] = fmax(worst[e], fabs(gc[e] - g0[e]) + bgc[e]);
+    }
+    if (bfs)
+        for (int i = 0; i < 27; ++i) bfs[i] += wfs[i];
+    if (fbar && bgrad)
+        for (int e = 0; e < ng; ++e) bgrad[e] += worst[e];
+    free(gc);
+    free(bgc);
+    free(worst);
+}
+
 /* The closure collision (and, with fbar, the objective and its gradient)
  * with the network's operands rounded to `bits` significant bits, plus
  * per-element bounds on how far an evaluation of the same network may land
- * from these values when it computes the quantities before each rounding
- * with small errors of its own: where such a quantity lies closer to the
- * midpoint between its two representable neighbours than that error, the
- * other evaluation may round it the other way.  For every such quantity
- * the node is evaluated again with that one rounding flipped, and the
- * absolute changes of f*, of the objective and of the node's gradient share
- * are summed into bound_fs, bound_grad[MLP_NPARAM] (objective) and
- * bound_grad[0..]; abs_grad accumulates |node share| per entry (the scale of
- * the sums' own rounding).  The error model err[3] of the other
- * evaluation's pre-rounding values:
+ * from these values when it computes what it rounds, and the derivative of
+ * GELU, with small errors of its own.  Error model err[4] of that
+ * evaluation, before each rounding:
  *   x_p:  err[0] * sum_i |f_i - w_i rho0| / (rho sigma_p)
- *   h:    err[1] * |a| + err[2] * (|b| + sum |W in|)   (a the pre-activation).
+ *   h:    err[1] * |a| + err[2] * (|b| + sum |W in|)   (a the pre-activation;
+ *         the logits z carry err[2] * (|b| + sum |W h|))
+ *   GELU'(a): err[3] (absolute).
+ * Where the error interval of a quantity rounds to other values than this
+ * evaluation's, their distance is carried forward (closure_node_bounds).
+ * bound_fs[n][27], bound_grad[MLP_NPARAM] (objective) and bound_grad[0..]
+ * receive the propagated bounds; abs_grad accumulates |node share| per
+ * entry (the scale of the FP32 rounding of the other evaluation's sums).
  * offsets (optional, [n][MLP_NQ]) receives the rounding errors used. */
 int orc_closure_eval_rounded(const orc_cfg *cfg, int n, const double *f, const double *fbar, const double *params,
                              const double *norm, int tie_even, int bits, double rho0, const double *err,
@@ -1283,16 +1511,15 @@ int orc_closure_eval_rounded(const orc_cfg *cfg, int n, const double *f, const d
     if (grad) memset(grad, 0, sizeof(double) * MLP_NPARAM);
     if (bound_grad) memset(bound_grad, 0, sizeof(double) * ng);
     if (abs_grad) memset(abs_grad, 0, sizeof(double) * ng);
-    double *g0 = (double *)malloc(sizeof(double) * ng), *g1 = (double *)malloc(sizeof(double) * ng);
-    if (!g0 || !g1) { free(g0); free(g1); return -2; }
+    if (bound_fs) memset(bound_fs, 0, sizeof(double) * 27 * (size_t)n);
+    double *g0 = (double *)malloc(sizeof(double) * ng);
+    if (!g0) return -2;
     double loss = 0.0;
     for (int k = 0; k < n; ++k) {
         const double *fk = f + (size_t)k * 27, *tk = fbar ? fbar + (size_t)k * 27 : NULL;
-        unsigned char flip[MLP_NQ];
-        memset(flip, 0, sizeof flip);
-        mlp_round q = {bits, flip, NULL};
-        mlp_trace t, t1;
-        double fs[27], fs1[27], l0 = 0.0, l1 = 0.0;
+        const mlp_round q = {bits, NULL, NULL};
+        mlp_trace t;
+        double fs[27], l0 = 0.0;
         memset(g0, 0, sizeof(double) * ng);
         closure_node(L, cfg, fk, tk, params, norm, tie_even, 1.0 / n, &q, &t, fs, omega_out + (size_t)k * MLP_NOUT,
                      &l0, (tk && grad) ? g0 : NULL);
@@ -1311,43 +1538,12 @@ int orc_closure_eval_rounded(const orc_cfg *cfg, int n, const double *f, const d
                 o[MLP_NIN + MLP_NH + m] = t.h2r[m] - t.h2[m];
             }
         }
-        if (!bound_fs && !bound_grad) continue;
-        /* pre-rounding values and their error bounds */
-        double rho = 0.0, dev = 0.0;
-        for (int i = 0; i < 27; ++i) {
-            rho += fk[i];
-            dev += fabs(fk[i] - L->w[i] * rho0);
-        }
-        double val[MLP_NQ], tol[MLP_NQ];
-        for (int m = 0; m < MLP_NIN; ++m) {
-            val[m] = t.x[m];
-            tol[m] = err[0] * dev / (rho * norm[m]);
-        }
-        for (int m = 0; m < MLP_NH; ++m) {
-            val[MLP_NIN + m] = t.h1[m];
-            tol[MLP_NIN + m] = err[1] * fabs(t.a1[m]) + err[2] * t.s1[m];
-            val[MLP_NIN + MLP_NH + m] = t.h2[m];
-            tol[MLP_NIN + MLP_NH + m] = err[1] * fabs(t.a2[m]) + err[2] * t.s2[m];
-        }
-        for (int m = 0; m < MLP_NQ; ++m) {
-            double lo, hi;
-            round_sig(val[m], bits, &lo, &hi);
-            if (lo == hi || fabs(val[m] - 0.5 * (lo + hi)) >= tol[m]) continue;
-            flip[m] = 1;
-            memset(g1, 0, sizeof(double) * ng);
-            closure_node(L, cfg, fk, tk, params, norm, tie_even, 1.0 / n, &q, &t1, fs1, NULL, &l1,
-                         (tk && grad) ? g1 : NULL);
-            g1[MLP_NPARAM] = l1;
-            flip[m] = 0;
-            if (bound_fs)
-                for (int i = 0; i < 27; ++i) bound_fs[(size_t)k * 27 + i] += fabs(fs1[i] - fs[i]);
-            if (bound_grad && tk)
-                for (int e = 0; e < ng; ++e) bound_grad[e] += fabs(g1[e] - g0[e]);
-        }
+        if (bound_fs || bound_grad)
+            closure_node_bounds(L, cfg, fk, tk, params, norm, tie_even, 1.0 / n, bits, rho0, err, &t, fs, g0,
+                                bound_fs ? bound_fs + (size_t)k * 27 : NULL, tk ? bound_grad : NULL);
     }
     if (loss_out) *loss_out = loss;
     free(g0);
-    free(g1);
     return 0;
 }
 

@@ -229,7 +229,9 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
             }
         }
         __syncthreads();
-        // backward through the hidden layers, one node per lane
+        // backward through the hidden layers, one node per lane.  The weight
+        // gradients use the activations the forward pass fed to the next
+        // layer: GELU of the same FP32 pre-activation, rounded to BF16.
         {
             float d2[kNH];
             const float dz0 = DZ[lane][0], dz1 = DZ[lane][1], dz2 = DZ[lane][2], dz3 = DZ[lane][3];
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
                 const float a2 = H2[lane][k];
                 const float s = net->w3f[0][k] * dz0 + net->w3f[1][k] * dz1 + net->w3f[2][k] * dz2 + net->w3f[3][k] * dz3;
                 d2[k] = s * gelu_grad_f(a2);
-                H2[lane][k] = gelu_f(a2);
+                H2[lane][k] = (float)(__bf16)gelu_f(a2);
                 D2[lane][k] = d2[k];
             }
 #pragma unroll 2
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
                 for (int j = 0; j < kNH; ++j) s += net->w2f[j][k] * d2[j];
                 const float a1 = H1[lane][k];
                 D1[lane][k] = s * gelu_grad_f(a1);
-                H1[lane][k] = gelu_f(a1);
+                H1[lane][k] = (float)(__bf16)gelu_f(a1);
             }
         }
         __syncthreads();

@@ -24,7 +24,7 @@ import pytest
 from paper_1808_04406_amd import inputs
 
 from test_gpu_parity import TOL, f16_scales, quantise
-from test_gpu_closure import params
+from test_gpu_closure import ERR_MODEL, params
 
 pytestmark = pytest.mark.gpu
 
@@ -212,10 +212,12 @@ def test_closure_128_sampled(cm, orc):
     nodes = np.concatenate([rng.choice(n ** 3, 3000, replace=False), [0, n - 1, n ** 3 - 1]])
     fin = orc.gather_nodes("D3Q27", S, nodes)
     cfg = orc.Cfg(lattice="D3Q27", tau={2: t2})
-    ref, om = orc.collide_closure(cfg, fin, P, sigma)
-    plain = orc.collide(orc.Cfg(lattice="D3Q27", tau={2: t2}, tau_hi=1.0), fin)
-    assert om.std() > 0.05
-    controlled = np.abs(ref - plain).max()
-    err = np.abs(got[:, nodes].T - ref).max()
-    print(f"closure 128^3 sampled: max|df| = {err:.3e}, network-controlled part {controlled:.3e}")
-    assert err <= 0.02 * controlled + 2e-6 * np.abs(ref - w[:, 0, 0, 0]).max()
+    # the network as the library defines it (BF16 operands), with the
+    # per-element bound of the closure parity tests
+    r = orc.closure_eval_rounded(cfg, fin, None, P, sigma, err=ERR_MODEL)
+    ref = r["fs"]
+    assert r["omega"].std() > 0.05
+    bound = r["bound_fs"] + 2e-6 * np.abs(ref - w[:, 0, 0, 0]).max()
+    err = np.abs(got[:, nodes].T - ref)
+    print(f"closure 128^3 sampled: max|df| = {err.max():.3e}, max err/bound = {(err / bound).max():.3f}")
+    assert (err <= bound).all()

@@ -239,10 +239,10 @@ def test_rounding_to_many_bits_is_the_fp64_network(orc):
     assert np.abs(r["grad"] - g).max() <= 1e-12 * np.abs(g).max()
 
 
-def test_flip_bound_counts_ambiguous_roundings(orc):
-    """With no error model nothing is ambiguous and the bounds vanish; with
-    one, each ambiguous rounding flipped alone changes the result by at most
-    its bound (the bound is the sum of those changes)."""
+def test_bounds_follow_the_error_model(orc):
+    """With no error model every rounding is certain and the bounds vanish;
+    with one they are positive, leave the values unchanged, and grow with
+    the modelled errors."""
     f = states(orc, 6, 33)
     fbar = states(orc, 6, 34)
     norm = np.random.default_rng(35).uniform(0.002, 0.02, 27)
@@ -250,9 +250,32 @@ def test_flip_bound_counts_ambiguous_roundings(orc):
     cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
     r0 = orc.closure_eval_rounded(cfg, f, fbar, P, norm)
     assert not r0["bound_fs"].any() and not r0["bound_grad"].any()
-    r1 = orc.closure_eval_rounded(cfg, f, fbar, P, norm, err=(1e-3, 1e-3, 1e-3))
+    r1 = orc.closure_eval_rounded(cfg, f, fbar, P, norm, err=(1e-4, 1e-4, 1e-4, 1e-4))
+    r2 = orc.closure_eval_rounded(cfg, f, fbar, P, norm, err=(1e-3, 1e-3, 1e-3, 1e-3))
     assert r1["bound_fs"].max() > 0 and r1["bound_grad"].max() > 0
     assert np.array_equal(r1["grad"], r0["grad"]) and np.array_equal(r1["fs"], r0["fs"])
-    # the bound covers one, then two more bits of rounding of the same network
-    r9 = orc.closure_eval_rounded(cfg, f, fbar, P, norm, bits=9)
-    assert np.abs(r9["omega"] - r0["omega"]).max() < 0.05
+    assert (r2["bound_fs"] >= r1["bound_fs"]).all() and (r2["bound_grad"] >= r1["bound_grad"]).all()
+
+
+def test_bounds_cover_a_perturbed_evaluation(orc):
+    """The bound of the rounded network covers the same network evaluated
+    with its pre-rounding quantities actually perturbed within the model:
+    here every GELU is replaced by GELU * (1 + 1e-3), inside a model of
+    eh_rel = 1.2e-3 (|GELU(a)| <= |a|), and every rate, f* and objective
+    then stays within the bounds."""
+    f = states(orc, 40, 37)
+    norm = np.random.default_rng(38).uniform(0.002, 0.02, 27)
+    P = bf16_params(39)
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.6})
+    r = orc.closure_eval_rounded(cfg, f, None, P, norm, err=(0.0, 1.2e-3, 0.0, 0.0))
+    W1, b1, W2, b2, W3, b3 = unpack(P)
+    import torch
+    gelu = lambda a: torch.nn.functional.gelu(torch.from_numpy(a)).numpy() * (1 + 1e-3)
+    x = orc.round_sig(orc.closure_inputs(f, norm), 8).reshape(-1, 27)
+    h1 = orc.round_sig(gelu(x @ W1.T + b1), 8).reshape(-1, 32)
+    h2 = orc.round_sig(gelu(h1 @ W2.T + b2), 8).reshape(-1, 32)
+    om = 0.5 + 1.45 / (1.0 + np.exp(-(h2 @ W3.T + b3)))
+    fs = np.concatenate([orc.collide(orc.Cfg(lattice="D3Q27", tau={2: 0.6, **{n + 3: 1 / om[k, n] for n in range(4)}}),
+                                     f[k:k + 1]) for k in range(len(f))])
+    assert np.abs(fs - r["fs"]).max() > 0          # the perturbation changes some roundings
+    assert (np.abs(fs - r["fs"]) <= r["bound_fs"] * (1 + 1e-9) + 1e-15).all()
