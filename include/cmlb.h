@@ -275,6 +275,25 @@ int cmlb_set_populations(cmlb_ctx *ctx, const double *f);
  * Returns CMLB_EUNSTABLE (with *out filled) if any population is not finite. */
 int cmlb_reduce(cmlb_ctx *ctx, cmlb_globals *out);
 
+/* ---- Allocation-free diagnostics ----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Computes
+ * exactly what cmlb_reduce computes, with the same kernels, but keeps their
+ * scratch (the FP64 velocity field of the enstrophy pass, the per-block
+ * partial sums and the final sums) in a fixed device array of
+ * CMLB_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends; it calls no hipMalloc or hipFree.  Grids of at
+ * most CMLB_NOALLOC_MAX_NODES nodes (for example 128^3, or 1536^2); larger
+ * grids get CMLB_EINVAL and nothing is launched.  All calls on one device
+ * share its array: calls that overlap on one GPU (from several host
+ * threads) race, and the caller must serialise them.  Every entry of the
+ * array is written before it is read, so no call depends on what an earlier
+ * one left there.  Synchronises the context stream; returns CMLB_EUNSTABLE
+ * like cmlb_reduce. */
+#define CMLB_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define CMLB_NOALLOC_MAX_NODES 2621440
+int cmlb_reduce_noalloc(cmlb_ctx *ctx, cmlb_globals *out);
+
 /* Device pointer and byte size of the current population buffer, and the
  * stream the library launches on (hipStream_t). */
 int cmlb_state(cmlb_ctx *ctx, void **f_cur, size_t *bytes, void **hip_stream);

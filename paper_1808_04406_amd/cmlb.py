@@ -93,6 +93,7 @@ def lib():
         L.cmlb_get_populations.argtypes = [vp, dp]
         L.cmlb_set_populations.argtypes = [vp, dp]
         L.cmlb_reduce.argtypes = [vp, P(Globals)]
+        L.cmlb_reduce_noalloc.argtypes = [vp, P(Globals)]
         L.cmlb_state.argtypes = [vp, P(vp), P(ctypes.c_size_t), P(vp)]
         L.cmlb_step_count.argtypes = [vp]
         L.cmlb_step_count.restype = c_i64
@@ -332,9 +333,12 @@ class Context:
         f = self._field(f, self.Q)
         self._check(lib().cmlb_set_populations(self.h, _dp(f)))
 
-    def reduce(self, allow_unstable=False):
+    def reduce(self, allow_unstable=False, noalloc=False):
+        """FP64 global diagnostics (cmlb_reduce; with noalloc=True
+        cmlb_reduce_noalloc, whose scratch is a fixed device array)."""
         g = Globals()
-        rc = lib().cmlb_reduce(self.h, ctypes.byref(g))
+        fn = lib().cmlb_reduce_noalloc if noalloc else lib().cmlb_reduce
+        rc = fn(self.h, ctypes.byref(g))
         if rc and not (allow_unstable and rc == EUNSTABLE):
             self._check(rc)
         return dict(mass=g.mass, momentum=np.array(list(g.momentum)), energy=g.energy,

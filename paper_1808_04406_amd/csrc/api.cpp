@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -723,25 +724,18 @@ int cmlb_set_populations(cmlb_ctx* c, const double* f) {
     return rc;
 }
 
-int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
-    if (!c) return CMLB_EINVAL;
-    if (!out) return fail(c, CMLB_EINVAL, "out is NULL");
-    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
-    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+// Launch the reduction kernels with the given scratch (uf: 3 x nodes
+// doubles; p1, p2: reduce_blocks(nodes) x kRedVals doubles each; out:
+// kRedVals doubles), read the sums back and fill *out.  Every scratch entry
+// is written before it is read, so nothing needs clearing between calls.
+static int reduce_with(cmlb_ctx* c, double* uf, double* p1, double* p2, double* out_dev, cmlb_globals* out) {
     hipError_t e;
-    const int nb = reduce_blocks(c->nodes);
-    if (!c->red_u) {
-        if ((e = hipMalloc(&c->red_u, c->nodes * 3 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_u = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
-        if ((e = hipMalloc(&c->red_p, (size_t)nb * 2 * kRedVals * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_p = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
-        if ((e = hipMalloc(&c->red_out, kRedVals * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_out = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
-    }
     StepArgs a = base_args(c);
     a.src = c->f[c->cur];
-    launch_reduce(c->p.lattice, c->p.storage, a, c->red_u, c->red_p, c->red_p + (size_t)nb * kRedVals, c->red_out,
-                  c->stream);
+    launch_reduce(c->p.lattice, c->p.storage, a, uf, p1, p2, out_dev, c->stream);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
     double v[kRedVals];
-    if ((e = hipMemcpyAsync(v, c->red_out, sizeof(v), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy");
+    if ((e = hipMemcpyAsync(v, out_dev, sizeof(v), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return hip_fail(c, e, "copy");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "reduce");
     double we2 = 0.0;
     for (int i = 0; i < c->L.Q; ++i)
@@ -759,6 +753,76 @@ int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
     out->u_max = std::sqrt(v[10]);
     if (out->n_nonfinite > 0) return fail(c, CMLB_EUNSTABLE, "non-finite populations in the state");
     return CMLB_OK;
+}
+
+int cmlb_reduce(cmlb_ctx* c, cmlb_globals* out) {
+    if (!c) return CMLB_EINVAL;
+    if (!out) return fail(c, CMLB_EINVAL, "out is NULL");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    hipError_t e;
+    const int nb = reduce_blocks(c->nodes);
+    if (!c->red_u) {
+        if ((e = hipMalloc(&c->red_u, c->nodes * 3 * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_u = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+        if ((e = hipMalloc(&c->red_p, (size_t)nb * 2 * kRedVals * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_p = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+        if ((e = hipMalloc(&c->red_out, kRedVals * sizeof(double))) != hipSuccess) { (void)hipGetLastError(); c->red_out = nullptr; return fail(c, CMLB_ENOMEM, "reduction scratch"); }
+    }
+    return reduce_with(c, c->red_u, c->red_p, c->red_p + (size_t)nb * kRedVals, c->red_out, out);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free reduction: the same kernels with their scratch in a
+// file-scope device array.  In host code `scratch` names a host-side stand-in,
+// not device memory; its device address on each GPU comes from
+// hipGetSymbolAddress (taken once per device, with that device current) and
+// only that address is ever passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[CMLB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 256;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device address of this device's scratch array (the device must be current).
+int scratch_address(cmlb_ctx* c, unsigned char** out) {
+    const int dev = c->p.device;
+    if (dev < 0 || dev >= kScratchDevices) return fail(c, CMLB_EINVAL, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(c, CMLB_EDEVICE, std::string("scratch symbol address: ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return CMLB_OK;
+}
+}  // namespace
+
+int cmlb_reduce_noalloc(cmlb_ctx* c, cmlb_globals* out) {
+    if (!c) return CMLB_EINVAL;
+    if (!out) return fail(c, CMLB_EINVAL, "out is NULL");
+    if (!c->initialised) return fail(c, CMLB_ESTATE, "state not initialised");
+    if (c->nodes > (uint64_t)CMLB_NOALLOC_MAX_NODES)
+        return fail(c, CMLB_EINVAL, "grid of " + std::to_string(c->nodes) + " nodes exceeds the allocation-free "
+                    "scratch (at most " + std::to_string(CMLB_NOALLOC_MAX_NODES) + " nodes)");
+    const int nb = reduce_blocks(c->nodes);
+    const size_t off_p1 = align256(c->nodes * 3 * sizeof(double));
+    const size_t off_p2 = off_p1 + align256((size_t)nb * kRedVals * sizeof(double));
+    const size_t off_out = off_p2 + align256((size_t)nb * kRedVals * sizeof(double));
+    if (off_out + kRedVals * sizeof(double) > (size_t)CMLB_NOALLOC_SCRATCH_BYTES)
+        return fail(c, CMLB_EINVAL, "reduction scratch larger than the allocation-free array");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    unsigned char* base = nullptr;
+    if (int rc = scratch_address(c, &base)) return rc;
+    return reduce_with(c, reinterpret_cast<double*>(base), reinterpret_cast<double*>(base + off_p1),
+                       reinterpret_cast<double*>(base + off_p2), reinterpret_cast<double*>(base + off_out), out);
 }
 
 int cmlb_state(cmlb_ctx* c, void** f_cur, size_t* bytes, void** stream) {
