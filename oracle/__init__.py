@@ -7,7 +7,10 @@ double precision); this module only marshals numpy arrays through ctypes, plus
 plain-definition analysis helpers (mode amplitudes, decay fits, closed-form
 dispersion relations, global diagnostics) in :mod:`oracle.analysis`.
 
-Lattice kinds: ``"D2Q9"``, ``"D3Q27"``, ``"D2Q37"``.  Velocities crossing
+Lattice kinds: ``"D2Q9"``, ``"D3Q27"``, ``"D2Q37"`` (also ``"E9A"``), and
+the other minimal 2D rules of Fig. 2: ``"E9B"``-``"E9D"`` (37 velocities,
+degree 9, N = M = 4) and ``"E7A"``-``"E7D"`` (17 velocities, degree 7,
+N = M = 3).  Velocities crossing
 this API are in lattice units (cells per step); theta is the paper's
 dimensionless temperature (reference value 1).
 """
@@ -24,7 +27,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cmlb_oracle.c")
 _LIB = os.path.join(_HERE, "libcmlb_oracle.so")
 
-KINDS = {"D2Q9": 0, "D3Q27": 1, "D2Q37": 2}
+KINDS = {"D2Q9": 0, "D3Q27": 1, "D2Q37": 2, "E9B": 3, "E9C": 4, "E9D": 5,
+         "E7A": 6, "E7B": 7, "E7C": 8, "E7D": 9}
+# the ninth-degree 37-velocity rule on |e|^2 <= 10 is also called E9A
+KINDS["E9A"] = KINDS["D2Q37"]
 MODELS = {"cm": 0, "raw_mrt": 1, "reg_bgk": 2}
 
 
@@ -115,7 +121,9 @@ def _p(a):
 
 
 def lattice(kind: str):
-    """Quadrature table: dict(D, Q, e (Q,3) int, w (Q,), r, resid)."""
+    """Quadrature table: dict(D, Q, e (Q,3) int, w (Q,), r, resid, N) with N
+    the Hermite truncation N = M the oracle uses on the lattice (0: the
+    complete tensor-product basis of D2Q9/D3Q27)."""
     D, Q = ctypes.c_int(), ctypes.c_int()
     e = np.zeros(37 * 3, np.int32)
     w = np.zeros(37)
@@ -127,7 +135,7 @@ def lattice(kind: str):
         raise RuntimeError("oracle lattice failed")
     q = Q.value
     return dict(D=D.value, Q=q, e=e[:3 * q].reshape(q, 3).astype(np.int64), w=w[:q].copy(),
-                r=r.value, resid=resid.value)
+                r=r.value, resid=resid.value, N={37: 4, 17: 3}.get(q, 0))
 
 
 def hermite(D: int, nmax: int, xi) -> list:

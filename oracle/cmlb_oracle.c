@@ -32,7 +32,11 @@
 #define ORC_MAXQ 37
 #define ORC_MAXN 6   /* highest tensor rank handled */
 
-enum { ORC_D2Q9 = 0, ORC_D3Q27 = 1, ORC_D2Q37 = 2 };
+/* Lattice kinds.  ORC_D2Q37 is the ninth-degree 37-velocity rule on the
+ * shells with |e|^2 <= 10 (called E9 A here); E9 B-D and E7 A-D are the other
+ * minimal on-lattice rules of Sec. III.A (Fig. 2), see make_hermite_rule. */
+enum { ORC_D2Q9 = 0, ORC_D3Q27 = 1, ORC_D2Q37 = 2, ORC_E9B = 3, ORC_E9C = 4, ORC_E9D = 5,
+       ORC_E7A = 6, ORC_E7B = 7, ORC_E7C = 8, ORC_E7D = 9, ORC_NKIND = 10 };
 enum { ORC_CM = 0, ORC_RAW_MRT = 1, ORC_REG_BGK = 2 };
 
 typedef struct {
@@ -40,11 +44,13 @@ typedef struct {
     int e[ORC_MAXQ][3];
     double w[ORC_MAXQ];
     double r;
+    int N;                      /* Hermite truncation N = M (0: complete tensor-product basis) */
+    double H[ORC_MAXQ][31];     /* H^(0..4)(xi_i) of a Hermite-truncated 2D lattice */
 } orc_lattice;
 
 /* Collision configuration (passed from Python as a flat struct). */
 typedef struct {
-    int lattice;       /* ORC_D2Q9 / ORC_D3Q27 / ORC_D2Q37 */
+    int lattice;       /* ORC_D2Q9 / ORC_D3Q27 / ORC_D2Q37 and the other 2D rules */
     int model;         /* ORC_CM (this paper), ORC_RAW_MRT (eq:regnmrt, right), ORC_REG_BGK (eq:lbgk-reg) */
     int thermal;       /* 1: theta is computed from f; 0: theta is frozen at theta0 (Sec. III.B) */
     int pad;
@@ -139,78 +145,119 @@ static int shell_images(int a, int b, int out[8][2])
     return n;
 }
 
-/* The 37-velocity ninth-degree 2D rule: shells (0,0),(1,0),(1,1),(2,0),(2,1),
- * (2,2),(3,0),(3,1) with all their images.  The eight shell weights and the
- * scale r solve the nine independent even-moment conditions of a degree-9
- * rule (odd moments vanish by symmetry): sum_i w_i xi_x^p xi_y^q = E[X^p]E[Y^q]
- * for (p,q) in the list below.  With x = 1/r^2 the conditions read
- * A w = b(x), b_k = E[X^p]E[Y^q] x^((p+q)/2); a solution exists where
- * det[A | b(x)] = 0.  The root is found by bisection and the weights by
- * solving eight of the equations; the ninth is the consistency check. */
-static int make_d2q37(orc_lattice *L, double *resid_out)
+/* On-lattice 2D rules from their velocity shells (Sec. II.A, eq:quad).  A
+ * rule of degree Q integrates every polynomial of degree <= Q against the
+ * Gaussian weight; with the symmetry of the shells (all sign changes and the
+ * axis exchange) the odd moments vanish and the conditions are
+ * sum_i w_i xi_x^p xi_y^q = E[X^p] E[Y^q] for even p >= q, p + q < Q.  The
+ * shell weights and the scale r solve them: with x = 1/r^2 they read
+ * A w = b(x), b_k = E[X^p]E[Y^q] x^((p+q)/2), which has a solution where
+ * det[A | b(x)] = 0.  The roots are located by a scan over x and bisection;
+ * the first root whose weights are all positive is taken.  The weights
+ * come from a square subsystem (the last condition dropped), and the
+ * dropped condition is the consistency check (resid_out).
+ *
+ * The rules of Sec. III.A (Fig. 2) are the minimal ones: 17 velocities for
+ * degree 7, 37 for degree 9.  A degree-7 rule has 6 conditions, so rest plus
+ * four 4-velocity shells; a degree-9 rule has 9, so rest plus five
+ * 4-velocity and two 8-velocity shells.  Among shells whose velocity
+ * components are at most 3, moment matching yields exactly four positive
+ * rules of each degree, matching the paper's count (their A-D letters are
+ * not recoverable from the text; the order here is by the shell lists):
+ *   E9 A = D2Q37: (1,0),(2,0),(3,0),(1,1),(2,2),(2,1),(3,1)   (|e|^2 <= 10)
+ *   E9 B:         (1,0),(2,0),(3,0),(1,1),(2,2),(2,1),(3,2)
+ *   E9 C:         (1,0),(2,0),(3,0),(1,1),(3,3),(2,1),(3,1)
+ *   E9 D:         (1,0),(2,0),(3,0),(1,1),(3,3),(2,1),(3,2)
+ *   E7 A:         (1,0),(3,0),(1,1),(2,2)
+ *   E7 B:         (1,0),(3,0),(1,1),(3,3)
+ *   E7 C:         (2,0),(3,0),(1,1),(3,3)
+ *   E7 D:         (3,0),(1,1),(2,2),(3,3)
+ * The degree-9 rules carry the order-4 truncation N = M = 4 of Sec. III; a
+ * degree-7 rule resolves eq:an exactly for orders up to 7 - N, so it
+ * carries N = M = 3. */
+static const int g_shells[ORC_NKIND][8][2] = {
+    [ORC_D2Q37] = {{0,0},{1,0},{2,0},{3,0},{1,1},{2,2},{2,1},{3,1}},
+    [ORC_E9B]   = {{0,0},{1,0},{2,0},{3,0},{1,1},{2,2},{2,1},{3,2}},
+    [ORC_E9C]   = {{0,0},{1,0},{2,0},{3,0},{1,1},{3,3},{2,1},{3,1}},
+    [ORC_E9D]   = {{0,0},{1,0},{2,0},{3,0},{1,1},{3,3},{2,1},{3,2}},
+    [ORC_E7A]   = {{0,0},{1,0},{3,0},{1,1},{2,2}},
+    [ORC_E7B]   = {{0,0},{1,0},{3,0},{1,1},{3,3}},
+    [ORC_E7C]   = {{0,0},{2,0},{3,0},{1,1},{3,3}},
+    [ORC_E7D]   = {{0,0},{3,0},{1,1},{2,2},{3,3}},
+};
+
+static int make_hermite_rule(int kind, orc_lattice *L, double *resid_out)
 {
-    static const int shells[8][2] = {{0,0},{1,0},{1,1},{2,0},{2,1},{2,2},{3,0},{3,1}};
-    /* (8,0) last: the other eight conditions form a well-conditioned square system */
-    static const int mons[9][2] = {{0,0},{2,0},{4,0},{2,2},{6,0},{4,2},{6,2},{4,4},{8,0}};
+    const int degree = (kind >= ORC_E7A) ? 7 : 9;
+    const int ns = (degree == 7) ? 5 : 8;
+    /* conditions (p, q), p >= q even, p + q < degree; the last is dropped from the square system */
+    static const int mons9[9][2] = {{0,0},{2,0},{4,0},{2,2},{6,0},{4,2},{6,2},{4,4},{8,0}};
+    static const int mons7[6][2] = {{0,0},{2,0},{4,0},{2,2},{4,2},{6,0}};
+    const int (*mons)[2] = (degree == 7) ? mons7 : mons9;
+    const int nm = ns + 1;
     int img[8][8][2], nimg[8];
     double A[9][8];
-    for (int s = 0; s < 8; ++s) nimg[s] = shell_images(shells[s][0], shells[s][1], img[s]);
-    for (int k = 0; k < 9; ++k)
-        for (int s = 0; s < 8; ++s) {
+    for (int k = 0; k < ns; ++k) nimg[k] = shell_images(g_shells[kind][k][0], g_shells[kind][k][1], img[k]);
+    for (int k = 0; k < nm; ++k)
+        for (int c = 0; c < ns; ++c) {
             double acc = 0.0;
-            for (int j = 0; j < nimg[s]; ++j)
-                acc += pow(img[s][j][0], mons[k][0]) * pow(img[s][j][1], mons[k][1]);
-            A[k][s] = acc;
+            for (int j = 0; j < nimg[c]; ++j)
+                acc += pow(img[c][j][0], mons[k][0]) * pow(img[c][j][1], mons[k][1]);
+            A[k][c] = acc;
         }
     double M[81];
 #define AUGDET(x, out) do {                                                   \
-        for (int k_ = 0; k_ < 9; ++k_) {                                      \
-            for (int s_ = 0; s_ < 8; ++s_) M[k_ * 9 + s_] = A[k_][s_];        \
-            M[k_ * 9 + 8] = gauss_moment(mons[k_][0]) * gauss_moment(mons[k_][1]) \
+        for (int k_ = 0; k_ < nm; ++k_) {                                     \
+            for (int s_ = 0; s_ < ns; ++s_) M[k_ * nm + s_] = A[k_][s_];      \
+            M[k_ * nm + ns] = gauss_moment(mons[k_][0]) * gauss_moment(mons[k_][1]) \
                           * pow((x), (mons[k_][0] + mons[k_][1]) / 2);        \
         }                                                                     \
-        (out) = determinant(9, M);                                            \
+        (out) = determinant(nm, M);                                           \
     } while (0)
-    /* scan for the sign change, then bisect */
-    double lo = 0.0, hi = 0.0, flo = 0.0, prev_x = 0.3, prev_f;
-    AUGDET(prev_x, prev_f);
+    double wv[8], x = 0.0;
     int found = 0;
-    for (int k = 1; k <= 1200 && !found; ++k) {
-        double x = 0.3 + k * 0.001, fx;
-        AUGDET(x, fx);
-        if ((fx < 0) != (prev_f < 0)) { lo = prev_x; hi = x; flo = prev_f; found = 1; }
-        prev_x = x; prev_f = fx;
-    }
-    if (!found) return -1;
-    for (int it = 0; it < 200; ++it) {
-        double mid = 0.5 * (lo + hi), fm;
-        AUGDET(mid, fm);
-        if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
+    double prev_x = 0.05, prev_f;
+    AUGDET(prev_x, prev_f);
+    for (int k = 1; k <= 4000 && !found; ++k) {
+        double xs = 0.05 + k * 0.001, fx;
+        AUGDET(xs, fx);
+        if ((fx < 0) != (prev_f < 0)) {
+            double lo = prev_x, hi = xs, flo = prev_f;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi), fm;
+                AUGDET(mid, fm);
+                if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
+            }
+            x = 0.5 * (lo + hi);
+            double S[64];
+            for (int r_ = 0; r_ < ns; ++r_) {
+                for (int c = 0; c < ns; ++c) S[r_ * ns + c] = A[r_][c];
+                wv[r_] = gauss_moment(mons[r_][0]) * gauss_moment(mons[r_][1]) * pow(x, (mons[r_][0] + mons[r_][1]) / 2);
+            }
+            int pos = !solve_dense(ns, S, wv);
+            for (int c = 0; c < ns && pos; ++c) pos = wv[c] > 0.0;
+            found = pos;
+        }
+        prev_x = xs; prev_f = fx;
     }
 #undef AUGDET
-    double x = 0.5 * (lo + hi);
-    double S[64], wv[8];
-    for (int k = 0; k < 8; ++k) {
-        for (int s = 0; s < 8; ++s) S[k * 8 + s] = A[k][s];
-        wv[k] = gauss_moment(mons[k][0]) * gauss_moment(mons[k][1]) * pow(x, (mons[k][0] + mons[k][1]) / 2);
-    }
-    if (solve_dense(8, S, wv)) return -1;
-    double r9 = -gauss_moment(mons[8][0]) * gauss_moment(mons[8][1]) * pow(x, 4);
-    for (int s = 0; s < 8; ++s) r9 += A[8][s] * wv[s];
-    if (resid_out) *resid_out = r9;
+    if (!found) return -1;
+    double rlast = -gauss_moment(mons[ns][0]) * gauss_moment(mons[ns][1]) * pow(x, (mons[ns][0] + mons[ns][1]) / 2);
+    for (int c = 0; c < ns; ++c) rlast += A[ns][c] * wv[c];
+    if (resid_out) *resid_out = rlast;
     /* populations ordered by (e_y, e_x) lexicographically */
-    L->D = 2; L->Q = 37; L->r = 1.0 / sqrt(x);
+    L->D = 2; L->Q = (degree == 7) ? 17 : 37; L->r = 1.0 / sqrt(x); L->N = (degree == 7) ? 3 : 4;
     int q = 0;
     for (int ey = -3; ey <= 3; ++ey)
         for (int ex = -3; ex <= 3; ++ex)
-            for (int s = 0; s < 8; ++s)
-                for (int j = 0; j < nimg[s]; ++j)
-                    if (img[s][j][0] == ex && img[s][j][1] == ey) {
+            for (int c = 0; c < ns; ++c)
+                for (int j = 0; j < nimg[c]; ++j)
+                    if (img[c][j][0] == ex && img[c][j][1] == ey) {
                         L->e[q][0] = ex; L->e[q][1] = ey; L->e[q][2] = 0;
-                        L->w[q] = wv[s];
+                        L->w[q] = wv[c];
                         ++q;
                     }
-    return q == 37 ? 0 : -1;
+    return q == L->Q ? 0 : -1;
 }
 
 /* D2Q9 and D3Q27: the tensor products of the three-point Gauss-Hermite rule
@@ -225,26 +272,27 @@ static void make_tensor_lattice(int D, orc_lattice *L)
         L->e[i][0] = ix - 1; L->e[i][1] = iy - 1; L->e[i][2] = (D == 3) ? iz - 1 : 0;
         L->w[i] = w1[ix] * w1[iy] * (D == 3 ? w1[iz] : 1.0);
     }
+    L->N = 0;
 }
 
 static int get_lattice(int kind, orc_lattice *L)
 {
     if (kind == ORC_D2Q9) { make_tensor_lattice(2, L); return 0; }
     if (kind == ORC_D3Q27) { make_tensor_lattice(3, L); return 0; }
-    if (kind == ORC_D2Q37) return make_d2q37(L, NULL);
+    if (kind >= ORC_D2Q37 && kind < ORC_NKIND) return make_hermite_rule(kind, L, NULL);
     return -1;
 }
 
 /* Lattice tables are built once per kind. */
-static orc_lattice g_lat[3];
-static int g_lat_ok[3];
+static orc_lattice g_lat[ORC_NKIND];
+static int g_lat_ok[ORC_NKIND];
 
-static void build_tables(const orc_lattice *L, int kind);
+static void build_tables(orc_lattice *L, int kind);
 
 /* Lattice and its Hermite tables; built on first use, before any parallel region. */
 static const orc_lattice *lattice(int kind)
 {
-    if (kind < 0 || kind > 2) return NULL;
+    if (kind < 0 || kind >= ORC_NKIND) return NULL;
     if (!g_lat_ok[kind]) {
         orc_lattice L;
         if (get_lattice(kind, &L)) return NULL;
@@ -266,7 +314,7 @@ int orc_lattice_info(int kind, int *D, int *Q, int *e, double *w, double *r, dou
     }
     if (resid) {
         *resid = 0.0;
-        if (kind == ORC_D2Q37) { orc_lattice T; make_d2q37(&T, resid); }
+        if (kind >= ORC_D2Q37) { orc_lattice T; make_hermite_rule(kind, &T, resid); }
     }
     return 0;
 }
@@ -571,19 +619,17 @@ static void tp_maxwell(int D, double rho, const double *u_xi, double theta, doub
 /* Discrete equilibrium f0_i, eq:fi applied to the Maxwellian coefficients:
  *   D2Q9/D3Q27: complete tensor-product basis (every resolved central moment
  *               is the Maxwellian's);
- *   D2Q37:      Hermite truncation at order M = 4 (Sec. II.B). */
-static void h37_init(const orc_lattice *L);
-static double g_H37[ORC_MAXQ][31];
-
+ *   2D rules:   Hermite truncation at order M = N of the lattice (4 on the
+ *               37-velocity rules, 3 on the 17-velocity rules; Sec. II.B). */
 static void equilibrium(const orc_lattice *L, int kind, double rho, const double *u_xi, double theta, double *f0)
 {
-    if (kind == ORC_D2Q37) {
-        const int D = 2, M = 4;
+    (void)kind;
+    if (L->N > 0) {
+        const int D = 2, M = L->N;
         double a[1 + 2 + 4 + 8 + 16];
-        h37_init(L);
         maxwell_coeffs(D, M, rho, u_xi, theta, a);
         for (int i = 0; i < L->Q; ++i) {
-            const double *H = g_H37[i];  /* H^(0..4)(xi_i) */
+            const double *H = L->H[i];  /* H^(0..4)(xi_i) */
             double s = 0.0;
             for (int n = 0; n <= M; ++n) s += t_contract(D, n, a + t_offset(D, n), H + t_offset(D, n)) / factorial(n);
             f0[i] = L->w[i] * s;
@@ -691,43 +737,40 @@ static int collide_tp_definitional(const orc_lattice *L, const orc_cfg *cfg, con
 /* Collision, D2Q37 (N = M = 4, Sec. II.C)                                   */
 /* ------------------------------------------------------------------------- */
 
-/* Hermite tensors of the 37 abscissas, built once. */
-static int g_H37_ok;
-
-static void h37_init(const orc_lattice *L)
+/* Hermite tensors H^(0..4) of the abscissas of a 2D rule. */
+static void hermite_init(orc_lattice *L)
 {
-    if (g_H37_ok) return;
     for (int i = 0; i < L->Q; ++i) {
         double xi[2] = {L->r * L->e[i][0], L->r * L->e[i][1]};
-        hermite_tensors(2, 4, xi, g_H37[i]);
+        hermite_tensors(2, 4, xi, L->H[i]);
     }
-    g_H37_ok = 1;
 }
 
-/* The paper's procedure for the truncated basis:
+/* The paper's procedure for the truncated basis (N = M = L->N):
  *  1. rho, u, theta (theta frozen at theta0 when isothermal);
- *  2. f0 = the order-4 Hermite equilibrium;
- *  3. a1^(n) = sum_i (f_i - f0_i) H^(n)(xi_i), n = 2, 3, 4 (eq:an);
- *  4. a_Omega^(n) from eq:mrt, with the delta term of the fourth order
- *     carrying cfg->delta_coef (6 satisfies eq:omega; the paper prints 72);
- *     raw MRT uses -omega_n a1^(n), regularised BGK -omega a1^(n) (eq:regnmrt);
- *  5. f*_i = f^_i + Omega_i, where f^ is the order-4 projection of eq:reg and
+ *  2. f0 = the order-N Hermite equilibrium;
+ *  3. a1^(n) = sum_i (f_i - f0_i) H^(n)(xi_i), n = 2 .. N (eq:an);
+ *  4. a_Omega^(n) from eq:mrt (its terms up to order N), with the delta
+ *     term of the fourth order carrying cfg->delta_coef (6 satisfies
+ *     eq:omega; the paper prints 72); raw MRT uses -omega_n a1^(n),
+ *     regularised BGK -omega a1^(n) (eq:regnmrt);
+ *  5. f*_i = f^_i + Omega_i, where f^ is the order-N projection of eq:reg and
  *     Omega_i = w_i sum_n a_Omega^(n):H^(n)(xi_i)/n! (eq:fi). */
-static void collide_d2q37(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+static void collide_hermite(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
 {
-    const int D = 2, N = 4;
-    h37_init(L);
+    const int D = 2, N = L->N;
     double rho, u[3], th;
     node_moments(L, f, &rho, u, &th);
     if (!cfg->thermal) th = cfg->theta0;
     double f0[ORC_MAXQ], af[31], a1[31], aO[31];
-    equilibrium(L, ORC_D2Q37, rho, u, th, f0);
+    equilibrium(L, cfg->lattice, rho, u, th, f0);
     memset(af, 0, sizeof(af));
     memset(a1, 0, sizeof(a1));
+    const int nk = t_offset(D, N + 1);
     for (int i = 0; i < L->Q; ++i)
-        for (int k = 0; k < 31; ++k) {
-            af[k] += f[i] * g_H37[i][k];
-            a1[k] += (f[i] - f0[i]) * g_H37[i][k];
+        for (int k = 0; k < nk; ++k) {
+            af[k] += f[i] * L->H[i][k];
+            a1[k] += (f[i] - f0[i]) * L->H[i][k];
         }
     memset(aO, 0, sizeof(aO));
     const double *A2 = a1 + t_offset(D, 2), *A3 = a1 + t_offset(D, 3), *A4 = a1 + t_offset(D, 4);
@@ -743,9 +786,10 @@ static void collide_d2q37(const orc_lattice *L, const orc_cfg *cfg, const double
         t_symprod(D, 2, delta, 2, A2, da2);
         for (int k = 0; k < 4; ++k) O2[k] = -w2 * A2[k];                                   /* eq:mrt-a */
         for (int k = 0; k < 8; ++k) O3[k] = -w3 * A3[k] + 3.0 * (w3 - w2) * ua2[k];         /* eq:mrt-b */
-        for (int k = 0; k < 16; ++k)
-            O4[k] = -w4 * A4[k] + 4.0 * (w4 - w3) * ua3[k]
-                  - 6.0 * (w4 + w2 - 2.0 * w3) * uua2[k] - cfg->delta_coef * (w4 - w2) * da2[k];
+        if (N >= 4)
+            for (int k = 0; k < 16; ++k)
+                O4[k] = -w4 * A4[k] + 4.0 * (w4 - w3) * ua3[k]
+                      - 6.0 * (w4 + w2 - 2.0 * w3) * uua2[k] - cfg->delta_coef * (w4 - w2) * da2[k];
     } else {
         for (int n = 2; n <= N; ++n) {
             double om = (cfg->model == ORC_REG_BGK) ? cfg->omega[2] : cfg->omega[n];
@@ -756,29 +800,30 @@ static void collide_d2q37(const orc_lattice *L, const orc_cfg *cfg, const double
         double s = 0.0;
         for (int n = 0; n <= N; ++n) {
             int o = t_offset(D, n);
-            s += t_contract(D, n, af + o, g_H37[i] + o) / factorial(n);
-            s += t_contract(D, n, aO + o, g_H37[i] + o) / factorial(n);
+            s += t_contract(D, n, af + o, L->H[i] + o) / factorial(n);
+            s += t_contract(D, n, aO + o, L->H[i] + o) / factorial(n);
         }
         out[i] = L->w[i] * s;
     }
 }
 
-/* Definitional form for D2Q37: f* lies in the span of w_i H_m(xi_i) (the 15
- * components of order <= 4) and its central monomial moments of order <= 4
- * are sum_i f*_i c_i^p = (1 - omega_{|p|}) sum_i f_i c_i^p + omega_{|p|} rho mu_px mu_py,
+/* Definitional form for the 2D rules: f* lies in the span of w_i H_m(xi_i)
+ * (the (N+1)(N+2)/2 components of order <= N: 15 for N = 4, 10 for N = 3)
+ * and its central monomial moments of order <= N are
+ * sum_i f*_i c_i^p = (1 - omega_{|p|}) sum_i f_i c_i^p + omega_{|p|} rho mu_px mu_py,
  * with mu the Gaussian central moments (1, 0, theta, 0, 3 theta^2) (eq:omega
- * for every resolved order).  Solved as a 15 x 15 system. */
-static int collide_d2q37_definitional(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
+ * for every resolved order).  Solved as a square system. */
+static int collide_hermite_definitional(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
 {
     double rho, u[3], th;
     node_moments(L, f, &rho, u, &th);
     if (!cfg->thermal) th = cfg->theta0;
     int basis[15][2], nb = 0;
-    for (int n = 0; n <= 4; ++n)
+    for (int n = 0; n <= L->N; ++n)
         for (int k = 0; k <= n; ++k) { basis[nb][0] = k; basis[nb][1] = n - k; ++nb; }
     double mu[5] = {1.0, 0.0, th, 0.0, 3.0 * th * th};
     double A[225], rhs[15];
-    for (int row = 0; row < 15; ++row) {
+    for (int row = 0; row < nb; ++row) {
         int px = basis[row][0], py = basis[row][1], ord = px + py;
         double kap = 0.0;
         for (int i = 0; i < L->Q; ++i) {
@@ -787,34 +832,35 @@ static int collide_d2q37_definitional(const orc_lattice *L, const orc_cfg *cfg, 
         }
         double om = (ord < 2) ? 0.0 : ((cfg->model == ORC_REG_BGK) ? cfg->omega[2] : cfg->omega[ord]);
         rhs[row] = (1.0 - om) * kap + om * rho * mu[px] * mu[py];
-        for (int col = 0; col < 15; ++col) {
+        for (int col = 0; col < nb; ++col) {
             double s = 0.0;
             for (int i = 0; i < L->Q; ++i) {
                 double xx = L->r * L->e[i][0], yy = L->r * L->e[i][1];
                 double phi = L->w[i] * he1d(basis[col][0], xx) * he1d(basis[col][1], yy);
                 s += phi * pow(xx - u[0], px) * pow(yy - u[1], py);
             }
-            A[row * 15 + col] = s;
+            A[row * nb + col] = s;
         }
     }
-    if (solve_dense(15, A, rhs)) return -1;
+    if (solve_dense(nb, A, rhs)) return -1;
     for (int i = 0; i < L->Q; ++i) {
         double xx = L->r * L->e[i][0], yy = L->r * L->e[i][1], s = 0.0;
-        for (int col = 0; col < 15; ++col) s += rhs[col] * L->w[i] * he1d(basis[col][0], xx) * he1d(basis[col][1], yy);
+        for (int col = 0; col < nb; ++col) s += rhs[col] * L->w[i] * he1d(basis[col][0], xx) * he1d(basis[col][1], yy);
         out[i] = s;
     }
     return 0;
 }
 
-static void build_tables(const orc_lattice *L, int kind)
+static void build_tables(orc_lattice *L, int kind)
 {
-    if (kind == ORC_D2Q37) h37_init(L);
+    if (L->N > 0) hermite_init(L);
     else (void)tp_table(L);
+    (void)kind;
 }
 
 static int collide_node(const orc_lattice *L, const orc_cfg *cfg, const double *f, double *out)
 {
-    if (cfg->lattice == ORC_D2Q37) collide_d2q37(L, cfg, f, out);
+    if (L->N > 0) collide_hermite(L, cfg, f, out);
     else collide_tp(L, cfg, f, out);
     return 0;
 }
@@ -823,7 +869,6 @@ int orc_collide(const orc_cfg *cfg, int n_nodes, const double *f, double *out)
 {
     const orc_lattice *L = lattice(cfg->lattice);
     if (!L) return -1;
-    if (cfg->lattice == ORC_D2Q37) h37_init(L);
     for (int k = 0; k < n_nodes; ++k) collide_node(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q);
     return 0;
 }
@@ -833,8 +878,8 @@ int orc_collide_definitional(const orc_cfg *cfg, int n_nodes, const double *f, d
     const orc_lattice *L = lattice(cfg->lattice);
     if (!L) return -1;
     for (int k = 0; k < n_nodes; ++k) {
-        int rc = (cfg->lattice == ORC_D2Q37)
-            ? collide_d2q37_definitional(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q)
+        int rc = (L->N > 0)
+            ? collide_hermite_definitional(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q)
             : collide_tp_definitional(L, cfg, f + (size_t)k * L->Q, out + (size_t)k * L->Q);
         if (rc) return rc;
     }
@@ -864,7 +909,6 @@ int orc_run(const orc_cfg *cfg, long nx, long ny, long nz, double *S, long nstep
     const orc_lattice *L = lattice(cfg->lattice);
     if (!L || nx < 1 || ny < 1 || nz < 1) return -1;
     if (L->D == 2 && nz != 1) return -1;
-    if (cfg->lattice == ORC_D2Q37) h37_init(L);
     size_t plane = (size_t)nx * ny * nz;
     double *T = (double *)malloc(sizeof(double) * plane * L->Q);
     if (!T) return -2;
@@ -892,7 +936,6 @@ int orc_step_nodes(const orc_cfg *cfg, long nx, long ny, long nz, const double *
 {
     const orc_lattice *L = lattice(cfg->lattice);
     if (!L) return -1;
-    if (cfg->lattice == ORC_D2Q37) h37_init(L);
     #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (long k = 0; k < n_nodes; ++k) {
         long idx = (long)nodes[k];

@@ -33,7 +33,21 @@ def gauss_mom(p):
 # --------------------------------------------------------------------------
 # Lattices (eq:quad)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("kind,degree", [("D2Q9", 5), ("D3Q27", 5), ("D2Q37", 9)])
+RULES_2D = ["D2Q37", "E9B", "E9C", "E9D", "E7A", "E7B", "E7C", "E7D"]
+SHELLS = {   # velocity shells of each minimal 2D rule (components at most 3)
+    "D2Q37": [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2)],
+    "E9B": [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (2, 2), (2, 3)],
+    "E9C": [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (3, 3)],
+    "E9D": [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (2, 3), (3, 3)],
+    "E7A": [(0, 0), (0, 1), (0, 3), (1, 1), (2, 2)],
+    "E7B": [(0, 0), (0, 1), (0, 3), (1, 1), (3, 3)],
+    "E7C": [(0, 0), (0, 2), (0, 3), (1, 1), (3, 3)],
+    "E7D": [(0, 0), (0, 3), (1, 1), (2, 2), (3, 3)],
+}
+
+
+@pytest.mark.parametrize("kind,degree", [("D2Q9", 5), ("D3Q27", 5)] + [(k, 9) for k in RULES_2D[:4]]
+                         + [(k, 7) for k in RULES_2D[4:]])
 def test_quadrature_exact_to_degree(orc, kind, degree):
     L = orc.lattice(kind)
     D, xi, w = L["D"], L["r"] * L["e"][:, :L["D"]], L["w"]
@@ -50,12 +64,14 @@ def test_quadrature_exact_to_degree(orc, kind, degree):
     assert abs(np.sum(w * xi[:, 0] ** (degree + 1)) - gauss_mom(degree + 1)) > 1e-3
 
 
-def test_lattice_structure(orc):
-    L = orc.lattice("D2Q37")
+@pytest.mark.parametrize("kind", RULES_2D)
+def test_lattice_structure(orc, kind):
+    L = orc.lattice(kind)
     e = L["e"]
-    assert L["Q"] == 37 and np.all(L["w"] > 0)
+    assert L["Q"] == (37 if kind in RULES_2D[:4] else 17) and np.all(L["w"] > 0)
+    assert L["N"] == (4 if L["Q"] == 37 else 3)
     shells = sorted({tuple(sorted(np.abs(v[:2]))) for v in e})
-    assert shells == [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2)]
+    assert shells == SHELLS[kind]
     # the rule is symmetric: every image of a velocity carries the same weight
     lookup = {tuple(v[:2]): w for v, w in zip(e, L["w"])}
     for (x, y), w in lookup.items():
@@ -63,6 +79,47 @@ def test_lattice_structure(orc):
             assert lookup[img] == pytest.approx(w, rel=1e-14)
     assert sum(L["w"]) == pytest.approx(1.0, abs=1e-14)
     assert abs(L["resid"]) < 1e-12
+    # populations in (e_y, e_x) lexicographic order: -e_i is population Q-1-i
+    q = L["Q"]
+    assert np.array_equal(e[::-1], -e)
+
+
+def _images(a, b):
+    return sorted({(sx * x, sy * y) for x, y in ((a, b), (b, a)) for sx in (1, -1) for sy in (1, -1)})
+
+
+@pytest.mark.parametrize("kind", RULES_2D)
+def test_rule_scale_is_a_root_of_the_moment_conditions(orc, kind):
+    """Independent re-derivation of r: with x = 1/r^2 the moment conditions
+    A w = b(x) are consistent only where det[A | b(x)] = 0, a polynomial in
+    x.  numpy fits it exactly from a few samples, its roots are computed,
+    and the one whose least-squares weights are all positive and satisfy
+    every condition is the oracle's 1/r^2.  For the 17-velocity rules the
+    four roots chosen are also checked to be the only positive rules."""
+    L = orc.lattice(kind)
+    shells = SHELLS[kind]
+    deg = 9 if L["Q"] == 37 else 7
+    mons = [(p, q) for p in range(0, deg, 2) for q in range(0, p + 1, 2) if p + q < deg]
+    A = np.array([[sum(x ** p * y ** q for x, y in _images(*sh)) for sh in shells] for p, q in mons], float)
+    b = lambda x: np.array([gauss_mom(p) * gauss_mom(q) * x ** ((p + q) // 2) for p, q in mons])
+    order = max((p + q) // 2 for p, q in mons)
+    xs = np.linspace(0.1, 2.5, order + 3)
+    vals = [np.linalg.det(np.column_stack([A, b(x)])) for x in xs]
+    coef = np.polyfit(xs, vals, order)
+    good = []
+    for x in np.roots(coef):
+        if abs(x.imag) > 1e-9 or x.real <= 0:
+            continue
+        x = x.real
+        wsh, *_ = np.linalg.lstsq(A, b(x), rcond=None)
+        if np.abs(A @ wsh - b(x)).max() < 1e-8 and (wsh > 0).all():
+            good.append((x, wsh))
+    assert len(good) == 1
+    x, wsh = good[0]
+    assert 1.0 / math.sqrt(x) == pytest.approx(L["r"], rel=1e-9)
+    lookup = {tuple(v[:2]): w for v, w in zip(L["e"], L["w"])}
+    for sh, w in zip(shells, wsh):
+        assert lookup[sh] == pytest.approx(w, rel=1e-8)
 
 
 def test_d2q37_scale_pinned_by_fig1(orc):
@@ -217,21 +274,28 @@ def test_equilibrium_d3q27_product_form(orc):
         assert np.allclose(f0, ref, atol=1e-15)
 
 
-def test_equilibrium_d2q37_moments(orc):
-    """The order-4 equilibrium reproduces the Maxwellian's Hermite coefficients
-    up to order 4 (eq:an on the degree-9 rule) and its raw moments to order 4."""
+@pytest.mark.parametrize("kind", RULES_2D)
+def test_equilibrium_hermite_rules_moments(orc, kind):
+    """The order-N equilibrium reproduces the Maxwellian's Hermite
+    coefficients up to order N (eq:an on the rule) and has no component
+    beyond: order N + 1 vanishes (N = 4 on 37 velocities, 3 on 17)."""
     rng = np.random.default_rng(7)
-    L = orc.lattice("D2Q37")
+    L = orc.lattice(kind)
+    N = L["N"]
     xi = L["r"] * L["e"][:, :2]
     for _ in range(3):
         rho, u_lat, th = 1 + 0.1 * rng.normal(), 0.05 * rng.normal(size=2), 1 + 0.1 * rng.normal()
-        f0 = orc.equilibrium("D2Q37", rho, u_lat, th)
+        f0 = orc.equilibrium(kind, rho, u_lat, th)
         u = L["r"] * u_lat
-        for px in range(5):
-            for py in range(5 - px):
+        for px in range(N + 1):
+            for py in range(N + 1 - px):
                 lhs = np.sum(f0 * he(px, xi[:, 0]) * he(py, xi[:, 1]))
                 ref = _maxwell_coeff_quadrature(rho, u, th, [px, py])
                 assert lhs == pytest.approx(ref, rel=1e-11, abs=1e-13)
+        if N == 3:   # exact where the rule's degree allows (3 + 4 = 7)
+            for px in range(5):
+                lhs = np.sum(f0 * he(px, xi[:, 0]) * he(4 - px, xi[:, 1]))
+                assert abs(lhs) < 1e-12
 
 
 # --------------------------------------------------------------------------
@@ -265,7 +329,8 @@ def _orders(D, cmax, nmax):
     return [p for p in itertools.product(range(cmax + 1), repeat=D) if sum(p) <= nmax]
 
 
-@pytest.mark.parametrize("kind,thermal", [("D2Q9", False), ("D3Q27", False), ("D2Q37", True), ("D2Q37", False)])
+@pytest.mark.parametrize("kind,thermal", [("D2Q9", False), ("D3Q27", False), ("D2Q37", True), ("D2Q37", False)]
+                         + [(k, True) for k in RULES_2D[1:]] + [("E7A", False)])
 def test_collide_paper_route_equals_definition(orc, kind, thermal):
     f = _random_states(orc, kind, 6, 10, thermal)
     for seed in range(3):
@@ -275,7 +340,8 @@ def test_collide_paper_route_equals_definition(orc, kind, thermal):
         assert np.abs(a - b).max() < 2e-14
 
 
-@pytest.mark.parametrize("kind,thermal", [("D2Q9", False), ("D3Q27", False), ("D2Q37", True)])
+@pytest.mark.parametrize("kind,thermal", [("D2Q9", False), ("D3Q27", False), ("D2Q37", True), ("E7A", True),
+                                         ("E7D", True), ("E9C", True)])
 def test_eq_omega_invariant(orc, kind, thermal):
     """sum_i Omega_i c^p = -omega_{|p|} sum_i f1_i c^p for every resolved central moment."""
     L = orc.lattice(kind)
@@ -283,7 +349,7 @@ def test_eq_omega_invariant(orc, kind, thermal):
     f = _random_states(orc, kind, 4, 11, thermal)
     cfg = _cfg(orc, kind, thermal, 3)
     fs = orc.collide(cfg, f)
-    orders = _orders(D, 2, 6) if kind != "D2Q37" else _orders(D, 4, 4)
+    orders = _orders(D, 2, 6) if L["N"] == 0 else _orders(D, L["N"], L["N"])
     om = cfg.omega()
     for k in range(len(f)):
         rho, u, th = orc.moments(kind, f[k][:, None])
@@ -322,7 +388,7 @@ def test_printed_72_breaks_eq_omega(orc):
     assert np.abs(orc.collide(same, f) - orc.collide(same72, f)).max() < 1e-15
 
 
-@pytest.mark.parametrize("kind,thermal", [("D2Q9", False), ("D3Q27", False), ("D2Q37", True)])
+@pytest.mark.parametrize("kind,thermal", [("D2Q9", False), ("D3Q27", False)] + [(k, True) for k in RULES_2D])
 def test_conservation(orc, kind, thermal):
     L = orc.lattice(kind)
     f = _random_states(orc, kind, 5, 13, thermal)
@@ -350,14 +416,14 @@ def _projection(orc, L, N):
 def test_single_rate_limits(orc):
     """All rates equal: CM-MRT = LBGK (eq:lbgk) on the complete basis and the
     regularised BGK (eq:lbgk-reg) on D2Q37 (Sec. II.C, remark after eq:regnmrt)."""
-    for kind, thermal in [("D3Q27", False), ("D2Q9", False), ("D2Q37", True)]:
+    for kind, thermal in [("D3Q27", False), ("D2Q9", False), ("D2Q37", True), ("E7A", True), ("E7C", True)]:
         L = orc.lattice(kind)
         f = _random_states(orc, kind, 4, 14, thermal)
         for w in (0.0, 0.7, 1.0, 1.6):
             tau = {n: 1.0 / w if w else 1e300 for n in range(2, 8)}
             cfg = orc.Cfg(lattice=kind, tau=tau, thermal=thermal)
             fs = orc.collide(cfg, f)
-            P = _projection(orc, L, 4) if kind == "D2Q37" else np.eye(L["Q"])
+            P = _projection(orc, L, L["N"]) if L["N"] else np.eye(L["Q"])
             for k in range(len(f)):
                 rho, u, th = orc.moments(kind, f[k][:, None])
                 f0 = orc.equilibrium(kind, rho[0], u[:, 0], th[0] if thermal else 1.0)
