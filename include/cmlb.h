@@ -16,9 +16,10 @@
  *      CMLB_D2Q9   e in {-1,0,1}^2, r = sqrt(3), complete tensor-product basis;
  *      CMLB_D3Q27  e in {-1,0,1}^3, r = sqrt(3), complete tensor-product basis;
  *      CMLB_D2Q37  e in Z^2 with |e|^2 <= 10, ninth-degree rule (r ~ 1.19698),
- *                  order-4 Hermite truncation N = M = 4 (Sec. II.B).
- *    Population order: D2Q9/D3Q27 i = (ex+1) + 3(ey+1) + 9(ez+1); D2Q37
- *    lexicographic in (ey, ex), both from -3 to 3.
+ *                  order-4 Hermite truncation N = M = 4 (Sec. II.B);
+ *      the other 2D Hermite rules of Fig. 2 (see the lattice enum).
+ *    Population order: D2Q9/D3Q27 i = (ex+1) + 3(ey+1) + 9(ez+1); the 2D
+ *    Hermite rules lexicographic in (ey, ex), both from -3 to 3.
  *  - Host arrays of fields and populations are FP64, structure of arrays,
  *    x fastest: fields [component][z][y][x], populations [i][z][y][x].
  *    Velocities are in lattice units (cells per step); theta is the paper's
@@ -50,7 +51,26 @@ extern "C" {
 #define CMLB_ESTATE (-4)    /* call not valid in the current state */
 #define CMLB_EUNSTABLE (-5) /* non-finite populations found (divergence) */
 
-enum { CMLB_D2Q9 = 0, CMLB_D3Q27 = 1, CMLB_D2Q37 = 2 };
+/* Lattices.  The 2D Hermite rules (eq:quad, Sec. III.A and Fig. 2) are the
+ * minimal on-lattice rules whose velocity components are at most 3: four of
+ * degree 9 on 37 velocities, carrying the order-4 truncation N = M = 4
+ * (CMLB_D2Q37 is the one on the shells with |e|^2 <= 10, also called E9 A),
+ * and four of degree 7 on 17 velocities, carrying N = M = 3 (a degree-7 rule
+ * resolves the Hermite coefficients of eq:an exactly only up to order
+ * 7 - N).  Their shells, as |e| component pairs beside the rest velocity:
+ *   CMLB_D2Q37 (E9 A)  (0,1) (1,1) (0,2) (1,2) (2,2) (0,3) (1,3)
+ *   CMLB_E9B           (0,1) (1,1) (0,2) (1,2) (2,2) (0,3) (2,3)
+ *   CMLB_E9C           (0,1) (1,1) (0,2) (1,2) (3,3) (0,3) (1,3)
+ *   CMLB_E9D           (0,1) (1,1) (0,2) (1,2) (3,3) (0,3) (2,3)
+ *   CMLB_E7A           (0,1) (1,1) (2,2) (0,3)
+ *   CMLB_E7B           (0,1) (1,1) (3,3) (0,3)
+ *   CMLB_E7C           (0,2) (1,1) (3,3) (0,3)
+ *   CMLB_E7D           (1,1) (2,2) (3,3) (0,3)
+ * The letters order the rules by their shells; the paper does not print its
+ * tables.  The rules other than D2Q37 take FP64 or FP32 storage, the
+ * central-moment or the regularised BGK model, and one step per launch. */
+enum { CMLB_D2Q9 = 0, CMLB_D3Q27 = 1, CMLB_D2Q37 = 2, CMLB_E9B = 3, CMLB_E9C = 4, CMLB_E9D = 5,
+       CMLB_E7A = 6, CMLB_E7B = 7, CMLB_E7C = 8, CMLB_E7D = 9 };
 
 /* Storage of the population field.  Every type stores the deviation
  * g_i = s_i (f_i - w_i rho0); arithmetic is FP64 for CMLB_F64 and FP32 for
@@ -63,18 +83,19 @@ enum { CMLB_F64 = 0, CMLB_F32 = 1, CMLB_BF16 = 2, CMLB_F16 = 3 };
  * (eq:omega, eq:mrt).  The two others are the comparison operators of
  * eq:regnmrt: raw-moment MRT relaxes absolute-frame Hermite coefficients at
  * per-order rates, regularised BGK (eq:lbgk-reg) relaxes every order at
- * omega_2.  Raw MRT and regularised BGK are available on CMLB_D2Q37. */
+ * omega_2.  Raw MRT is available on CMLB_D2Q37, regularised BGK on every 2D
+ * Hermite rule. */
 enum { CMLB_MODEL_CM = 0, CMLB_MODEL_RAW_MRT = 1, CMLB_MODEL_REG_BGK = 2 };
 
 typedef struct cmlb_params {
-    int32_t lattice;   /* CMLB_D2Q9, CMLB_D3Q27, CMLB_D2Q37 */
+    int32_t lattice;   /* CMLB_D2Q9, CMLB_D3Q27, CMLB_D2Q37, CMLB_E9B..CMLB_E7D */
     int32_t storage;   /* CMLB_F64, CMLB_F32, CMLB_BF16, CMLB_F16 */
     int32_t model;     /* CMLB_MODEL_* */
-    int32_t thermal;   /* 1: theta follows from f (D2Q37 only); 0: theta frozen at theta0 */
+    int32_t thermal;   /* 1: theta follows from f (2D Hermite rules only); 0: theta frozen at theta0 */
     int64_t nx, ny, nz;/* periodic grid, each 1..2^20; nz must be 1 for 2D
-                          lattices; D2Q37 needs nx, ny >= 3 (its velocities
-                          reach 3 cells); nx*ny*nz < 2^32 and
-                          Q*nx*ny*nz < 2^35 */
+                          lattices; the 2D Hermite rules need nx, ny >= 3
+                          (their velocities reach 3 cells); nx*ny*nz < 2^32
+                          and Q*nx*ny*nz < 2^35 */
     double rho0;       /* reference density of the deviation storage (>0, finite) */
     double theta0;     /* frozen temperature of isothermal runs (>0, finite) */
     double tau[8];     /* tau[n]: relaxation time of central-moment order n

@@ -15,7 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcmlb.so")
 
-LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q37": 2}
+LATTICES = {"D2Q9": 0, "D3Q27": 1, "D2Q37": 2, "E9B": 3, "E9C": 4, "E9D": 5, "E7A": 6, "E7B": 7, "E7C": 8,
+            "E7D": 9}
+LATTICES["E9A"] = LATTICES["D2Q37"]   # the ninth-degree 37-velocity rule on |e|^2 <= 10
 STORAGES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 MODELS = {"cm": 0, "raw_mrt": 1, "reg_bgk": 2}

@@ -27,61 +27,81 @@ struct HostLattice {
     double wcls[8] = {};
 };
 
-// D2Q37 weights per |e|^2 class and the scale r.  The nine even-moment
-// conditions of a degree-9 rule, sum_i w_i xi_x^p xi_y^q = E[X^p] E[Y^q]
-// with xi = r e, are solved for the eight class weights and x = 1/r^2 by
-// Newton's method (the conditions are linear in w and polynomial in x).
-bool solve_d2q37(double (&wcls)[8], double& r) {
-    static const int mons[9][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}, {8, 0}, {6, 2}, {4, 4}};
+// Weights per shell and the scale r of a 2D Hermite rule.  The
+// even-moment conditions of its degree (nine for degree 9, six for degree
+// 7), sum_i w_i xi_x^p xi_y^q = E[X^p] E[Y^q] with xi = r e, are solved for
+// the shell weights and x = 1/r^2 by Newton's method (the conditions are
+// linear in w and polynomial in x).  Newton starts from equal weights and
+// x = 0.5, then from other x until it reaches the rule's one solution with
+// positive weights.
+bool solve_rule(int kind, double (&wcls)[8], double& r) {
+    const TabH2 t = make_tab_h2(kind);
+    const int nc = (t.q == 37) ? 8 : 5, nm = nc + 1;
+    static const int mons9[9][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}, {8, 0}, {6, 2}, {4, 4}};
+    static const int mons7[6][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}};
+    const int (*mons)[2] = (t.q == 37) ? mons9 : mons7;
     auto gm = [](int p) { double m = 1.0; if (p % 2) return 0.0; for (int k = p - 1; k > 0; k -= 2) m *= k; return m; };
     double S[9][8] = {};
-    for (int i = 0; i < 37; ++i) {
-        const int ex = kTab37.ex[i], ey = kTab37.ey[i], c = kTab37.cls[i];
-        for (int k = 0; k < 9; ++k) S[k][c] += std::pow((double)ex, mons[k][0]) * std::pow((double)ey, mons[k][1]);
+    for (int i = 0; i < t.q; ++i) {
+        const int ex = t.ex[i], ey = t.ey[i], c = t.cls[i];
+        for (int k = 0; k < nm; ++k) S[k][c] += std::pow((double)ex, mons[k][0]) * std::pow((double)ey, mons[k][1]);
     }
-    double v[9];
-    for (int c = 0; c < 8; ++c) v[c] = 1.0 / 37.0;
-    v[8] = 0.5;
-    for (int it = 0; it < 100; ++it) {
-        double J[9][10];
-        double norm = 0.0;
-        for (int k = 0; k < 9; ++k) {
-            const int h = (mons[k][0] + mons[k][1]) / 2;
-            const double g = gm(mons[k][0]) * gm(mons[k][1]);
-            double F = -g * std::pow(v[8], h);
-            for (int c = 0; c < 8; ++c) { F += S[k][c] * v[c]; J[k][c] = S[k][c]; }
-            J[k][8] = h ? -g * h * std::pow(v[8], h - 1) : 0.0;
-            J[k][9] = -F;
-            norm += F * F;
-        }
-        // Gaussian elimination with partial pivoting on the augmented system
-        for (int col = 0; col < 9; ++col) {
-            int piv = col;
-            for (int row = col + 1; row < 9; ++row)
-                if (std::fabs(J[row][col]) > std::fabs(J[piv][col])) piv = row;
-            if (J[piv][col] == 0.0) return false;
-            for (int k = 0; k < 10; ++k) std::swap(J[col][k], J[piv][k]);
-            for (int row = col + 1; row < 9; ++row) {
-                const double m = J[row][col] / J[col][col];
-                for (int k = col; k < 10; ++k) J[row][k] -= m * J[col][k];
+    static const double x0s[6] = {0.5, 0.3, 0.7, 1.0, 1.5, 2.0};
+    for (double x0 : x0s) {
+        double v[9];
+        for (int c = 0; c < nc; ++c) v[c] = 1.0 / t.q;
+        v[nc] = x0;
+        bool ok = true;
+        for (int it = 0; it < 100 && ok; ++it) {
+            double J[9][10];
+            double norm = 0.0;
+            for (int k = 0; k < nm; ++k) {
+                const int h = (mons[k][0] + mons[k][1]) / 2;
+                const double g = gm(mons[k][0]) * gm(mons[k][1]);
+                double F = -g * std::pow(v[nc], h);
+                for (int c = 0; c < nc; ++c) { F += S[k][c] * v[c]; J[k][c] = S[k][c]; }
+                J[k][nc] = h ? -g * h * std::pow(v[nc], h - 1) : 0.0;
+                J[k][nm] = -F;
+                norm += F * F;
             }
+            // Gaussian elimination with partial pivoting on the augmented system
+            for (int col = 0; col < nm && ok; ++col) {
+                int piv = col;
+                for (int row = col + 1; row < nm; ++row)
+                    if (std::fabs(J[row][col]) > std::fabs(J[piv][col])) piv = row;
+                if (J[piv][col] == 0.0) { ok = false; break; }
+                for (int k = 0; k <= nm; ++k) std::swap(J[col][k], J[piv][k]);
+                for (int row = col + 1; row < nm; ++row) {
+                    const double m = J[row][col] / J[col][col];
+                    for (int k = col; k <= nm; ++k) J[row][k] -= m * J[col][k];
+                }
+            }
+            if (!ok) break;
+            double dv[9];
+            for (int row = nm - 1; row >= 0; --row) {
+                double sum = J[row][nm];
+                for (int k = row + 1; k < nm; ++k) sum -= J[row][k] * dv[k];
+                dv[row] = sum / J[row][row];
+            }
+            for (int k = 0; k < nm; ++k) v[k] += dv[k];
+            if (norm < 1e-30 && it > 3) break;
         }
-        double dv[9];
-        for (int row = 8; row >= 0; --row) {
-            double s = J[row][9];
-            for (int k = row + 1; k < 9; ++k) s -= J[row][k] * dv[k];
-            dv[row] = s / J[row][row];
+        bool pos = ok && v[nc] > 0.0 && std::isfinite(v[nc]);
+        for (int c = 0; c < nc && pos; ++c) pos = v[c] > 0.0;
+        if (!pos) continue;
+        // converged: every condition holds
+        double worst = 0.0;
+        for (int k = 0; k < nm; ++k) {
+            double F = -gm(mons[k][0]) * gm(mons[k][1]) * std::pow(v[nc], (mons[k][0] + mons[k][1]) / 2);
+            for (int c = 0; c < nc; ++c) F += S[k][c] * v[c];
+            worst = std::fmax(worst, std::fabs(F));
         }
-        for (int k = 0; k < 9; ++k) v[k] += dv[k];
-        if (norm < 1e-30 && it > 3) break;
+        if (!(worst < 1e-12)) continue;
+        for (int c = 0; c < 8; ++c) wcls[c] = c < nc ? v[c] : 0.0;
+        r = 1.0 / std::sqrt(v[nc]);
+        return true;
     }
-    for (int c = 0; c < 8; ++c) {
-        if (!(v[c] > 0.0)) return false;
-        wcls[c] = v[c];
-    }
-    if (!(v[8] > 0.0)) return false;
-    r = 1.0 / std::sqrt(v[8]);
-    return true;
+    return false;
 }
 
 bool host_lattice(int kind, HostLattice& L) {
@@ -100,22 +120,27 @@ bool host_lattice(int kind, HostLattice& L) {
         }
         return true;
     }
-    if (kind == CMLB_D2Q37) {
-        static bool done = false;
-        static double wc[8], r;
-        if (!done) {
-            if (!solve_d2q37(wc, r)) return false;
-            done = true;
+    if (kind >= CMLB_D2Q37 && kind < kNumLattices) {
+        static std::mutex m;
+        static bool done[kNumLattices] = {};
+        static double wc_all[kNumLattices][8], r_all[kNumLattices];
+        {
+            std::lock_guard<std::mutex> lock(m);
+            if (!done[kind]) {
+                if (!solve_rule(kind, wc_all[kind], r_all[kind])) return false;
+                done[kind] = true;
+            }
         }
+        const TabH2 t = make_tab_h2(kind);
         L.D = 2;
-        L.Q = 37;
-        L.r = r;
-        for (int c = 0; c < 8; ++c) L.wcls[c] = wc[c];
-        for (int i = 0; i < 37; ++i) {
-            L.e[i][0] = kTab37.ex[i];
-            L.e[i][1] = kTab37.ey[i];
+        L.Q = t.q;
+        L.r = r_all[kind];
+        for (int c = 0; c < 8; ++c) L.wcls[c] = wc_all[kind][c];
+        for (int i = 0; i < t.q; ++i) {
+            L.e[i][0] = t.ex[i];
+            L.e[i][1] = t.ey[i];
             L.e[i][2] = 0;
-            L.w[i] = wc[kTab37.cls[i]];
+            L.w[i] = wc_all[kind][t.cls[i]];
         }
         return true;
     }
@@ -124,7 +149,9 @@ bool host_lattice(int kind, HostLattice& L) {
 
 size_t storage_bytes(int st) { return st == CMLB_F64 ? 8 : st == CMLB_F32 ? 4 : 2; }
 
-int lattice_q(int lattice) { return lattice == CMLB_D2Q9 ? 9 : (lattice == CMLB_D3Q27 ? 27 : 37); }
+int lattice_q(int lattice) {
+    return lattice == CMLB_D2Q9 ? 9 : (lattice == CMLB_D3Q27 ? 27 : make_tab_h2(lattice).q);
+}
 
 // Bytes of one population buffer: Q planes of pitch * ny * nz elements.
 size_t state_bytes_of(const cmlb_params* p) {
@@ -135,6 +162,8 @@ size_t state_bytes_of(const cmlb_params* p) {
 
 }  // namespace
 
+static_assert(CMLB_D2Q37 == cmlb::kD2Q37 && CMLB_E9B == cmlb::kE9B && CMLB_E7A == cmlb::kE7A &&
+              CMLB_E7D == cmlb::kE7D && CMLB_E7D + 1 == cmlb::kNumLattices, "lattice numbering");
 static_assert(CMLB_MAX_BATCH == cmlb::kMaxBatch, "batch size limit");
 static_assert(sizeof(cmlb::BatchArgs) <= 4096, "batch arguments fit the kernel argument segment");
 
@@ -222,18 +251,23 @@ void set_omegas(cmlb_ctx* c) {
 
 std::string validate(const cmlb_params* p) {
     if (!p) return "params is NULL";
-    if (p->lattice < CMLB_D2Q9 || p->lattice > CMLB_D2Q37) return "unknown lattice";
+    if (p->lattice < CMLB_D2Q9 || p->lattice > CMLB_E7D) return "unknown lattice";
     if (p->storage < CMLB_F64 || p->storage > CMLB_F16) return "unknown storage";
     if (p->model < CMLB_MODEL_CM || p->model > CMLB_MODEL_REG_BGK) return "unknown collision model";
-    if (p->model != CMLB_MODEL_CM && p->lattice != CMLB_D2Q37)
-        return "raw-moment MRT and regularised BGK are implemented for D2Q37 only";
-    if (p->thermal && p->lattice != CMLB_D2Q37) return "thermal mode needs the D2Q37 lattice";
+    const bool rule2d = p->lattice >= CMLB_D2Q37;   // a 2D Hermite rule
+    if (p->model == CMLB_MODEL_RAW_MRT && p->lattice != CMLB_D2Q37)
+        return "raw-moment MRT is implemented for D2Q37 only";
+    if (p->model == CMLB_MODEL_REG_BGK && !rule2d)
+        return "regularised BGK is implemented for the 2D Hermite rules only";
+    if (rule2d && p->lattice != CMLB_D2Q37 && p->storage != CMLB_F64 && p->storage != CMLB_F32)
+        return "the 2D rules other than D2Q37 take FP64 or FP32 storage";
+    if (p->thermal && !rule2d) return "thermal mode needs a 2D Hermite rule (D2Q37, E9*, E7*)";
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "grid sizes must be >= 1";
     if (p->lattice != CMLB_D3Q27 && p->nz != 1) return "2D lattices need nz == 1";
-    // the D2Q37 gather wraps shifts of up to 3 cells with a single correction
-    if (p->lattice == CMLB_D2Q37 && (p->nx < 3 || p->ny < 3)) return "D2Q37 needs nx, ny >= 3";
+    // the gather of the 2D rules wraps shifts of up to 3 cells with a single correction
+    if (rule2d && (p->nx < 3 || p->ny < 3)) return "the 2D Hermite rules need nx, ny >= 3";
     if (p->nx > (1 << 20) || p->ny > (1 << 20) || p->nz > (1 << 20)) return "grid size too large";
-    const int Q = (p->lattice == CMLB_D2Q9) ? 9 : (p->lattice == CMLB_D3Q27 ? 27 : 37);
+    const int Q = lattice_q(p->lattice);
     const double nodes = (double)p->nx * (double)p->ny * (double)p->nz;
     if (nodes * Q >= 4294967296.0 * 8) return "grid too large";
     if ((uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz >= (1ull << 32)) return "more than 2^32 nodes";

@@ -1,12 +1,13 @@
-// Central-moment collision on the 37-velocity ninth-degree 2D lattice with
-// order-4 Hermite truncation (N = M = 4, Sec. II.B-C), thermal or isothermal.
+// Central-moment collision on the 2D Hermite rules: the ninth-degree
+// 37-velocity rules with order-4 truncation (N = M = 4, Sec. II.B-C) and the
+// seventh-degree 17-velocity rules with N = M = 3, thermal or isothermal.
 //
-// The paper's update f* = f^ + Omega keeps the 15 Hermite components of
-// order <= 4 (eq:reg) and relaxes them so that eq:omega holds for n <= 4.
-// On this lattice the raw moments of order <= 4 of f and of its projection
-// f^ agree (the quadrature is exact to degree 9), so the kernel works with
+// The paper's update f* = f^ + Omega keeps the Hermite components of order
+// <= N (eq:reg) and relaxes them so that eq:omega holds for n <= N.  On these
+// rules the raw moments of order <= N of f and of its projection f^ agree
+// (the quadrature degree is at least 2N + 1), so the kernel works with
 // moments throughout:
-//   1. integer lattice moments M_kl = sum_i h_i e_x^k e_y^l (k + l <= 4),
+//   1. integer lattice moments M_kl = sum_i h_i e_x^k e_y^l (k + l <= N),
 //      paired over +-e so even orders use h_i + h_-i and odd ones h_i - h_-i;
 //   2. xi-unit raw moments m_kl = r^(k+l) M_kl, then rho, u, theta;
 //   3. central moments by a per-axis binomial shift (Appendix A, eq:trans-a);
@@ -22,15 +23,16 @@
 // The raw-moment MRT of eq:regnmrt instead relaxes the a_kl themselves.
 //
 // Everything is carried on deviations h = f - w rho0: their moments are the
-// moments of f minus rho0 times the standard-normal moments, and the
-// deviation equilibrium is assembled from small differences only.
+// moments of f minus rho0 times the standard-normal moments (exact to the
+// rule's degree), and the deviation equilibrium is assembled from small
+// differences only.
 #pragma once
 
 #include "common.hpp"
 
 namespace cmlb {
 
-// Triangle of multi-indices (k, l), k + l <= 4, stored in a 5x5 array.
+// Triangle of multi-indices (k, l), k + l <= N <= 4, stored in a 5x5 array.
 template <class R>
 struct Tri {
     R v[5][5];
@@ -52,22 +54,23 @@ __host__ __device__ constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b *
 __host__ __device__ constexpr int fact_c(int n) { return n <= 1 ? 1 : n * fact_c(n - 1); }
 
 // 1. lattice moments of the deviation populations.
-template <class R>
-__device__ __forceinline__ Tri<R> d37_moments(const R (&h)[37]) {
+template <int LAT, class R>
+__device__ __forceinline__ Tri<R> h2_moments(const R (&h)[H2<LAT>::Q]) {
+    using L = H2<LAT>;
     Tri<R> M;
     static_for<0, 5>([&](auto K) {
-        static_for<0, 5>([&](auto L) { M.v[decltype(K)::value][decltype(L)::value] = R(0); });
+        static_for<0, 5>([&](auto L_) { M.v[decltype(K)::value][decltype(L_)::value] = R(0); });
     });
-    M.v[0][0] = h[18];
-    static_for<19, 37>([&](auto I) {
+    M.v[0][0] = h[L::rest];
+    static_for<L::rest + 1, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
-        const R s = h[i] + h[36 - i];
-        const R d = h[i] - h[36 - i];
+        constexpr int ex = L::tab.ex[i], ey = L::tab.ey[i];
+        const R s = h[i] + h[L::Q - 1 - i];
+        const R d = h[i] - h[L::Q - 1 - i];
         static_for<0, 5>([&](auto K) {
-            static_for<0, 5>([&](auto L) {
-                constexpr int k = decltype(K)::value, l = decltype(L)::value;
-                if constexpr (k + l <= 4) {
+            static_for<0, 5>([&](auto L_) {
+                constexpr int k = decltype(K)::value, l = decltype(L_)::value;
+                if constexpr (k + l <= L::N) {
                     constexpr int c = ipow_c(ex, k) * ipow_c(ey, l);
                     if constexpr (c != 0) {
                         if constexpr ((k + l) % 2 == 0) M.v[k][l] += R(c) * s;
@@ -83,14 +86,14 @@ __device__ __forceinline__ Tri<R> d37_moments(const R (&h)[37]) {
 // Per-axis binomial shift of a triangle: out_kl = sum_a C(k,a) t^(k-a) in_al
 // along x (AXIS = 0) or along y (AXIS = 1).  t = -u gives central moments
 // from raw ones, t = +u the inverse.
-template <int AXIS, class R>
-__device__ __forceinline__ Tri<R> d37_shift(const Tri<R>& in, R t) {
+template <int N, int AXIS, class R>
+__device__ __forceinline__ Tri<R> h2_shift(const Tri<R>& in, R t) {
     const R tp[5] = {R(1), t, t * t, t * t * t, (t * t) * (t * t)};
     Tri<R> out;
     static_for<0, 5>([&](auto K) {
         static_for<0, 5>([&](auto L) {
             constexpr int k = decltype(K)::value, l = decltype(L)::value;
-            if constexpr (k + l <= 4) {
+            if constexpr (k + l <= N) {
                 constexpr int n = AXIS == 0 ? k : l;
                 R acc = in.v[k][l];
                 static_for<0, n>([&](auto A) {
@@ -107,14 +110,14 @@ __device__ __forceinline__ Tri<R> d37_shift(const Tri<R>& in, R t) {
 }
 
 template <class R>
-struct D37State {
+struct H2State {
     R drho, rho, ux, uy, dtheta;  // xi-units velocity, theta - 1
 };
 
 // 2. macroscopic state from the xi-unit raw moments of the deviations.
 template <class R>
-__device__ __forceinline__ D37State<R> d37_state(const Tri<R>& m, R rho0, bool thermal, R theta0) {
-    D37State<R> st;
+__device__ __forceinline__ H2State<R> h2_state(const Tri<R>& m, R rho0, bool thermal, R theta0) {
+    H2State<R> st;
     st.drho = m.v[0][0];
     st.rho = rho0 + st.drho;
     const R inv = recip<R>(st.rho);
@@ -133,7 +136,7 @@ __device__ __forceinline__ D37State<R> d37_state(const Tri<R>& m, R rho0, bool t
 // mu' the central moments of the standard normal about u, written as
 // drho mu_k mu_l + rho0 (Delta_k mu_l + mu'_k Delta_l), Delta = mu - mu'.
 template <class R>
-__device__ __forceinline__ void d37_eq_factors(R u, R dth, R (&mu)[5], R (&mup)[5], R (&del)[5]) {
+__device__ __forceinline__ void h2_eq_factors(R u, R dth, R (&mu)[5], R (&mup)[5], R (&del)[5]) {
     const R th = R(1) + dth, u2 = u * u;
     mu[0] = R(1); mu[1] = R(0); mu[2] = th; mu[3] = R(0); mu[4] = R(3) * th * th;
     mup[0] = R(1); mup[1] = -u; mup[2] = R(1) + u2; mup[3] = -u * (u2 + R(3)); mup[4] = u2 * (u2 + R(6)) + R(3);
@@ -143,14 +146,14 @@ __device__ __forceinline__ void d37_eq_factors(R u, R dth, R (&mu)[5], R (&mup)[
 
 // 5. raw xi-moments of f* - w rho0 -> coefficients C_ab of the polynomial
 // sum_ab C_ab e_x^a e_y^b = sum_kl a_kl He_k(r e_x) He_l(r e_y) / (k! l!).
-template <class R>
-__device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
+template <int N, class R>
+__device__ __forceinline__ Tri<R> h2_poly_from_raw(const Tri<R>& m, R r) {
     // a_kl = sum_ab he(k,a) he(l,b) m_ab
     Tri<R> t, a, c, C;
     static_for<0, 5>([&](auto K) {
         static_for<0, 5>([&](auto L) {
             constexpr int k = decltype(K)::value, l = decltype(L)::value;
-            if constexpr (k + l <= 4) {
+            if constexpr (k + l <= N) {
                 R acc = R(0);
                 static_for<0, k + 1>([&](auto A) {
                     constexpr int aa = decltype(A)::value;
@@ -164,7 +167,7 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
     static_for<0, 5>([&](auto K) {
         static_for<0, 5>([&](auto L) {
             constexpr int k = decltype(K)::value, l = decltype(L)::value;
-            if constexpr (k + l <= 4) {
+            if constexpr (k + l <= N) {
                 R acc = R(0);
                 static_for<0, l + 1>([&](auto B) {
                     constexpr int b = decltype(B)::value;
@@ -180,9 +183,9 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
     static_for<0, 5>([&](auto A) {
         static_for<0, 5>([&](auto L) {
             constexpr int aa = decltype(A)::value, l = decltype(L)::value;
-            if constexpr (aa + l <= 4) {
+            if constexpr (aa + l <= N) {
                 R acc = R(0);
-                static_for<aa, 5 - l>([&](auto K) {
+                static_for<aa, N + 1 - l>([&](auto K) {
                     constexpr int k = decltype(K)::value;
                     constexpr int c = he_coef(k, aa);
                     if constexpr (c != 0) acc += R(c) * a.v[k][l];
@@ -195,9 +198,9 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
     static_for<0, 5>([&](auto A) {
         static_for<0, 5>([&](auto B) {
             constexpr int aa = decltype(A)::value, b = decltype(B)::value;
-            if constexpr (aa + b <= 4) {
+            if constexpr (aa + b <= N) {
                 R acc = R(0);
-                static_for<b, 5 - aa>([&](auto L) {
+                static_for<b, N + 1 - aa>([&](auto L) {
                     constexpr int l = decltype(L)::value;
                     constexpr int cc = he_coef(l, b);
                     if constexpr (cc != 0) acc += R(cc) * c.v[aa][l];
@@ -210,17 +213,18 @@ __device__ __forceinline__ Tri<R> d37_poly_from_raw(const Tri<R>& m, R r) {
 }
 
 // Reconstruct deviation populations from the polynomial coefficients.
-template <class R>
-__device__ __forceinline__ void d37_reconstruct(R (&h)[37], const Tri<R>& C, const R (&wc)[8]) {
-    h[18] = wc[0] * C.v[0][0];
-    static_for<19, 37>([&](auto I) {
+template <int LAT, class R>
+__device__ __forceinline__ void h2_reconstruct(R (&h)[H2<LAT>::Q], const Tri<R>& C, const R (&wc)[8]) {
+    using L = H2<LAT>;
+    h[L::rest] = wc[0] * C.v[0][0];
+    static_for<L::rest + 1, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int ex = kTab37.ex[i], ey = kTab37.ey[i];
+        constexpr int ex = L::tab.ex[i], ey = L::tab.ey[i];
         R ev = R(0), od = R(0);
         static_for<0, 5>([&](auto A) {
             static_for<0, 5>([&](auto B) {
                 constexpr int a = decltype(A)::value, b = decltype(B)::value;
-                if constexpr (a + b <= 4) {
+                if constexpr (a + b <= L::N) {
                     constexpr int c = ipow_c(ex, a) * ipow_c(ey, b);
                     if constexpr (c != 0) {
                         if constexpr ((a + b) % 2 == 0) ev += R(c) * C.v[a][b];
@@ -229,25 +233,27 @@ __device__ __forceinline__ void d37_reconstruct(R (&h)[37], const Tri<R>& C, con
                 }
             });
         });
-        const R w = wc[kTab37.cls[i]];
+        const R w = wc[L::tab.cls[i]];
         h[i] = w * (ev + od);
-        h[36 - i] = w * (ev - od);
+        h[L::Q - 1 - i] = w * (ev - od);
     });
 }
 
 // Full collision of one node (in place on deviation populations).
-template <int MODEL, class R>
-__device__ __forceinline__ void d37_collide(R (&h)[37], R rho0, const R* om, R r, const R (&wc)[8],
-                                            bool thermal, R theta0) {
-    Tri<R> M = d37_moments<R>(h);
+template <int LAT, int MODEL, class R>
+__device__ __forceinline__ void h2_collide(R (&h)[H2<LAT>::Q], R rho0, const R* om, R r, const R (&wc)[8],
+                                           bool thermal, R theta0) {
+    constexpr int N = H2<LAT>::N;
+    static_assert(MODEL == kCM || N == 4, "raw-moment MRT and regularised BGK are built for the order-4 rules");
+    Tri<R> M = h2_moments<LAT, R>(h);
     const R rp[5] = {R(1), r, r * r, r * r * r, (r * r) * (r * r)};
     static_for<0, 5>([&](auto K) {
         static_for<0, 5>([&](auto L) {
             constexpr int k = decltype(K)::value, l = decltype(L)::value;
-            if constexpr (k + l <= 4) M.v[k][l] *= rp[k + l];
+            if constexpr (k + l <= N) M.v[k][l] *= rp[k + l];
         });
     });
-    const D37State<R> st = d37_state<R>(M, rho0, thermal, theta0);
+    const H2State<R> st = h2_state<R>(M, rho0, thermal, theta0);
     Tri<R> mstar;
     if constexpr (MODEL == kRawMRT) {
         // Relax absolute-frame Hermite coefficients a_kl of the raw moments:
@@ -332,44 +338,45 @@ __device__ __forceinline__ void d37_collide(R (&h)[37], R rho0, const R* om, R r
         });
     } else {
         // central moments of the deviations
-        Tri<R> kap = d37_shift<1, R>(d37_shift<0, R>(M, -st.ux), -st.uy);
+        Tri<R> kap = h2_shift<N, 1, R>(h2_shift<N, 0, R>(M, -st.ux), -st.uy);
         R mux[5], mupx[5], delx[5], muy[5], mupy[5], dely[5];
-        d37_eq_factors<R>(st.ux, st.dtheta, mux, mupx, delx);
-        d37_eq_factors<R>(st.uy, st.dtheta, muy, mupy, dely);
+        h2_eq_factors<R>(st.ux, st.dtheta, mux, mupx, delx);
+        h2_eq_factors<R>(st.uy, st.dtheta, muy, mupy, dely);
         static_for<0, 5>([&](auto K) {
             static_for<0, 5>([&](auto L) {
                 constexpr int k = decltype(K)::value, l = decltype(L)::value;
-                if constexpr (k + l >= 2 && k + l <= 4) {
+                if constexpr (k + l >= 2 && k + l <= N) {
                     const R keq = st.drho * mux[k] * muy[l] + rho0 * (delx[k] * muy[l] + mupx[k] * dely[l]);
                     kap.v[k][l] += om[k + l] * (keq - kap.v[k][l]);
                 }
             });
         });
-        mstar = d37_shift<1, R>(d37_shift<0, R>(kap, st.ux), st.uy);
+        mstar = h2_shift<N, 1, R>(h2_shift<N, 0, R>(kap, st.ux), st.uy);
     }
-    const Tri<R> C = d37_poly_from_raw<R>(mstar, r);
-    d37_reconstruct<R>(h, C, wc);
+    const Tri<R> C = h2_poly_from_raw<N, R>(mstar, r);
+    h2_reconstruct<LAT, R>(h, C, wc);
 }
 
-// Deviation equilibrium populations: the order-4 Hermite equilibrium has the
-// Maxwellian's central moments up to order 4.
-template <class R>
-__device__ __forceinline__ void d37_equilibrium(R (&h)[37], R drho, R rho0, R ux_xi, R uy_xi, R dtheta,
-                                                R r, const R (&wc)[8]) {
+// Deviation equilibrium populations: the order-N Hermite equilibrium has the
+// Maxwellian's central moments up to order N.
+template <int LAT, class R>
+__device__ __forceinline__ void h2_equilibrium(R (&h)[H2<LAT>::Q], R drho, R rho0, R ux_xi, R uy_xi, R dtheta,
+                                               R r, const R (&wc)[8]) {
+    constexpr int N = H2<LAT>::N;
     R mux[5], mupx[5], delx[5], muy[5], mupy[5], dely[5];
-    d37_eq_factors<R>(ux_xi, dtheta, mux, mupx, delx);
-    d37_eq_factors<R>(uy_xi, dtheta, muy, mupy, dely);
+    h2_eq_factors<R>(ux_xi, dtheta, mux, mupx, delx);
+    h2_eq_factors<R>(uy_xi, dtheta, muy, mupy, dely);
     Tri<R> kap;
     static_for<0, 5>([&](auto K) {
         static_for<0, 5>([&](auto L) {
             constexpr int k = decltype(K)::value, l = decltype(L)::value;
-            if constexpr (k + l <= 4)
+            if constexpr (k + l <= N)
                 kap.v[k][l] = drho * mux[k] * muy[l] + rho0 * (delx[k] * muy[l] + mupx[k] * dely[l]);
         });
     });
-    const Tri<R> m = d37_shift<1, R>(d37_shift<0, R>(kap, ux_xi), uy_xi);
-    const Tri<R> C = d37_poly_from_raw<R>(m, r);
-    d37_reconstruct<R>(h, C, wc);
+    const Tri<R> m = h2_shift<N, 1, R>(h2_shift<N, 0, R>(kap, ux_xi), uy_xi);
+    const Tri<R> C = h2_poly_from_raw<N, R>(m, r);
+    h2_reconstruct<LAT, R>(h, C, wc);
 }
 
 }  // namespace cmlb

@@ -8,7 +8,12 @@
 
 namespace cmlb {
 
-enum Lattice { kD2Q9 = 0, kD3Q27 = 1, kD2Q37 = 2 };
+// D2Q37 is the ninth-degree 37-velocity rule on |e|^2 <= 10; E9B-E9D and
+// E7A-E7D are the other minimal 2D rules of degree 9 (37 velocities) and 7
+// (17 velocities) whose velocity components are at most 3.
+enum Lattice { kD2Q9 = 0, kD3Q27 = 1, kD2Q37 = 2, kE9B = 3, kE9C = 4, kE9D = 5, kE7A = 6, kE7B = 7, kE7C = 8,
+               kE7D = 9 };
+constexpr int kNumLattices = 10;
 enum Storage { kF64 = 0, kF32 = 1, kBF16 = 2, kF16 = 3 };
 enum Model { kCM = 0, kRawMRT = 1, kRegBGK = 2 };
 
@@ -47,36 +52,69 @@ __device__ __forceinline__ uint32_t wrap_sub(uint32_t v, int e, uint32_t n) {
 // ---------------------------------------------------------------------------
 // Lattice velocity tables.
 // D2Q9 / D3Q27: e in {-1,0,1}^D, index i = (ex+1) + 3(ey+1) + 9(ez+1).
-// D2Q37: e in Z^2 with |e|^2 <= 10, ordered lexicographically in (ey, ex);
-// the ordering is centrally symmetric, so -e_i is population 36 - i and the
-// rest population is 18.  cls(i) numbers the weight classes by |e|^2.
+// 2D Hermite rules: the velocities of their shells, ordered lexicographically
+// in (ey, ex); the ordering is centrally symmetric, so -e_i is population
+// Q - 1 - i and the rest population is (Q - 1) / 2.  cls(i) is the index of
+// the velocity's shell, which numbers the weight classes.
 // ---------------------------------------------------------------------------
-struct TabD37 {
+struct Shells2 {
+    int n;           // number of shells (8 on 37 velocities, 5 on 17)
+    int ab[8][2];    // |e| component pairs, smaller first
+};
+
+constexpr Shells2 rule_shells(int lat) {
+    switch (lat) {
+        case kD2Q37: return {8, {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {1, 3}}};
+        case kE9B: return {8, {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {2, 3}}};
+        case kE9C: return {8, {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {3, 3}, {0, 3}, {1, 3}}};
+        case kE9D: return {8, {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {3, 3}, {0, 3}, {2, 3}}};
+        case kE7A: return {5, {{0, 0}, {0, 1}, {1, 1}, {2, 2}, {0, 3}}};
+        case kE7B: return {5, {{0, 0}, {0, 1}, {1, 1}, {3, 3}, {0, 3}}};
+        case kE7C: return {5, {{0, 0}, {0, 2}, {1, 1}, {3, 3}, {0, 3}}};
+        case kE7D: return {5, {{0, 0}, {1, 1}, {2, 2}, {3, 3}, {0, 3}}};
+    }
+    return {0, {}};
+}
+
+struct TabH2 {
+    int q;       // velocities
+    int n;       // Hermite truncation N = M: 4 for degree 9, 3 for degree 7
     int ex[37], ey[37], cls[37];
 };
 
-constexpr int d37_norm_class(int n2) {
-    // |e|^2 takes the values 0, 1, 2, 4, 5, 8, 9, 10
-    return n2 == 0 ? 0 : n2 == 1 ? 1 : n2 == 2 ? 2 : n2 == 4 ? 3 : n2 == 5 ? 4 : n2 == 8 ? 5 : n2 == 9 ? 6 : 7;
-}
-
-constexpr TabD37 make_tab_d37() {
-    TabD37 t{};
+constexpr TabH2 make_tab_h2(int lat) {
+    TabH2 t{};
+    const Shells2 sh = rule_shells(lat);
+    t.n = sh.n == 8 ? 4 : 3;
     int k = 0;
     for (int ey = -3; ey <= 3; ++ey)
-        for (int ex = -3; ex <= 3; ++ex)
-            if (ex * ex + ey * ey <= 10) {
-                t.ex[k] = ex;
-                t.ey[k] = ey;
-                t.cls[k] = d37_norm_class(ex * ex + ey * ey);
-                ++k;
-            }
+        for (int ex = -3; ex <= 3; ++ex) {
+            const int ax = ex < 0 ? -ex : ex, ay = ey < 0 ? -ey : ey;
+            const int a = ax < ay ? ax : ay, b = ax < ay ? ay : ax;
+            for (int c = 0; c < sh.n; ++c)
+                if (sh.ab[c][0] == a && sh.ab[c][1] == b) {
+                    t.ex[k] = ex;
+                    t.ey[k] = ey;
+                    t.cls[k] = c;
+                    ++k;
+                }
+        }
+    t.q = k;
     return t;
 }
 
-inline constexpr TabD37 kTab37 = make_tab_d37();
-static_assert(kTab37.ex[36] == 1 && kTab37.ey[36] == 3, "D2Q37 table");
+// Compile-time description of a 2D Hermite rule.
+template <int LAT>
+struct H2 {
+    static constexpr TabH2 tab = make_tab_h2(LAT);
+    static constexpr int Q = tab.q, N = tab.n, rest = (tab.q - 1) / 2;
+};
+
+inline constexpr TabH2 kTab37 = make_tab_h2(kD2Q37);
+static_assert(kTab37.q == 37 && kTab37.ex[36] == 1 && kTab37.ey[36] == 3, "D2Q37 table");
 static_assert(kTab37.ex[18] == 0 && kTab37.ey[18] == 0, "D2Q37 rest population");
+static_assert(H2<kE7A>::Q == 17 && H2<kE7D>::Q == 17 && H2<kE9D>::Q == 37, "rule sizes");
+static_assert(H2<kE7C>::tab.ex[8] == 0 && H2<kE7C>::tab.ey[8] == 0, "17-velocity rest population");
 
 template <int D>
 struct TP {

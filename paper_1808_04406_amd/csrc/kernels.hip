@@ -10,7 +10,7 @@
 // the storage type.
 #include "launch.hpp"
 
-#include "collide_d2q37.hpp"
+#include "collide_h2.hpp"
 #include "collide_tp.hpp"
 
 namespace cmlb {
@@ -37,21 +37,22 @@ __global__ __launch_bounds__(256) void k_init_tp(StepArgs a, FieldArgs fa) {
     }
 }
 
-template <int ST>
-__global__ __launch_bounds__(256) void k_init_d37(StepArgs a, FieldArgs fa) {
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_init_h2(StepArgs a, FieldArgs fa) {
     using S = Store<ST>;
     using T = typename S::T;
+    constexpr int Q = H2<LAT>::Q;
     T* dst = static_cast<T*>(a.dst);
     double wc[8];
     for (int k = 0; k < 8; ++k) wc[k] = a.wcls[k];
     for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < nodes_of(a.g);
          n += (uint64_t)gridDim.x * blockDim.x) {
         const double th = fa.theta ? fa.theta[n] : a.theta0;
-        double h[37];
+        double h[Q];
         const uint64_t off = node_offset(a.g.nx, a.pitch, n);
-        d37_equilibrium<double>(h, fa.rho[n] - a.rho0, a.rho0, a.r * fa.u[n], a.r * fa.u[nodes_of(a.g) + n],
-                                th - 1.0, a.r, wc);
-        static_for<0, 37>([&](auto I) {
+        h2_equilibrium<LAT, double>(h, fa.rho[n] - a.rho0, a.rho0, a.r * fa.u[n], a.r * fa.u[nodes_of(a.g) + n],
+                                    th - 1.0, a.r, wc);
+        static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             dst[(uint64_t)i * a.g.plane + off] = S::from_double(h[i] * (double)a.s[i]);
         });
@@ -62,7 +63,12 @@ __global__ __launch_bounds__(256) void k_init_d37(StepArgs a, FieldArgs fa) {
 // Readout, codecs
 // ---------------------------------------------------------------------------
 template <int LAT>
-struct LatInfo;
+struct LatInfo {   // the 2D Hermite rules
+    static constexpr int D = 2, Q = H2<LAT>::Q;
+    static constexpr int ex(int i) { return H2<LAT>::tab.ex[i]; }
+    static constexpr int ey(int i) { return H2<LAT>::tab.ey[i]; }
+    static constexpr int ez(int) { return 0; }
+};
 template <>
 struct LatInfo<kD2Q9> {
     static constexpr int D = 2, Q = 9;
@@ -76,13 +82,6 @@ struct LatInfo<kD3Q27> {
     static constexpr int ex(int i) { return TP<3>::ex(i); }
     static constexpr int ey(int i) { return TP<3>::ey(i); }
     static constexpr int ez(int i) { return TP<3>::ez(i); }
-};
-template <>
-struct LatInfo<kD2Q37> {
-    static constexpr int D = 2, Q = 37;
-    static constexpr int ex(int i) { return kTab37.ex[i]; }
-    static constexpr int ey(int i) { return kTab37.ey[i]; }
-    static constexpr int ez(int) { return 0; }
 };
 
 // Sums of one node's deviation populations (FP64): sum h, sum h e, sum h |e|^2.
@@ -357,12 +356,13 @@ static dim3 flat_grid(uint64_t n) {
 
 int launch_step2(int lattice, int storage, int model, const StepArgs& a, bool force, hipStream_t s) {
     if (lattice == kD2Q37) return launch_step2_d37(storage, model, a, force, s);
-    return launch_step2_tp(lattice, storage, a, force, s);
+    if (lattice == kD2Q9 || lattice == kD3Q27) return launch_step2_tp(lattice, storage, a, force, s);
+    return -1;
 }
 
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s) {
     if (lattice == kD2Q9 || lattice == kD3Q27) return launch_step_tp(lattice, storage, a, s);
-    if (lattice == kD2Q37) return launch_step_d37(storage, model, a, s);
+    if (lattice >= kD2Q37 && lattice < kNumLattices) return launch_step_h2(lattice, storage, model, a, s);
     return -1;
 }
 
@@ -373,13 +373,33 @@ int launch_step_batch(int lattice, int storage, int model, const BatchArgs& A, i
     return -1;
 }
 
+// The other 2D rules: FP64 and FP32 storage.
+template <int ST>
+static int launch_init_rule(int lattice, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
+    if constexpr (ST != kF64 && ST != kF32) {
+        return -1;
+    } else {
+        dim3 grid = flat_grid(nodes_of(a.g)), block(256);
+        switch (lattice) {
+            case kE9B: hipLaunchKernelGGL((k_init_h2<kE9B, ST>), grid, block, 0, s, a, f); return 0;
+            case kE9C: hipLaunchKernelGGL((k_init_h2<kE9C, ST>), grid, block, 0, s, a, f); return 0;
+            case kE9D: hipLaunchKernelGGL((k_init_h2<kE9D, ST>), grid, block, 0, s, a, f); return 0;
+            case kE7A: hipLaunchKernelGGL((k_init_h2<kE7A, ST>), grid, block, 0, s, a, f); return 0;
+            case kE7B: hipLaunchKernelGGL((k_init_h2<kE7B, ST>), grid, block, 0, s, a, f); return 0;
+            case kE7C: hipLaunchKernelGGL((k_init_h2<kE7C, ST>), grid, block, 0, s, a, f); return 0;
+            case kE7D: hipLaunchKernelGGL((k_init_h2<kE7D, ST>), grid, block, 0, s, a, f); return 0;
+        }
+        return -1;
+    }
+}
+
 template <int ST>
 static int launch_init_st(int lattice, const StepArgs& a, const FieldArgs& f, hipStream_t s) {
     dim3 grid = flat_grid(nodes_of(a.g)), block(256);
     if (lattice == kD2Q9) hipLaunchKernelGGL((k_init_tp<2, ST>), grid, block, 0, s, a, f);
     else if (lattice == kD3Q27) hipLaunchKernelGGL((k_init_tp<3, ST>), grid, block, 0, s, a, f);
-    else if (lattice == kD2Q37) hipLaunchKernelGGL((k_init_d37<ST>), grid, block, 0, s, a, f);
-    else return -1;
+    else if (lattice == kD2Q37) hipLaunchKernelGGL((k_init_h2<kD2Q37, ST>), grid, block, 0, s, a, f);
+    else return launch_init_rule<ST>(lattice, a, f, s);
     return 0;
 }
 
@@ -407,6 +427,20 @@ int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f,
         case kD2Q37 * 4 + kF32: LAUNCH(kD2Q37, kF32); break;                      \
         case kD2Q37 * 4 + kBF16: LAUNCH(kD2Q37, kBF16); break;                    \
         case kD2Q37 * 4 + kF16: LAUNCH(kD2Q37, kF16); break;                      \
+        case kE9B * 4 + kF64: LAUNCH(kE9B, kF64); break;                          \
+        case kE9B * 4 + kF32: LAUNCH(kE9B, kF32); break;                          \
+        case kE9C * 4 + kF64: LAUNCH(kE9C, kF64); break;                          \
+        case kE9C * 4 + kF32: LAUNCH(kE9C, kF32); break;                          \
+        case kE9D * 4 + kF64: LAUNCH(kE9D, kF64); break;                          \
+        case kE9D * 4 + kF32: LAUNCH(kE9D, kF32); break;                          \
+        case kE7A * 4 + kF64: LAUNCH(kE7A, kF64); break;                          \
+        case kE7A * 4 + kF32: LAUNCH(kE7A, kF32); break;                          \
+        case kE7B * 4 + kF64: LAUNCH(kE7B, kF64); break;                          \
+        case kE7B * 4 + kF32: LAUNCH(kE7B, kF32); break;                          \
+        case kE7C * 4 + kF64: LAUNCH(kE7C, kF64); break;                          \
+        case kE7C * 4 + kF32: LAUNCH(kE7C, kF32); break;                          \
+        case kE7D * 4 + kF64: LAUNCH(kE7D, kF64); break;                          \
+        case kE7D * 4 + kF32: LAUNCH(kE7D, kF32); break;                          \
         default: return -1;                                                       \
     }
 

@@ -31,7 +31,9 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t nchunks) {
 // Each returns 0, or -1 for an unsupported lattice/storage/model combination.
 int launch_step(int lattice, int storage, int model, const StepArgs& a, hipStream_t s);
 int launch_step_tp(int lattice, int storage, const StepArgs& a, hipStream_t s);     // step_tp.hip
-int launch_step_d37(int storage, int model, const StepArgs& a, hipStream_t s);      // step_d37.hip
+// 2D Hermite rules (step_d37.hip): D2Q37 with every storage and model, the
+// other rules with FP64/FP32 storage and the central-moment kernel.
+int launch_step_h2(int lattice, int storage, int model, const StepArgs& a, hipStream_t s);
 // One step of `count` lattices (A.l[0..count)) in one launch.
 int launch_step_batch(int lattice, int storage, int model, const BatchArgs& A, int count, hipStream_t s);
 int launch_step_tp_batch(int lattice, int storage, const BatchArgs& A, int count, hipStream_t s);

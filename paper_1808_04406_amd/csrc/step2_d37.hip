@@ -25,7 +25,7 @@
 // equals two single steps exactly.  FP32 storage only.
 #include "launch.hpp"
 
-#include "collide_d2q37.hpp"
+#include "collide_h2.hpp"
 
 namespace cmlb {
 
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
             rslot[g] = (wslot[g] == g * step) ? 0 : wslot[g] + step;
         });
         if (act1) {
-            d37_collide<MODEL, float>(h, rho0, om, r, wc, thermal, theta0);
+            h2_collide<kD2Q37, MODEL, float>(h, rho0, om, r, wc, thermal, theta0);
             static_for<0, 37>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int g = kTab37.ey[i] + 3;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
                 const float* row = lds + kGroups37.base[g] * kD2Threads + rslot[g] + t + 3;
                 g2[i] = row[kRing37.k[i] * kD2Threads - kTab37.ex[i]];
             });
-            d37_collide<MODEL, float>(g2, rho0, om, r, wc, thermal, theta0);
+            h2_collide<kD2Q37, MODEL, float>(g2, rho0, om, r, wc, thermal, theta0);
             if (act2) {
                 const uint32_t so = (y0 + (uint32_t)j - 6) * rowb;
                 static_for<0, 37>([&](auto I) {

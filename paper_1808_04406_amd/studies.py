@@ -150,14 +150,14 @@ def _mode2(field, m):
 
 
 def wave_run(n, nu, kappa, theta0, tau4=1.0, steps=350, every=5, model="cm", storage="f32", u0=0.0,
-             amp=(0.001, 0.001, 0.001), k_thermal=(1, 1), stream=None):
-    """One linear-mode run: D2Q37 thermal, tau_2 = 1/2 + nu/theta0,
-    tau_3 = 1/2 + kappa/theta0 (paper's units), background (0, u0).  Returns
-    the measured viscous and thermal decay rates, the acoustic decay rate and
-    frequency (when the acoustic amplitude is non-zero), the eq:dr values and
-    the relative errors."""
-    r = cmlb.lattice_info("D2Q37")["r"]
-    ctx = cmlb.Context("D2Q37", (n, n), storage=storage, thermal=True, model=model,
+             amp=(0.001, 0.001, 0.001), k_thermal=(1, 1), lattice="D2Q37", stream=None):
+    """One linear-mode run on a thermal 2D Hermite rule (D2Q37 by default),
+    tau_2 = 1/2 + nu/theta0, tau_3 = 1/2 + kappa/theta0 (paper's units),
+    background (0, u0).  Returns the measured viscous and thermal decay
+    rates, the acoustic decay rate and frequency (when the acoustic amplitude
+    is non-zero), the eq:dr values and the relative errors."""
+    r = cmlb.lattice_info(lattice)["r"]
+    ctx = cmlb.Context(lattice, (n, n), storage=storage, thermal=True, model=model,
                        tau={2: 0.5 + nu / theta0, 3: 0.5 + kappa / theta0, 4: tau4}, stream=stream)
     rho, u, th = inputs.linear_modes(n, nu, kappa, theta0, r, amp=amp, k_thermal=k_thermal, background=(0.0, u0))
     ctx.init_fields(rho, u, th)
@@ -187,8 +187,8 @@ def wave_run(n, nu, kappa, theta0, tau4=1.0, steps=350, every=5, model="cm", sto
 
     v_th, _, ar_th, ai_th = dr(k1)
     t_th = dr(kt)[1]
-    out = {"n": n, "model": model, "storage": storage, "tau4": tau4, "u0": u0, "steps": steps, "wall_s": wall,
-           "viscous_theory": v_th, "thermal_theory": t_th}
+    out = {"lattice": lattice, "n": n, "model": model, "storage": storage, "tau4": tau4, "theta0": theta0,
+           "u0": u0, "steps": steps, "wall_s": wall, "viscous_theory": v_th, "thermal_theory": t_th}
     if amp[0] != 0.0:
         out["viscous"] = _decay_rate(ts[1:], np.abs(av[1:]))
         out["viscous_err"] = out["viscous"] / v_th - 1
@@ -237,6 +237,48 @@ def modes(stream=None):
                 res["galilean"].append(o)
                 print(f"Fig. 3 tau4={tau4:.5f} {model} u0={u0}: viscosity error {o['viscous_err']:+.3e}, "
                       f"diffusivity error {o['thermal_err']:+.3e}", flush=True)
+    return res
+
+
+RULES_2D = ["D2Q37", "E9B", "E9C", "E9D", "E7A", "E7B", "E7C", "E7D"]
+
+
+def convergence_run(lattice, n, nu, kappa, theta0, tau4=1.0, stream=None):
+    """Grid-convergence point of Fig. 2 on one rule: a viscous and a thermal
+    wave in separate FP64 runs of 1000 (L/100)^2 steps on an L x L lattice;
+    returns both relative rate errors."""
+    steps = int(round(1000 * (n / 100.0) ** 2))
+    every = max(1, steps // 400)
+    steps = every * (steps // every)
+    ov = wave_run(n, nu, kappa, theta0, tau4=tau4, steps=steps, every=every, storage="f64",
+                  amp=(0.001, 0.0, 0.0), lattice=lattice, stream=stream)
+    ot = wave_run(n, nu, kappa, theta0, tau4=tau4, steps=steps, every=every, storage="f64",
+                  amp=(0.0, 0.001, 0.0), lattice=lattice, stream=stream)
+    return {"lattice": lattice, "n": n, "steps": steps, "theta0": theta0, "viscous_err": ov["viscous_err"],
+            "thermal_err": ot["thermal_err"]}
+
+
+def fig2(sizes=(20, 40, 80, 160, 320), stream=None):
+    """Fig. 2 on all eight minimal rules: grid convergence of the viscosity
+    and thermal diffusivity errors (nu = 0.1, kappa = 0.2 as in Fig. 1, tau4
+    = 1 on the order-4 rules), at theta0 = 1 and at Fig. 1's theta0 = 1.2,
+    plus Fig. 1's four errors on every rule at L = 100."""
+    nu, kappa = 0.1, 0.2
+    res = {"nu": nu, "kappa": kappa, "sizes": list(sizes), "convergence": [], "fig1": []}
+    t0 = time.perf_counter()
+    for theta0 in (1.0, 1.2):
+        for lat in RULES_2D:
+            for n in sizes:
+                o = convergence_run(lat, n, nu, kappa, theta0, stream=stream)
+                res["convergence"].append(o)
+                print(f"Fig. 2 {lat} theta0={theta0} L={n}: viscosity error {o['viscous_err']:+.3e}, "
+                      f"diffusivity error {o['thermal_err']:+.3e}", flush=True)
+            o = wave_run(100, nu, kappa, theta0, tau4=1.0, storage="f64", lattice=lat, stream=stream)
+            res["fig1"].append(o)
+            print(f"Fig. 1 {lat} theta0={theta0}: errors viscous {o['viscous_err']:+.3e} thermal "
+                  f"{o['thermal_err']:+.3e} acoustic {o['acoustic_rate_err']:+.3e} / {o['acoustic_freq_err']:+.3e}",
+                  flush=True)
+    res["wall_s"] = time.perf_counter() - t0
     return res
 
 
@@ -289,13 +331,13 @@ class _DslRun:
     finite and <u^2>/u0^2 <= ke_bound."""
 
     def __init__(self, ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0,
-                 checks=32, ke_bound=2.0, stream=None):
-        r = cmlb.lattice_info("D2Q37")["r"]
+                 checks=32, ke_bound=2.0, lattice="D2Q37", stream=None):
+        r = cmlb.lattice_info(lattice)["r"]
         u_lat = ma / r
         nu = ma * r * n / re
         tau2 = 0.5 + nu
         self.tau = {2: tau2, 3: 0.5 + nu / pr, 4: tau2 if tau4 is None else tau4}
-        self.ctx = cmlb.Context("D2Q37", (n, n), storage=storage, thermal=thermal, model=model, tau=self.tau,
+        self.ctx = cmlb.Context(lattice, (n, n), storage=storage, thermal=thermal, model=model, tau=self.tau,
                                 stream=stream)
         rho, u, th = inputs.double_shear_layer(n, u_lat)
         self.ctx.init_fields(rho, u, th)
@@ -334,7 +376,7 @@ class _DslRun:
 def dsl_run(ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0, checks=32,
             ke_bound=2.0, history=False, stream=None):
     """One double-shear-layer run (Sec. III.B), stepped on its own."""
-    run = _DslRun(ma, re, pr, model, thermal, n, tau4, storage, t_end, checks, ke_bound, stream)
+    run = _DslRun(ma, re, pr, model, thermal, n, tau4, storage, t_end, checks, ke_bound, stream=stream)
     while not run.finished:
         k = run.to_next()
         run.ctx.step(k)
@@ -342,7 +384,7 @@ def dsl_run(ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32
     return run.result(history)
 
 
-def max_stable_batched(cases, lo, hi, tol, model="cm", thermal=True, n=128, stream=None):
+def max_stable_batched(cases, lo, hi, tol, model="cm", thermal=True, n=128, stream=None, **run_kw):
     """max_stable for many (Re, Pr) cases of one model at once: every case
     runs its own bisection, and the runs in flight advance together, up to
     cmlb.MAX_BATCH lattices per launch (cmlb_step_batch).  Each run makes the
@@ -353,12 +395,16 @@ def max_stable_batched(cases, lo, hi, tol, model="cm", thermal=True, n=128, stre
     results = [None] * len(cases)
     active = {}
     for i, (re, pr) in enumerate(cases):
-        active[i] = _DslRun(next(gens[i]), re, pr, model, thermal, n, stream=stream)
+        active[i] = _DslRun(next(gens[i]), re, pr, model, thermal, n, stream=stream, **run_kw)
     while active:
         items = sorted(active.items())
         k = min(r.to_next() for _, r in items)
-        for j in range(0, len(items), cmlb.MAX_BATCH):
-            cmlb.step_batch([r.ctx for _, r in items[j:j + cmlb.MAX_BATCH]], k)
+        if run_kw.get("lattice", "D2Q37") == "D2Q37":
+            for j in range(0, len(items), cmlb.MAX_BATCH):
+                cmlb.step_batch([r.ctx for _, r in items[j:j + cmlb.MAX_BATCH]], k)
+        else:   # batched launches are built for D2Q37; the other rules step one by one
+            for _, r in items:
+                r.ctx.step(k)
         for i, r in items:
             r.advanced(k)
             if not r.finished:
@@ -370,7 +416,7 @@ def max_stable_batched(cases, lo, hi, tol, model="cm", thermal=True, n=128, stre
                 del active[i]
                 continue
             re, pr = cases[i]
-            active[i] = _DslRun(x, re, pr, model, thermal, n, stream=stream)
+            active[i] = _DslRun(x, re, pr, model, thermal, n, stream=stream, **run_kw)
     return results
 
 
@@ -396,6 +442,34 @@ def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0)
             print(f"{label} Pr={pr} Re={re:.0e}: Ma_max = {m:.4f} ({len(calls)} runs)", flush=True)
     out["wall_s"] = time.perf_counter() - t0
     out["wall_fig6_s"] = t_fig6
+    return out
+
+
+def dsl_factors(n=128, res_=(1e5, 1e6, 1e7), tol=0.005, stream=None):
+    """What moves the isothermal stability boundary (Sec. III.B, Fig. 5):
+    isothermal CM-MRT at Pr = 1 under the reference settings (tau4 = tau2,
+    <u^2> at most twice its initial value, the |e|^2 <= 10 rule, FP32), then
+    one change at a time: the divergence criterion alone (every population
+    finite), tau4 = 1, the other 37-velocity rules, FP64 storage, and raw MRT."""
+    base = dict(model="cm", ke_bound=2.0, tau4=None, lattice="D2Q37", storage="f32")
+    variants = [("reference", {}), ("finite only", {"ke_bound": float("inf")}), ("tau4 = 1", {"tau4": 1.0}),
+                ("E9B", {"lattice": "E9B"}), ("E9C", {"lattice": "E9C"}), ("E9D", {"lattice": "E9D"}),
+                ("FP64", {"storage": "f64"}), ("raw MRT", {"model": "raw_mrt"}),
+                ("Pr = 0.5", {"pr": 0.5}), ("Pr = 2", {"pr": 2.0})]
+    out = {"n": n, "tol": tol, "res": list(res_), "variants": []}
+    t0 = time.perf_counter()
+    for label, change in variants:
+        kw = dict(base, **change)
+        pr = kw.pop("pr", 1.0)
+        model = kw.pop("model")
+        cases = [(re, pr) for re in res_]
+        found = max_stable_batched(cases, 0.05, 1.2, tol, model=model, thermal=False, n=n, stream=stream, **kw)
+        row = {"label": label, "pr": pr, "model": model, **{k: (v if v != float("inf") else "inf") for k, v in kw.items()},
+               "ma_max": [m for m, _ in found]}
+        out["variants"].append(row)
+        print(f"DSL isothermal {label}: Ma_max " + ", ".join(f"Re={re:.0e} {m:.4f}" for re, (m, _) in zip(res_, found)),
+              flush=True)
+    out["wall_s"] = time.perf_counter() - t0
     return out
 
 
@@ -697,7 +771,8 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "thermal", "closure", "modes", "dsl", "galilean", "tgv"])
+    ap.add_argument("study", choices=["precision", "thermal", "closure", "modes", "fig2", "dsl", "dsl_factors",
+                                      "galilean", "tgv"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--every", type=int, default=None)
@@ -715,8 +790,12 @@ def main(argv=None):
             res = closure(n_fine=a.n or 512, stream=stream)
         elif a.study == "modes":
             res = modes(stream=stream)
+        elif a.study == "fig2":
+            res = fig2(stream=stream)
         elif a.study == "dsl":
             res = dsl(n=a.n or 128, stream=stream)
+        elif a.study == "dsl_factors":
+            res = dsl_factors(n=a.n or 128, stream=stream)
         elif a.study == "tgv":
             res = tgv_energy(n=a.n or 256, steps=a.steps if a.steps != 5000 else 2000, every=a.every or 20,
                              stream=stream)

@@ -27,13 +27,13 @@ def test_header_symbols_exported(cm):
     assert not missing, missing
 
 
-@pytest.mark.parametrize("kind", ["D2Q9", "D3Q27", "D2Q37"])
+@pytest.mark.parametrize("kind", ["D2Q9", "D3Q27", "D2Q37", "E9B", "E9C", "E9D", "E7A", "E7B", "E7C", "E7D"])
 def test_lattice_tables_match_oracle(cm, orc, kind):
     a = cm.lattice_info(kind)
     b = orc.lattice(kind)
     assert a["D"] == b["D"] and a["Q"] == b["Q"]
     assert np.array_equal(a["e"], b["e"])
-    assert a["r"] == pytest.approx(b["r"], rel=1e-14)
+    assert a["r"] == pytest.approx(b["r"], rel=5e-15)
     assert np.allclose(a["w"], b["w"], rtol=1e-13, atol=0)
 
 
@@ -47,6 +47,10 @@ def test_lattice_tables_match_oracle(cm, orc, kind):
     dict(lattice="D2Q37", shape=(8, 8), scale=[-1.0] * 37),
     dict(lattice="D3Q27", shape=(4096, 4096, 4096)),
     dict(lattice="D2Q37", shape=(2, 8)),            # D2Q37 shifts reach 3 cells
+    dict(lattice="E7C", shape=(8, 2)),              # so do the other 2D rules
+    dict(lattice="E9B", shape=(8, 8), storage="bf16"),     # other 2D rules: FP64/FP32 only
+    dict(lattice="E7A", shape=(8, 8), model="raw_mrt"),    # raw MRT: D2Q37 only
+    dict(lattice="D3Q27", shape=(8, 8, 8), model="reg_bgk"),
 ])
 def test_create_rejects_invalid_params(cm, bad):
     with pytest.raises(cm.CmlbError) as ei:
@@ -145,7 +149,7 @@ def test_checkpoint_header_errors(tmp_path):
 # ---------------------------------------------------------------------------
 # cmlb_create parameter validation against the ranges documented in cmlb.h
 # ---------------------------------------------------------------------------
-_Q_OF = {0: 9, 1: 27, 2: 37}
+_Q_OF = {0: 9, 1: 27, 2: 37, 3: 37, 4: 37, 5: 37, 6: 17, 7: 17, 8: 17, 9: 17}
 
 
 def _documented_valid(p):
@@ -153,14 +157,19 @@ def _documented_valid(p):
     lat, sto, mod, th = p["lattice"], p["storage"], p["model"], p["thermal"]
     if lat not in _Q_OF or sto not in (0, 1, 2, 3) or mod not in (0, 1, 2):
         return False
-    if (mod != 0 or th != 0) and lat != 2:          # raw MRT, regularised BGK, thermal: D2Q37 only
+    rule2d = lat >= 2                               # the 2D Hermite rules
+    if mod == 1 and lat != 2:                       # raw MRT: D2Q37 only
+        return False
+    if (mod == 2 or th != 0) and not rule2d:        # regularised BGK, thermal: the 2D rules
+        return False
+    if rule2d and lat != 2 and sto not in (0, 1):   # the other 2D rules: FP64 / FP32 storage
         return False
     nx, ny, nz = p["nx"], p["ny"], p["nz"]
     if min(nx, ny, nz) < 1 or max(nx, ny, nz) > 2 ** 20:
         return False
     if lat != 1 and nz != 1:
         return False
-    if lat == 2 and (nx < 3 or ny < 3):
+    if rule2d and (nx < 3 or ny < 3):
         return False
     n = nx * ny * nz
     if n >= 2 ** 32 or n * _Q_OF[lat] >= 2 ** 35:
@@ -181,10 +190,10 @@ def _param_blocks():
 
     @st.composite
     def block(draw):
-        lat = draw(st.integers(0, 2))
-        p = {"lattice": lat, "storage": draw(st.integers(0, 3)),
-             "model": draw(st.integers(0, 2)) if lat == 2 else 0,
-             "thermal": draw(st.integers(0, 1)) if lat == 2 else 0,
+        lat = draw(st.integers(0, 9))
+        p = {"lattice": lat, "storage": draw(st.integers(0, 3)) if lat <= 2 else draw(st.integers(0, 1)),
+             "model": draw(st.integers(0, 2)) if lat == 2 else (draw(st.sampled_from([0, 2])) if lat > 2 else 0),
+             "thermal": draw(st.integers(0, 1)) if lat >= 2 else 0,
              "nx": draw(st.sampled_from([3, 8, 64, 1000])), "ny": draw(st.sampled_from([3, 8, 64])),
              "nz": draw(st.sampled_from([1, 8, 64])) if lat == 1 else 1,
              "rho0": draw(st.sampled_from([1.0, 0.7])), "theta0": draw(st.sampled_from([1.0, 1.2])),
@@ -192,7 +201,7 @@ def _param_blocks():
              "scale": draw(st.lists(st.sampled_from([0.0, 0.0, 0.0, 2.0, 0.5]), min_size=37, max_size=37)),
              "reserved": 0}
         edits = {
-            "lattice": [-1, 3], "storage": [-1, 4], "model": [-1, 1, 2, 3], "thermal": [1, 2],
+            "lattice": [-1, 10], "storage": [-1, 2, 4], "model": [-1, 1, 2, 3], "thermal": [1, 2],
             "nx": [-1, 0, 1, 2, 2 ** 20, 2 ** 20 + 1, 2 ** 31], "ny": [0, 1, 2, 2 ** 20 + 1, 2 ** 31],
             "nz": [0, 2, 2 ** 20, 2 ** 20 + 1],
             "rho0": [0.0, -1.0, nan, inf], "theta0": [0.0, -2.0, nan, inf], "reserved": [1, -1],

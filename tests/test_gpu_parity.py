@@ -108,6 +108,50 @@ def test_one_step_parity_d2q37_models(cm, orc, model, thermal):
         assert err <= TOL[storage] * scale
 
 
+# The other minimal 2D rules of Fig. 2 (FP64 and FP32 storage, central moments)
+RULES = ["E9B", "E9C", "E9D", "E7A", "E7B", "E7C", "E7D"]
+
+
+@pytest.mark.parametrize("thermal", [True, False])
+@pytest.mark.parametrize("kind", RULES)
+def test_one_step_parity_rules(cm, orc, kind, thermal):
+    for storage in ("f64", "f32"):
+        for shape in ((13, 41), (4, 130)):   # ragged rows; padded rows of 130
+            err, scale = one_step_case(cm, orc, kind, storage, shape, seed=400 + len(kind) + shape[1],
+                                       thermal=thermal)
+            print(f"{kind} {shape} {storage} thermal={thermal}: {err:.3e} / {scale:.3e}")
+            assert err <= TOL[storage] * scale
+
+
+@pytest.mark.parametrize("kind", ["E9C", "E7A", "E7D"])
+def test_rules_thermal_waves_multistep(cm, orc, kind):
+    """Shear + thermal waves with a background flow, 40 steps, on 2D rules of
+    both degrees: moments against the oracle (FP64 1e-12, FP32 2e-6), and
+    mass, momentum and energy of the FP64 run conserved."""
+    shape, steps = (24, 30), 40
+    tau = {2: 0.6, 3: 0.64, 4: 1.0}
+    rho, u, th = inputs.waves2d(30, 24, shear_amp=0.01, thermal_amp=0.01, background=(0.0, 0.1))
+    cfg = orc.Cfg(lattice=kind, tau=tau, thermal=True)
+    S = orc.init_equilibrium(cfg, rho, u, th)
+    orc.run(cfg, S, steps)
+    o_rho, o_u, o_th = orc.moments(kind, S)
+    for storage, tol in (("f64", 1e-12), ("f32", 2e-6)):
+        ctx = cm.Context(kind, shape, storage=storage, thermal=True, tau=tau)
+        ctx.init_fields(rho, u, th)
+        g0 = ctx.reduce()
+        ctx.step(steps)
+        g1 = ctx.reduce()
+        g_rho, g_u, g_th = ctx.get_moments()
+        ctx.destroy()
+        err = max(np.abs(g_u - o_u).max(), np.abs(g_th - o_th).max(), np.abs(g_rho - o_rho).max())
+        print(f"{kind} waves {storage}: max err {err:.3e}")
+        assert err <= tol
+        if storage == "f64":
+            assert g1["mass"] == pytest.approx(g0["mass"], rel=1e-13)
+            assert np.abs(g1["momentum"] - g0["momentum"]).max() <= 1e-12 * g0["mass"]
+            assert g1["energy"] == pytest.approx(g0["energy"], rel=1e-12)
+
+
 def test_tgv_fp64_multistep(cm, orc):
     """D3Q27 TGV 24^3, tau = 0.6, 60 steps in FP64: max|du| <= 1e-12."""
     n, steps = 24, 60

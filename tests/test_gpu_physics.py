@@ -247,3 +247,18 @@ def test_tgv2d_d2q9_fp64_against_oracle(cm, orc):
     nu = (tau - 0.5) / 3.0
     print(f"D2Q9 64^2 FP64: decay rate {rate:.6e} vs 2 nu k^2 = {2 * nu * k * k:.6e}")
     assert rate == pytest.approx(2 * nu * k * k, rel=0.01)
+
+
+@pytest.mark.parametrize("lattice", ["E7A", "E7D", "E9C"])
+def test_fig2_rules_second_order(cm, lattice):
+    """Fig. 2 on rules of both degrees (theta0 = 1, nu = 0.1, kappa = 0.2):
+    the viscosity and diffusivity errors fall by about 4 when L doubles from
+    40 to 80 (second order), and stay below 3 % at L = 40."""
+    from paper_1808_04406_amd import studies
+    a = studies.convergence_run(lattice, 40, 0.1, 0.2, 1.0)
+    b = studies.convergence_run(lattice, 80, 0.1, 0.2, 1.0)
+    print(f"{lattice}: L=40 {a['viscous_err']:+.3e} {a['thermal_err']:+.3e}; "
+          f"L=80 {b['viscous_err']:+.3e} {b['thermal_err']:+.3e}")
+    for key in ("viscous_err", "thermal_err"):
+        assert abs(a[key]) < 0.03
+        assert 3.3 < a[key] / b[key] < 4.7
