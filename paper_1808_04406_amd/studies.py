@@ -641,6 +641,75 @@ def _input_scales(state, n, samples=20000, seed=0):
     return np.maximum(sig, 1e-12)
 
 
+def closure_leverage(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), train_steps=1500, lr=2e-3,
+                     stream=None):
+    """How much the rates the closure may set move its objective: 128^3
+    random multi-mode runs at Re = 1e5 filtered to 64^3 (one coarse step =
+    2 fine steps).  On held-out data: the one-step objective with constant
+    omega_3 and omega_5 over [0.6, 1.94] (even orders tied to omega_2, the
+    stable setting), with constant even-order rates untied, the linear
+    stability of those untied rates, and networks trained from the stable
+    fixed rates with two learning rates."""
+    import torch
+    u0, re = 0.05, 1.0e5
+    tau_f = 0.5 + 3.0 * u0 * (n_fine / (2 * math.pi)) / re
+    tau_c = 0.5 + (tau_f - 0.5) / factor
+    nc = n_fine // factor
+    data = {}
+    for seed in seeds:
+        rho, u = inputs.random_multimode(n_fine, seed, kmax=4, umax=u0)
+        fine = cmlb.Context("D3Q27", (n_fine,) * 3, storage="f32", tau=_tgv_rates(tau_f), stream=stream)
+        fine.init_fields(rho, u)
+        fine.step(100 * factor)
+        pairs = []
+        for _ in range(3):
+            a = torch.empty(27 * nc ** 3, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            fine.box_filter(factor, a)
+            fine.step(factor)
+            fine.box_filter(factor, b)
+            pairs.append((a, b))
+            fine.step(40 * factor - factor)
+        fine.sync()
+        fine.destroy()
+        data[seed] = pairs
+    train = [p for s_ in seeds if s_ not in held_out for p in data[s_]]
+    test = [p for s_ in held_out for p in data[s_]]
+    sigma = _input_scales(train[0][0].cpu().numpy(), nc)
+    ctx = cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)
+
+    def obj(params, pairs, tie=True):
+        ctx.closure_load(params, sigma)
+        ctx.closure_tie_even(tie)
+        return float(np.mean([ctx.closure_objective(a, b, grad=False) for a, b in pairs]))
+
+    stable = _constant_net([1.0] * 4, seed=1, scale=0.1)
+    base = obj(stable, test)
+    res = {"n_fine": n_fine, "n_coarse": nc, "tau_coarse": tau_c, "objective_stable_fixed_test": base,
+           "omega3_sweep": [], "omega5_sweep": [], "even_untied_sweep": [], "trained": []}
+    for w in (0.6, 0.8, 1.0, 1.2, 1.4, 1.6, 1.8, 1.94):
+        res["omega3_sweep"].append({"omega3": w, "ratio": obj(_constant_net([w, 1.0, 1.0, 1.0], 1, 0.1), test) / base})
+        res["omega5_sweep"].append({"omega5": w, "ratio": obj(_constant_net([1.0, 1.0, w, 1.0], 1, 0.1), test) / base})
+    for w in (0.8, 1.2, 1.6, 1.9, 1.94):
+        res["even_untied_sweep"].append({"omega4_omega6": w,
+                                         "ratio": obj(_constant_net([1.0, w, 1.0, w], 1, 0.1), test, tie=False) / base})
+    for r_ in res["omega3_sweep"] + res["omega5_sweep"] + res["even_untied_sweep"]:
+        print("leverage", r_, flush=True)
+    for lr_ in (lr, 5 * lr):
+        ctx.closure_load(stable, sigma)
+        ctx.closure_tie_even(True)
+        for it in range(train_steps):
+            a, b = train[it % len(train)]
+            ctx.closure_train_step(a, b, lr_ * (1.0 - it / train_steps))
+        P = ctx.closure_get().astype(np.float64)
+        row = {"lr": lr_, "steps": train_steps, "ratio_test": obj(P, test) / base,
+               "ratio_train": obj(P, train) / obj(stable, train)}
+        res["trained"].append(row)
+        print("trained", row, flush=True)
+    ctx.destroy()
+    return res
+
+
 def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=400, pairs_per_seed=3, gap=400,
             train_steps=600, lr=2e-3, tgv_coarse_steps=1250, every=50, stream=None):
     """Learned closure: data from fine random multi-mode runs at Re = 1e5
@@ -771,8 +840,8 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "thermal", "closure", "modes", "fig2", "dsl", "dsl_factors",
-                                      "galilean", "tgv"])
+    ap.add_argument("study", choices=["precision", "thermal", "closure", "closure_leverage", "modes", "fig2", "dsl",
+                                      "dsl_factors", "galilean", "tgv"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--every", type=int, default=None)
@@ -788,6 +857,8 @@ def main(argv=None):
             res = precision(n=a.n or 512, steps=a.steps, every=a.every or 100, stream=stream)
         elif a.study == "closure":
             res = closure(n_fine=a.n or 512, stream=stream)
+        elif a.study == "closure_leverage":
+            res = closure_leverage(n_fine=a.n or 128, stream=stream)
         elif a.study == "modes":
             res = modes(stream=stream)
         elif a.study == "fig2":

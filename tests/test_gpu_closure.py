@@ -197,14 +197,22 @@ def test_box_filter(cm, orc, shape):
     assert np.abs(out.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-8
 
 
-def test_trained_closure_beats_fixed_rates(cm):
+def test_trained_closure_against_fixed_rates(cm):
     """What training gains over the method without the network: 128^3
     random multi-mode runs at Re = 1e5, box-filtered 2^3 -> 64^3 (one coarse
-    step = 2 fine steps); the network starts at rate 1 for orders 3..6 (the
-    plain method's rates) with all four outputs free, trains 300 Adam steps on
-    seeds 0 and 1, and is evaluated on held-out seed 2.  Measured: held-out
-    objective 1.57x lower than the plain method's, within 0.2 % of the best
-    constant rate set (odd orders at 1, even orders at omega_2)."""
+    step = 2 fine steps).  The baseline is the plain method at the rates it
+    runs stably here: odd orders at 1, even orders at omega_2 (any other
+    even-order rate makes the linearised update grow as tau_2 -> 1/2, so the
+    network's even outputs are tied to omega_2).  The network starts at that
+    fixed set, trains 300 Adam steps on seeds 0 and 1 and is evaluated on
+    held-out seed 2.
+
+    Measured: it matches the fixed set to 0.1 % and does not beat it by a
+    useful margin: constant omega_3 or omega_5 anywhere in [0.6, 1.94] moves
+    the held-out objective by less than 1 % (the odd orders have almost no
+    leverage on this objective), so the rate 1 the plain method uses is
+    already near the best.  Against every order >= 3 at rate 1 (the unstable
+    set) the held-out objective is 1.5x lower."""
     import math
     import torch
     from paper_1808_04406_amd import studies
@@ -243,17 +251,21 @@ def test_trained_closure_beats_fixed_rates(cm):
             ctx.closure_tie_even(tie)
             return float(np.mean([ctx.closure_objective(a, b, grad=False) for a, b in pairs]))
 
-        plain = objective(rate1, test, False)
-        best_fixed = objective(stable, test, True)
-        ctx.closure_load(rate1, sigma)
-        ctx.closure_tie_even(False)
+        unstable = objective(rate1, test, False)
+        fixed = objective(stable, test, True)
+        sweep = [objective(studies._constant_net([w, 1.0, w, 1.0], seed=1, scale=0.1), test, True)
+                 for w in (0.6, 1.4, 1.94)]
+        ctx.closure_load(stable, sigma)
+        ctx.closure_tie_even(True)
         for it in range(300):
             a, b = train[it % len(train)]
             ctx.closure_train_step(a, b, 2e-3 * (1.0 - it / 300))
-        learned = objective(ctx.closure_get().astype(np.float64), test, False)
+        learned = objective(ctx.closure_get().astype(np.float64), test, True)
     finally:
         ctx.destroy()
-    print(f"held-out objective: plain (rates 1) {plain:.4e}, best constant rates {best_fixed:.4e}, "
-          f"trained network {learned:.4e} (gain {plain / learned:.3f})")
-    assert plain / learned > 1.3
-    assert learned < 1.02 * best_fixed
+    print(f"held-out objective: every order >= 3 at 1 {unstable:.4e}, fixed odd 1 / even omega_2 {fixed:.4e}, "
+          f"trained network {learned:.4e} (ratio to the fixed set {learned / fixed:.5f}); constant odd rates "
+          f"0.6 / 1.4 / 1.94: {', '.join(f'{v / fixed:.4f}' for v in sweep)}")
+    assert learned <= 1.001 * fixed             # training keeps at least the fixed set's quality
+    assert unstable / learned > 1.3             # and gains over the unstable all-ones set
+    assert all(0.99 < v / fixed < 1.03 for v in sweep)   # the odd orders barely move the objective
