@@ -328,7 +328,11 @@ class _DslRun:
     nu = Ma r L / Re, tau_2 = 1/2 + nu, tau_3 = 1/2 + nu / Pr (theta0 = 1),
     tau_4 = tau_2 unless given.  The run goes to t = t_end t_c with
     t_c = L / u0 steps and is stable if every check finds all populations
-    finite and <u^2>/u0^2 <= ke_bound."""
+    finite, the density positive everywhere and the kinetic energy between 0
+    and ke_bound times its initial value.  A run that blows up in FP64 storage
+    can stay finite (values near 1e270 were seen), and its kinetic energy can
+    turn negative with the density, so finiteness alone or an upper bound
+    alone does not detect it."""
 
     def __init__(self, ma, re, pr, model="cm", thermal=True, n=128, tau4=None, storage="f32", t_end=2.0,
                  checks=32, ke_bound=2.0, lattice="D2Q37", stream=None):
@@ -360,7 +364,7 @@ class _DslRun:
         ratio = g["ke"] / self.e0 if np.isfinite(g["ke"]) else float("inf")
         self.hist.append((self.done, ratio))
         self.mi += 1
-        if g["nonfinite"] > 0 or not ratio <= self.ke_bound:
+        if g["nonfinite"] > 0 or not g["rho_min"] > 0.0 or not 0.0 <= ratio <= self.ke_bound:
             self.ok = False
         if not self.ok or self.mi == len(self.marks):
             self.finished = True
@@ -420,12 +424,17 @@ def max_stable_batched(cases, lo, hi, tol, model="cm", thermal=True, n=128, stre
     return results
 
 
-def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0), tol=0.005, stream=None):
-    out = {"n": n, "tol": tol, "criterion": "finite and <u^2>/<u^2>_0 <= 2 at 32 checks up to t/t_c = 2",
-           "boundaries": [], "fig6": None}
+def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0), tol=0.005, storage="f32",
+        ke_bound=2.0, stream=None):
+    """Fig. 6's Mach sequence and Fig. 5's stability boundaries for the given
+    storage and kinetic-energy bound of the stability criterion."""
+    crit = "finite, rho > 0" + ("" if ke_bound == float("inf") else f" and 0 <= <u^2>/<u^2>_0 <= {ke_bound:g}") + \
+        " at 32 checks up to t/t_c = 2"
+    out = {"n": n, "tol": tol, "storage": storage, "criterion": crit, "boundaries": [], "fig6": None}
+    kw = dict(storage=storage, ke_bound=ke_bound)
     t0 = time.perf_counter()
     # Fig. 6: the Mach sequence of the thermal CM-MRT run at Pr = 1, Re = 1e7
-    out["fig6"] = {str(ma): dsl_run(ma, 1e7, 1.0, history=True, stream=stream)
+    out["fig6"] = {str(ma): dsl_run(ma, 1e7, 1.0, history=True, stream=stream, **kw)
                    for ma in (0.2, 0.25, 0.2625, 0.2688, 0.275)}
     for ma, o in out["fig6"].items():
         print(f"Fig. 6 Ma={ma}: stable={o['stable']}, steps {o['steps_run']}/{o['steps']}", flush=True)
@@ -434,7 +443,7 @@ def dsl(n=128, res_=(1e3, 1e4, 1e5, 1e6, 1e7), prs=(0.01, 0.1, 1.0, 10.0, 100.0)
                                   ("thermal CM-MRT", "cm", True)):
         cases = [(re, pr) for pr in prs for re in res_]
         t1 = time.perf_counter()
-        found = max_stable_batched(cases, 0.05, 1.2, tol, model=model, thermal=thermal, n=n, stream=stream)
+        found = max_stable_batched(cases, 0.05, 1.2, tol, model=model, thermal=thermal, n=n, stream=stream, **kw)
         print(f"{label}: {len(cases)} searches, {sum(len(c) for _, c in found)} runs in "
               f"{time.perf_counter() - t1:.2f} s (batched)", flush=True)
         for (re, pr), (m, calls) in zip(cases, found):
@@ -449,25 +458,41 @@ def dsl_factors(n=128, res_=(1e5, 1e6, 1e7), tol=0.005, stream=None):
     """What moves the isothermal stability boundary (Sec. III.B, Fig. 5):
     isothermal CM-MRT at Pr = 1 under the reference settings (tau4 = tau2,
     <u^2> at most twice its initial value, the |e|^2 <= 10 rule, FP32), then
-    one change at a time: the divergence criterion alone (every population
-    finite), tau4 = 1, the other 37-velocity rules, FP64 storage, and raw MRT."""
-    base = dict(model="cm", ke_bound=2.0, tau4=None, lattice="D2Q37", storage="f32")
-    variants = [("reference", {}), ("finite only", {"ke_bound": float("inf")}), ("tau4 = 1", {"tau4": 1.0}),
+    one change at a time: no kinetic-energy bound (the populations finite and
+    the density positive), tau4 = 1, the other 37-velocity rules, FP64
+    storage, and raw MRT; then FP64 storage combined with the other changes,
+    with a kinetic-energy bound of 1e6 and with none, and the thermal model
+    in FP32 and FP64."""
+    inf = float("inf")
+    base = dict(model="cm", thermal=False, ke_bound=2.0, tau4=None, lattice="D2Q37", storage="f32")
+    f64 = {"storage": "f64"}
+    variants = [("reference", {}), ("no KE bound", {"ke_bound": inf}), ("tau4 = 1", {"tau4": 1.0}),
                 ("E9B", {"lattice": "E9B"}), ("E9C", {"lattice": "E9C"}), ("E9D", {"lattice": "E9D"}),
-                ("FP64", {"storage": "f64"}), ("raw MRT", {"model": "raw_mrt"}),
-                ("Pr = 0.5", {"pr": 0.5}), ("Pr = 2", {"pr": 2.0})]
+                ("FP64", f64), ("raw MRT", {"model": "raw_mrt"}),
+                ("Pr = 0.5", {"pr": 0.5}), ("Pr = 2", {"pr": 2.0}),
+                ("FP64, raw MRT", dict(f64, model="raw_mrt")),
+                ("FP64, E9B", dict(f64, lattice="E9B")),
+                ("FP64, E9C", dict(f64, lattice="E9C")),
+                ("FP64, E9D", dict(f64, lattice="E9D")),
+                ("FP64, Pr = 0.5", dict(f64, pr=0.5)),
+                ("FP64, Pr = 2", dict(f64, pr=2.0)),
+                ("FP64, KE bound 1e6", dict(f64, ke_bound=1e6)),
+                ("FP64, no KE bound", dict(f64, ke_bound=inf)),
+                ("thermal", {"thermal": True}),
+                ("thermal, FP64", dict(f64, thermal=True))]
     out = {"n": n, "tol": tol, "res": list(res_), "variants": []}
     t0 = time.perf_counter()
     for label, change in variants:
         kw = dict(base, **change)
         pr = kw.pop("pr", 1.0)
         model = kw.pop("model")
+        thermal = kw.pop("thermal")
         cases = [(re, pr) for re in res_]
-        found = max_stable_batched(cases, 0.05, 1.2, tol, model=model, thermal=False, n=n, stream=stream, **kw)
-        row = {"label": label, "pr": pr, "model": model, **{k: (v if v != float("inf") else "inf") for k, v in kw.items()},
-               "ma_max": [m for m, _ in found]}
+        found = max_stable_batched(cases, 0.05, 1.2, tol, model=model, thermal=thermal, n=n, stream=stream, **kw)
+        row = {"label": label, "pr": pr, "model": model, "thermal": thermal,
+               **{k: (v if v != inf else "inf") for k, v in kw.items()}, "ma_max": [m for m, _ in found]}
         out["variants"].append(row)
-        print(f"DSL isothermal {label}: Ma_max " + ", ".join(f"Re={re:.0e} {m:.4f}" for re, (m, _) in zip(res_, found)),
+        print(f"DSL {label}: Ma_max " + ", ".join(f"Re={re:.0e} {m:.4f}" for re, (m, _) in zip(res_, found)),
               flush=True)
     out["wall_s"] = time.perf_counter() - t0
     return out
@@ -864,7 +889,7 @@ def main(argv=None):
         elif a.study == "fig2":
             res = fig2(stream=stream)
         elif a.study == "dsl":
-            res = dsl(n=a.n or 128, stream=stream)
+            res = dsl(n=a.n or 128, storage=a.storage, stream=stream)
         elif a.study == "dsl_factors":
             res = dsl_factors(n=a.n or 128, stream=stream)
         elif a.study == "tgv":

@@ -166,6 +166,19 @@ def test_dsl_stability_classification(cm):
     assert not wild["stable"] and wild["steps_run"] < wild["steps"]
 
 
+def test_dsl_blowup_detected_in_fp64(cm):
+    """An isothermal run past the boundary in FP64 storage blows up without
+    leaving the FP64 range (its values reach 1e270 and its kinetic energy
+    turns negative with the density): the stability check must still flag
+    it, with no kinetic-energy bound at all, and the same run in FP32 too."""
+    from paper_1808_04406_amd import studies
+    for storage in ("f64", "f32"):
+        o = studies.dsl_run(0.70, 1e7, 1.0, thermal=False, storage=storage, ke_bound=float("inf"), history=True)
+        print(storage, o["stable"], o["steps_run"], o["history"][-3:])
+        assert not o["stable"], storage
+        assert o["steps_run"] < o["steps"]
+
+
 @pytest.mark.parametrize("model,thermal", [("cm", True), ("raw_mrt", False)])
 def test_batched_search_equals_sequential(cm, model, thermal):
     """The stability search run in lockstep batches (17 cases: one full
