@@ -191,9 +191,10 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--steps-per-launch", type=int, default=2, choices=[1, 2, 3],
                     help="2: pairs of steps in one launch where supported (D3Q27 FP32/FP64, D2Q37 FP32; default); "
-                         "1: one launch per step")
+                         "1: one launch per step; 3: as 2, with the D2Q37 kernel that accumulates the second "
+                         "step's moments row by row (equal to two single steps to FP32 rounding, not bitwise)")
     ap.add_argument("--workload", default="tgv256_f32", choices=sorted(WORKLOADS),
                     help="default: the D3Q27 256^3 FP32 Taylor-Green benchmark; others report the precision "
                          "form and the thermal lattice with the same JSON fields")
@@ -287,7 +288,7 @@ def run(torch, cmlb, inputs, stream, args):
     # pairs of steps run as one launch (intermediate state on chip): D3Q27
     # FP32 and FP64, D2Q37 FP32
     fused = (storage == "f32" or (lattice == "D3Q27" and storage == "f64")) and not closure \
-        and args.steps_per_launch == 2
+        and args.steps_per_launch >= 2
     ctx.set_step_fusion(args.steps_per_launch)
 
     # Achievable ceilings, measured before the steps: torch's device copy
@@ -348,7 +349,8 @@ def run(torch, cmlb, inputs, stream, args):
     if fused and lattice == "D3Q27":
         kernel = "k_step2_tp<%s>" % STORAGE_TAG[storage]
     elif fused:
-        kernel = "k_step2_d37<%s>" % MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")]
+        kernel = "k_step2_d37%s<%s>" % ("_acc" if args.steps_per_launch == 3 else "",
+                                        MODEL_TAG[WORKLOAD_MODEL.get(args.workload, "cm")])
     elif lattice == "D3Q27":
         kernel = "k_step_tp<3, %s>" % STORAGE_TAG[storage]
     else:

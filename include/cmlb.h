@@ -233,8 +233,16 @@ int cmlb_step(cmlb_ctx *ctx, int64_t n);
  *                cost model of the grid's launch shape expects two single
  *                launches to be faster (small grids);
  *   1            one kernel per step;
- *   2            two steps per launch wherever supported.
- * All give bitwise the same populations.  CMLB_EINVAL for other values. */
+ *   2            two steps per launch wherever supported;
+ *   3            as 2, but D2Q37 runs the kernel that folds each first-step
+ *                row into the moments of the second-step rows it feeds
+ *                (one row in LDS, two waves per SIMD).  Its moment sums run
+ *                in another order, so it equals two single steps to FP32
+ *                rounding, not bitwise; on one MI355X it is no faster
+ *                (1024^2: 21,500 against 21,700 MLUPS; 2048^2: 23,000
+ *                against 24,600).
+ * Modes 0, 1 and 2 give bitwise the same populations.  CMLB_EINVAL for
+ * other values. */
 int cmlb_set_step_fusion(cmlb_ctx *ctx, int steps_per_launch);
 
 /* Replay the steps of cmlb_step from a HIP graph of `steps` steps (a

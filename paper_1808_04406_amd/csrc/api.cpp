@@ -181,7 +181,7 @@ struct cmlb_ctx {
     double omega[8] = {};
     float s[37] = {}, inv_s[37] = {};
     int64_t steps = 0;
-    int fuse = 0;                 // 0 automatic, 1 one step per launch, 2 two where supported
+    int fuse = 0;                 // 0 automatic, 1 one step per launch, 2 two where supported, 3 two, D2Q37 rows accumulated
     // HIP graph of graph_steps steps (0: launch eagerly), captured from the
     // buffer parity graph_cur; replays leave the parity unchanged
     int graph_steps = 0;
@@ -521,7 +521,7 @@ static int enqueue_steps(cmlb_ctx* c, int64_t n) {
         if (c->closure_on) {
             launch_step_closure(a, c->cl_net, c->stream);
         } else if (c->fuse != 1 && n - k >= 2 &&
-                   launch_step2(c->p.lattice, c->p.storage, c->p.model, a, c->fuse == 2, c->stream) == 0) {
+                   launch_step2(c->p.lattice, c->p.storage, c->p.model, a, c->fuse, c->stream) == 0) {
             adv = 2;
         } else if (launch_step(c->p.lattice, c->p.storage, c->p.model, a, c->stream)) {
             return fail(c, CMLB_EINVAL, "unsupported configuration");
@@ -669,8 +669,8 @@ int cmlb_set_graph_steps(cmlb_ctx* c, int steps) {
 
 int cmlb_set_step_fusion(cmlb_ctx* c, int steps_per_launch) {
     if (!c) return CMLB_EINVAL;
-    if (steps_per_launch < 0 || steps_per_launch > 2)
-        return fail(c, CMLB_EINVAL, "steps per launch must be 0 (automatic), 1 or 2");
+    if (steps_per_launch < 0 || steps_per_launch > 3)
+        return fail(c, CMLB_EINVAL, "steps per launch must be 0 (automatic), 1, 2 or 3");
     c->fuse = steps_per_launch;
     graph_drop(c);
     return CMLB_OK;

@@ -239,13 +239,13 @@ __device__ __forceinline__ void h2_reconstruct(R (&h)[H2<LAT>::Q], const Tri<R>&
     });
 }
 
-// Full collision of one node (in place on deviation populations).
+// Collision of one node from the lattice moments M of its deviation
+// populations (step 1 done), writing the post-collision deviations to h.
 template <int LAT, int MODEL, class R>
-__device__ __forceinline__ void h2_collide(R (&h)[H2<LAT>::Q], R rho0, const R* om, R r, const R (&wc)[8],
-                                           bool thermal, R theta0) {
+__device__ __forceinline__ void h2_collide_moments(Tri<R> M, R (&h)[H2<LAT>::Q], R rho0, const R* om, R r,
+                                                   const R (&wc)[8], bool thermal, R theta0) {
     constexpr int N = H2<LAT>::N;
     static_assert(MODEL == kCM || N == 4, "raw-moment MRT and regularised BGK are built for the order-4 rules");
-    Tri<R> M = h2_moments<LAT, R>(h);
     const R rp[5] = {R(1), r, r * r, r * r * r, (r * r) * (r * r)};
     static_for<0, 5>([&](auto K) {
         static_for<0, 5>([&](auto L) {
@@ -355,6 +355,13 @@ __device__ __forceinline__ void h2_collide(R (&h)[H2<LAT>::Q], R rho0, const R* 
     }
     const Tri<R> C = h2_poly_from_raw<N, R>(mstar, r);
     h2_reconstruct<LAT, R>(h, C, wc);
+}
+
+// Full collision of one node (in place on deviation populations).
+template <int LAT, int MODEL, class R>
+__device__ __forceinline__ void h2_collide(R (&h)[H2<LAT>::Q], R rho0, const R* om, R r, const R (&wc)[8],
+                                           bool thermal, R theta0) {
+    h2_collide_moments<LAT, MODEL, R>(h2_moments<LAT, R>(h), h, rho0, om, r, wc, thermal, theta0);
 }
 
 // Deviation equilibrium populations: the order-N Hermite equilibrium has the

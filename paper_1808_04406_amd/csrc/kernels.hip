@@ -354,9 +354,9 @@ static dim3 flat_grid(uint64_t n) {
     return dim3((uint32_t)b);
 }
 
-int launch_step2(int lattice, int storage, int model, const StepArgs& a, bool force, hipStream_t s) {
-    if (lattice == kD2Q37) return launch_step2_d37(storage, model, a, force, s);
-    if (lattice == kD2Q9 || lattice == kD3Q27) return launch_step2_tp(lattice, storage, a, force, s);
+int launch_step2(int lattice, int storage, int model, const StepArgs& a, int mode, hipStream_t s) {
+    if (lattice == kD2Q37) return launch_step2_d37(storage, model, a, mode, s);
+    if (lattice == kD2Q9 || lattice == kD3Q27) return launch_step2_tp(lattice, storage, a, mode != kFuseAuto, s);
     return -1;
 }
 

@@ -38,14 +38,19 @@ int launch_step_h2(int lattice, int storage, int model, const StepArgs& a, hipSt
 int launch_step_batch(int lattice, int storage, int model, const BatchArgs& A, int count, hipStream_t s);
 int launch_step_tp_batch(int lattice, int storage, const BatchArgs& A, int count, hipStream_t s);
 int launch_step_d37_batch(int storage, int model, const BatchArgs& A, int count, hipStream_t s);
+// Steps-per-launch modes of cmlb_set_step_fusion.
+enum { kFuseAuto = 0, kFuseOne = 1, kFuseTwo = 2, kFuseTwoAcc = 3 };
 // Two steps in one launch (step_tp2.hip, D3Q27 with FP32 storage); -1 if the
 // configuration is not supported or, unless force is set, if two single-step
 // launches are expected to be faster.
 int launch_step2_tp(int lattice, int storage, const StepArgs& a, bool force, hipStream_t s);
-// Two steps in one launch on D2Q37 with FP32 storage (step2_d37.hip); same contract.
-int launch_step2_d37(int storage, int model, const StepArgs& a, bool force, hipStream_t s);
-// Two steps in one launch where supported (either of the above); same contract.
-int launch_step2(int lattice, int storage, int model, const StepArgs& a, bool force, hipStream_t s);
+// Two steps in one launch on D2Q37 with FP32 storage (step2_d37.hip): mode
+// kFuseTwoAcc runs the row-accumulating kernel, kFuseTwo the bitwise one,
+// kFuseAuto the bitwise one unless two single steps are expected faster.
+int launch_step2_d37(int storage, int model, const StepArgs& a, int mode, hipStream_t s);
+// Two steps in one launch where supported (either of the above); mode as
+// above (kFuseTwoAcc is kFuseTwo on the tensor-product lattices).
+int launch_step2(int lattice, int storage, int model, const StepArgs& a, int mode, hipStream_t s);
 int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_codec(int lattice, int storage, bool decode, void* stor, double* full, const StepArgs& a,

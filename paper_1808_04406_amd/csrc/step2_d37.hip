@@ -230,6 +230,168 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
 }
 
 // ---------------------------------------------------------------------------
+// Two steps per launch, the second step's moments accumulated row by row
+// ---------------------------------------------------------------------------
+// The collision depends on the pulled populations only through their 15
+// lattice moments M_kl (k + l <= 4).  Population i of first-step row f is
+// pulled by second-step row f + e_y,i, so each first-step row, once in LDS,
+// is folded into the moments of the seven second-step rows f - 3..f + 3
+// that it feeds; a thread keeps those seven partial moment sets in
+// registers, and row f - 3 is complete after row f has been folded in.  LDS
+// then holds one first-step row (double-buffered: 37,888 bytes) instead of
+// the 148-row ring, four workgroups share a CU, and each SIMD runs two waves.
+// The moments are summed in another order than in the single-step kernel,
+// so the result agrees with two single steps to FP32 rounding, not bitwise.
+constexpr int kD2AccLds = 2 * 37 * kD2Threads;   // floats
+constexpr int kD2AccPerCU = (160 * 1024) / (kD2AccLds * 4);
+constexpr uint32_t kD2AccSlots = 256u * kD2AccPerCU;
+static_assert(kD2AccPerCU == 4, "four workgroups of two waves per CU");
+
+template <int MODEL, bool PAD>
+__global__ __launch_bounds__(kD2Threads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_step2_d37_acc(Step2D37Args A) {
+    __shared__ float lds[kD2AccLds];
+    const StepArgs& a = A.a;
+    const uint32_t nx = a.g.nx, ny = a.g.ny;
+    uint32_t b = blockIdx.x;
+    if (gridDim.x % 8 == 0) b = (b % 8) * (gridDim.x / 8) + b / 8;
+    const uint32_t bx = b % A.ntx, by = b / A.ntx;
+    const uint32_t tx = A.tx;
+    const uint32_t x0 = bx * tx, y0 = by * A.cy;
+    const uint32_t yend = min(y0 + A.cy, ny);
+    const int t = threadIdx.x;
+    const uint32_t plane_b = (uint32_t)a.g.plane * (uint32_t)sizeof(float);
+    const uint32_t rowb = (PAD ? a.pitch : nx) * (uint32_t)sizeof(float);
+    const int nbytes = (int)(37u * plane_b);
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.src), 0, nbytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc(a.dst, 0, nbytes, kBufferWord3);
+
+    // First step: region column t, global x = x0 + t - 3 (periodic); xo[e + 3]
+    // is the byte offset of column x - e.
+    const bool act1 = (uint32_t)t < tx + 6;
+    const uint32_t gx = (x0 + (uint32_t)t + nx - 3) % nx;
+    uint32_t xo[7];
+    static_for<0, 7>([&](auto E) {
+        constexpr int e = decltype(E)::value - 3;
+        xo[e + 3] = wrap_sub(gx, e, nx) * (uint32_t)sizeof(float);
+    });
+    // Second step: segment column t.
+    const bool in2 = (uint32_t)t < tx;
+    const uint32_t gx2 = x0 + (uint32_t)t;
+    const bool act2 = in2 && gx2 < nx;
+    const uint32_t xst = gx2 * (uint32_t)sizeof(float);
+
+    float om[8], wc[8];
+    static_for<0, 8>([&](auto N) {
+        om[decltype(N)::value] = (float)a.omega[decltype(N)::value];
+        wc[decltype(N)::value] = (float)a.wcls[decltype(N)::value];
+    });
+    const float rho0 = (float)a.rho0, r = (float)a.r, theta0 = (float)a.theta0;
+    const bool thermal = a.thermal != 0;
+
+    auto load_state = [&](float (&h)[37], const uint32_t (&srow)[7]) {
+        static_for<0, 37>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            h[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                rsrc, (int)xo[kTab37.ex[i] + 3], (int)(srow[kTab37.ey[i] + 3] + (uint32_t)i * plane_b), 0));
+        });
+    };
+    const uint32_t wrapb = ny * rowb;
+    auto next_row = [&](uint32_t (&srow)[7]) {
+        static_for<0, 7>([&](auto E) {
+            constexpr int e = decltype(E)::value;
+            const uint32_t v = srow[e] + rowb;
+            srow[e] = v == wrapb ? 0u : v;
+        });
+    };
+
+    // acc[s]: partial moments of second-step row f - 3 + s, f the first-step
+    // row of the current iteration.
+    Tri<float> acc[7];
+    static_for<0, 7>([&](auto S) {
+        static_for<0, 5>([&](auto K) {
+            static_for<0, 5 - decltype(K)::value>([&](auto L) {
+                acc[decltype(S)::value].v[decltype(K)::value][decltype(L)::value] = 0.0f;
+            });
+        });
+    });
+
+    float h[37];
+    uint32_t srow[7];
+    const uint32_t f0 = (y0 + ny - 3) % ny;
+    static_for<0, 7>([&](auto E) {
+        constexpr int e = decltype(E)::value - 3;
+        srow[e + 3] = wrap_sub(f0, e, ny) * rowb;
+    });
+    if (act1) load_state(h, srow);
+    const int J = (int)(yend - y0) + 5;   // iterations j = 0..J: first step of row y0 - 3 + j
+    for (int j = 0; j <= J; ++j) {
+        float* buf = lds + (j & 1) * (37 * kD2Threads);
+        if (act1) {
+            h2_collide<kD2Q37, MODEL, float>(h, rho0, om, r, wc, thermal, theta0);
+            static_for<0, 37>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                buf[i * kD2Threads + t] = h[i];
+            });
+        }
+        if (j < J) {   // the rows stay workgroup-uniform (scalar) outside the branch
+            next_row(srow);
+            if (act1) load_state(h, srow);
+        }
+        __syncthreads();
+        if (in2) {
+            // fold this row into the seven rows it feeds: population i goes to
+            // slot e_y,i + 3 with weights e_x^k e_y^l
+            static_for<0, 7>([&](auto G) {
+                constexpr int e = decltype(G)::value - 3;
+                float P[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // sum over the group of v e_x^k
+                static_for<0, 37>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    if constexpr (kTab37.ey[i] == e) {
+                        constexpr int ex = kTab37.ex[i];
+                        const float v = buf[i * kD2Threads + t + 3 - ex];
+                        static_for<0, 5>([&](auto K) {
+                            constexpr int k = decltype(K)::value;
+                            constexpr int c = ipow_c(ex, k);
+                            if constexpr (c == 1) P[k] += v;
+                            else if constexpr (c == -1) P[k] -= v;
+                            else if constexpr (c != 0) P[k] += float(c) * v;
+                        });
+                    }
+                });
+                static_for<0, 5>([&](auto K) {
+                    static_for<0, 5 - decltype(K)::value>([&](auto L) {
+                        constexpr int k = decltype(K)::value, l = decltype(L)::value;
+                        constexpr int c = ipow_c(e, l);
+                        if constexpr (c == 1) acc[e + 3].v[k][l] += P[k];
+                        else if constexpr (c == -1) acc[e + 3].v[k][l] -= P[k];
+                        else if constexpr (c != 0) acc[e + 3].v[k][l] += float(c) * P[k];
+                    });
+                });
+            });
+            if (j >= 6) {
+                float g2[37];
+                h2_collide_moments<kD2Q37, MODEL, float>(acc[0], g2, rho0, om, r, wc, thermal, theta0);
+                if (act2) {
+                    const uint32_t so = (y0 + (uint32_t)j - 6) * rowb;
+                    static_for<0, 37>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, g2[i]), rdst, (int)xst,
+                                                              (int)(so + (uint32_t)i * plane_b), 0);
+                    });
+                }
+            }
+            static_for<0, 6>([&](auto S) { acc[decltype(S)::value] = acc[decltype(S)::value + 1]; });
+            static_for<0, 5>([&](auto K) {
+                static_for<0, 5 - decltype(K)::value>([&](auto L) {
+                    acc[6].v[decltype(K)::value][decltype(L)::value] = 0.0f;
+                });
+            });
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launcher
 // ---------------------------------------------------------------------------
 // kD2PerCU workgroups share a CU's LDS, so a launch of B workgroups runs in
@@ -243,6 +405,10 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
 // measured: single steps up to 512^2, two steps per launch from 640^2 on.
 constexpr double kD2ItUs = 4.3, kD2LaunchUs = 3.0, kD2StepPsPerNode = 58.0;
 
+// The row-accumulating kernel runs four workgroups per CU (kD2AccSlots per
+// round); an iteration of a full round takes kD2AccItUs.
+constexpr double kD2AccItUs = 6.0;
+
 namespace {
 struct Step2D37Plan {
     Step2D37Args A;
@@ -250,7 +416,10 @@ struct Step2D37Plan {
     double cost_us;
 };
 
-Step2D37Plan step2_d37_plan(const StepArgs& a) {
+// Segments of at most kD2MaxTX columns, and the row chunking with the lowest
+// modelled time for `slots` workgroups per round.
+template <uint32_t kSlots, int kTag>
+Step2D37Plan step2_d37_plan(const StepArgs& a, double it_us) {
     thread_local uint32_t key[2] = {0, 0};
     thread_local Step2D37Plan last;
     if (key[0] == a.g.nx && key[1] == a.g.ny) {
@@ -267,8 +436,8 @@ Step2D37Plan step2_d37_plan(const StepArgs& a) {
     for (uint32_t nc = 1; nc <= a.g.ny && nc <= 8192; ++nc) {
         const uint32_t cy = (a.g.ny + nc - 1) / nc;
         if ((a.g.ny + cy - 1) / cy != nc) continue;   // the same chunking as a smaller count
-        const double rounds = (double)(((uint64_t)P.A.ntx * nc + kD2Slots - 1) / kD2Slots);
-        const double tm = rounds * (cy + 3) * kD2ItUs;   // six half-cost lead-in iterations
+        const double rounds = (double)(((uint64_t)P.A.ntx * nc + kSlots - 1) / kSlots);
+        const double tm = rounds * (cy + 3) * it_us;   // six half-cost lead-in iterations
         if (nc == 1 || tm < best) { best = tm; best_cy = cy; }
     }
     P.A.cy = best_cy;
@@ -280,11 +449,26 @@ Step2D37Plan step2_d37_plan(const StepArgs& a) {
 }
 }  // namespace
 
-int launch_step2_d37(int storage, int model, const StepArgs& a, bool force, hipStream_t s) {
+static int launch_step2_d37_acc(int model, const StepArgs& a, hipStream_t s) {
+    const Step2D37Plan P = step2_d37_plan<kD2AccSlots, 1>(a, kD2AccItUs);
+    const bool raw = (model == kRawMRT), pad = (a.pitch != a.g.nx);
+    if (raw) {
+        if (pad) hipLaunchKernelGGL((k_step2_d37_acc<kRawMRT, true>), dim3(P.blocks), dim3(kD2Threads), 0, s, P.A);
+        else hipLaunchKernelGGL((k_step2_d37_acc<kRawMRT, false>), dim3(P.blocks), dim3(kD2Threads), 0, s, P.A);
+    } else {
+        if (pad) hipLaunchKernelGGL((k_step2_d37_acc<kCM, true>), dim3(P.blocks), dim3(kD2Threads), 0, s, P.A);
+        else hipLaunchKernelGGL((k_step2_d37_acc<kCM, false>), dim3(P.blocks), dim3(kD2Threads), 0, s, P.A);
+    }
+    return 0;
+}
+
+int launch_step2_d37(int storage, int model, const StepArgs& a, int mode, hipStream_t s) {
     if (storage != kF32) return -1;
-    // the kernel addresses the whole state (37 planes) with 32-bit offsets
+    // the kernels address the whole state (37 planes) with 32-bit offsets
     if (37ull * a.g.plane * 4 >= (1ull << 32)) return -1;
-    const Step2D37Plan P = step2_d37_plan(a);
+    if (mode == kFuseTwoAcc) return launch_step2_d37_acc(model, a, s);
+    const bool force = (mode == kFuseTwo);
+    const Step2D37Plan P = step2_d37_plan<kD2Slots, 0>(a, kD2ItUs);
     if (!force) {
         const double single_us = kD2LaunchUs + (double)nodes_of(a.g) * kD2StepPsPerNode * 1e-6;
         if (P.cost_us >= 2.0 * single_us) return -1;

@@ -109,7 +109,8 @@ def test_precision_form_512_two_steps_sampled(cm, orc, tgv512, storage):
     assert g["nonfinite"] == 0
 
 
-def test_thermal_waves_1024_two_steps(cm, orc):
+@pytest.mark.parametrize("fuse", [0, 3])   # automatic (the bitwise two-step kernel), row-accumulating kernel
+def test_thermal_waves_1024_two_steps(cm, orc, fuse):
     n, kx, amp, pr, tau2 = 1024, 4, 0.01, 7.0, 0.6
     r = cm.lattice_info("D2Q37")["r"]
     tau = {2: tau2, 3: 0.5 + (tau2 - 0.5) / pr, 4: tau2}
@@ -119,6 +120,7 @@ def test_thermal_waves_1024_two_steps(cm, orc):
     w = orc.lattice("D2Q37")["w"][:, None, None]
     ctx = cm.Context("D2Q37", (n, n), storage="f32", thermal=True, tau=tau)
     try:
+        ctx.set_step_fusion(fuse)
         ctx.set_populations(S)
         ctx.step(2)
         got = ctx.get_populations()
@@ -131,15 +133,16 @@ def test_thermal_waves_1024_two_steps(cm, orc):
             ref = quantise(ref - w, "f32") + w
     err = np.abs(got - ref).max()
     dev = np.abs(ref - w).max()
-    print(f"D2Q37 1024^2 thermal waves, two steps: max|df| = {err:.3e} (deviation scale {dev:.3e})")
+    print(f"D2Q37 1024^2 thermal waves, two steps (mode {fuse}): max|df| = {err:.3e} (deviation scale {dev:.3e})")
     assert err <= 2 * TOL["f32"] * dev
 
 
 def test_thermal_two_step_past_2gib(cm, orc):
     """D2Q37 4096^2 FP32 (a 2.48 GB state, so population offsets pass 2^31
-    in the two-step kernel's 32-bit buffer addressing): two steps in one
-    launch equal two single-step launches bitwise, compared on the device;
-    a few nodes are also checked against the oracle's step."""
+    in the two-step kernels' 32-bit buffer addressing): two steps in one
+    launch equal two single-step launches bitwise, compared on the device,
+    and the row-accumulating kernel equals them to FP32 rounding; a few
+    nodes are also checked against the oracle's step."""
     import torch
     n, amp = 4096, 0.01
     r = cm.lattice_info("D2Q37")["r"]
@@ -148,7 +151,7 @@ def test_thermal_two_step_past_2gib(cm, orc):
     nbytes = cm.state_bytes("D2Q37", (n, n), "f32")
     assert nbytes >= 2 ** 31
     out = []
-    for fuse in (1, 2):
+    for fuse in (1, 2, 3):
         ctx = cm.Context("D2Q37", (n, n), storage="f32", thermal=True, tau=tau)
         try:
             ctx.set_step_fusion(fuse)
@@ -161,6 +164,15 @@ def test_thermal_two_step_past_2gib(cm, orc):
         finally:
             ctx.destroy()
     assert torch.equal(out[0], out[1])
+    # the row-accumulating kernel (plane offsets past 2^31 in its scalar
+    # offsets) within FP32 rounding of two single steps, every node
+    s1 = out[0].view(torch.float32).view(37, -1)
+    s3 = out[2].view(torch.float32).view(37, -1)
+    d13 = (s3 - s1).abs().max().item()
+    dev1 = s1.abs().max().item()   # the stored values are deviations from w rho0
+    print(f"D2Q37 4096^2 row-accumulating kernel vs single steps: {d13:.3e} (deviation scale {dev1:.3e})")
+    assert d13 <= 2 * TOL["f32"] * dev1
+    del s1, s3
     # the last population planes (offsets past 2^31) against the oracle at sampled nodes
     g = out[1].view(torch.float32).view(37, -1)
     nodes = np.array([0, n - 1, n * n // 2 + 17, n * n - 1, 12345678], dtype=np.int64)

@@ -602,14 +602,56 @@ def test_two_step_launch_equals_single_steps_d37(cm, orc, shape, model, thermal)
         assert np.array_equal(out[1][1], out[k][1])
 
 
+@pytest.mark.parametrize("shape,model,thermal", D37_FUSION_CASES)
+def test_two_step_accumulating_kernel_d37(cm, orc, shape, model, thermal):
+    """The D2Q37 two-step kernel that folds each first-step row into the
+    moments of the rows it feeds (steps-per-launch mode 3): two steps against
+    the oracle's two steps from the same FP32 state (the intermediate state
+    rounded to FP32 as the kernel keeps it), element by element within the
+    FP32 bound of two steps; then 7 steps (three launches and a single step)
+    against 7 single-step launches.  The moment sums run in another order
+    than the single-step kernel's, so each step may differ by FP32 rounding:
+    the bound is 7 times the one-step FP32 bound."""
+    S = random_state(orc, "D2Q37", shape, seed=sum(shape) + 5, thermal=thermal)
+    w = orc.lattice("D2Q37")["w"][:, None, None]
+    S = quantise(S - w, "f32") + w
+    tau = taus("D2Q37", seed=shape[-1] + 1)
+    out = {}
+    for fuse in (1, 3):
+        ctx = cm.Context("D2Q37", shape, storage="f32", model=model, thermal=thermal, tau=tau)
+        try:
+            ctx.set_step_fusion(fuse)
+            ctx.set_populations(S)
+            ctx.step(2)
+            a = ctx.get_populations()
+            ctx.step(5)
+            out[fuse] = (a, ctx.get_populations(), ctx.step_count())
+        finally:
+            ctx.destroy()
+    assert out[1][2] == out[3][2] == 7
+    cfg = orc.Cfg(lattice="D2Q37", tau=tau, thermal=thermal, model=model)
+    ref = S.copy()
+    orc.run(cfg, ref, 1)
+    ref = quantise(ref - w, "f32") + w
+    orc.run(cfg, ref, 1)
+    dev = np.abs(ref - w).max()
+    err2 = np.abs(out[3][0] - ref).max()
+    err7 = np.abs(out[3][1] - out[1][1]).max()
+    dev7 = np.abs(out[1][1] - w).max()
+    print(f"D2Q37 {shape} {model} thermal={thermal}: two steps vs oracle {err2:.3e} / {dev:.3e}, "
+          f"7 steps vs single steps {err7:.3e} / {dev7:.3e}")
+    assert err2 <= 2 * TOL["f32"] * dev
+    assert err7 <= 7 * TOL["f32"] * dev7
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_two_step_launch_options(cm, storage):
     ctx = cm.Context("D3Q27", (4, 4, 4), storage=storage, tau={2: 0.6})
     try:
-        for bad in (3, -1):
+        for bad in (4, -1):
             with pytest.raises(cm.CmlbError):
                 ctx.set_step_fusion(bad)
-        for v in (0, 2):         # 16-bit storage: one step per launch, silently
+        for v in (0, 2, 3):      # 16-bit storage: one step per launch, silently
             ctx.set_step_fusion(v)
         ctx.init_fields(np.ones((4, 4, 4)), np.zeros((3, 4, 4, 4)))
         ctx.step(3)
