@@ -63,27 +63,26 @@ __device__ __forceinline__ float normal_cdf_f(float a, float& e) {
     const float q = 0.5f * poly * e;   // Phi(-|a|)
     return a >= 0.0f ? 1.0f - q : q;
 }
-// GELU(a) = a Phi(a) = max(a, 0) - |a| Phi(-|a|), no branch on the sign.
-// Phi(-y) = erfc(y / sqrt(2)) / 2 uses the shorter rational approximation of
-// Hastings in Abramowitz and Stegun (formula 7.1.25: erfc(x) =
-// t (a1 + t (a2 + t a3)) exp(-x^2), t = 1 / (1 + p x), |error| <= 2.5e-5),
-// with halved coefficients and exp(-a^2 / 2) as a base-2 exponential.  Its
-// error, at most 1.25e-5 |a|, is far below the BF16 rounding of the
-// activations (relative 2^-9), and it costs two FMAs less than formula
-// 7.1.26.  The factor |a| t is formed as (1 - t) / p', p' = p / sqrt(2),
-// which stays finite for infinite inputs (GELU(+inf) = +inf, GELU(-inf) = 0);
-// its cancellation for small |a| costs at most ~1e-7 in absolute terms.
+// GELU(a) = a Phi(a) = max(a, 0) - |a| Phi(-|a|), with no branch and no
+// transcendental instruction: Phi(-x) for x = min(|a|, 4.5) is a degree-11
+// polynomial in u = 2 x / 4.5 - 1 (the Chebyshev interpolant on [0, 4.5] in
+// power form, evaluated by Horner's rule; paper_1808_04406_amd/gelu_poly.py
+// writes the coefficients and checks the error).  Beyond 4.5 the correction
+// stays at its value there, Phi(-4.5) = 3.4e-6 times 4.5.  In FP32,
+// |GELU_f(a) - GELU(a)| <= 4.6e-6 |a| everywhere, far below the BF16 rounding
+// of the activations (relative 2^-9).  GELU_f(+inf) = +inf; a NaN input gives
+// a finite output (the state it came from is non-finite and is detected
+// there).
+constexpr float kGeluPoly[12] = {
+    1.222619885e-02f, -7.141333294e-02f, 1.806419585e-01f, -2.448524967e-01f,
+    1.588103216e-01f, 2.736721357e-02f, -1.356795843e-01f, 7.390512033e-02f,
+    3.677727454e-02f, -4.407159648e-02f, -2.773498561e-03f, 9.067683363e-03f};
 __device__ __forceinline__ float gelu_f(float a) {
-    constexpr float p = 0.47047f * 0.70710678118654752f;   // p / sqrt(2)
-    constexpr float inv_p = 1.0f / p;
-    constexpr float h1 = 0.5f * 0.3480242f, h2 = 0.5f * -0.0958798f, h3 = 0.5f * 0.7478556f;
-    constexpr float c = -0.72134752044448170f;              // -log2(e) / 2
-    const float t = recip<float>(fmaf(p, fabsf(a), 1.0f));
-    float poly = fmaf(t, h3, h2);
-    poly = fmaf(t, poly, h1);
-    const float yt = fmaf(-t, inv_p, inv_p);
-    const float e = __builtin_amdgcn_exp2f(a * a * c);
-    return fmaf(-yt * e, poly, fmaxf(a, 0.0f));
+    const float x = fminf(fabsf(a), 4.5f);
+    const float u = fmaf(x, 2.0f / 4.5f, -1.0f);
+    float p = kGeluPoly[11];
+    static_for<0, 11>([&](auto K) { p = fmaf(p, u, kGeluPoly[10 - decltype(K)::value]); });
+    return fmaf(-x, p, fmaxf(a, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad_f(float a) {
     float e;
