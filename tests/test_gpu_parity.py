@@ -116,7 +116,7 @@ RULES = ["E9B", "E9C", "E9D", "E7A", "E7B", "E7C", "E7D"]
 @pytest.mark.parametrize("kind", RULES)
 def test_one_step_parity_rules(cm, orc, kind, thermal):
     for storage in ("f64", "f32"):
-        for shape in ((13, 41), (4, 130)):   # ragged rows; padded rows of 130
+        for shape in ((13, 41), (4, 130), (3, 700)):   # ragged rows; padded rows of 130; two x-chunks of a row
             err, scale = one_step_case(cm, orc, kind, storage, shape, seed=400 + len(kind) + shape[1],
                                        thermal=thermal)
             print(f"{kind} {shape} {storage} thermal={thermal}: {err:.3e} / {scale:.3e}")
