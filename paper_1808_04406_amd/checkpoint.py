@@ -24,7 +24,7 @@ MAGIC = b"CMLBCKPT"
 VERSION = 1
 
 _NAMES = {
-    "lattice": {v: k for k, v in cmlb.LATTICES.items()},
+    "lattice": {v: k for k, v in reversed(list(cmlb.LATTICES.items()))},   # the first name of an alias
     "storage": {v: k for k, v in cmlb.STORAGES.items()},
     "model": {v: k for k, v in cmlb.MODELS.items()},
 }

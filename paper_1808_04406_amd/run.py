@@ -5,14 +5,15 @@ diagnostic histories as JSON lines.
 
 Configuration keys (x first in ``grid``; defaults in brackets):
 
-    lattice      "D2Q9" | "D3Q27" | "D2Q37"                      (required)
+    lattice      "D2Q9" | "D3Q27" | "D2Q37" (also "E9A") | "E9B" | "E9C" | "E9D"
+                 | "E7A" | "E7B" | "E7C" | "E7D" (the 2D rules of Fig. 2)  (required)
     grid         [nx, ny] or [nx, ny, nz]                         (required)
     storage      "f64" | "f32" | "bf16" | "f16"                   ["f32"]
     model        "cm" | "raw_mrt" | "reg_bgk" (the last two: D2Q37)  ["cm"]
-    thermal      true | false (D2Q37)                             [false]
+    thermal      true | false (the 2D Hermite rules)              [false]
     rho0, theta0 reference density and temperature                [1.0, 1.0]
     tau          {order: relaxation time}, orders 2..7 (missing orders: 1.0)
-    scale        storage scale per population (37 values, 0 = automatic) [automatic]
+    scale        storage scale per population (Q values, 0 = automatic) [automatic]
     init         {"kind": ...} with
                    "rest"                 uniform rho0, u = 0
                    "tgv"                  Taylor-Green vortex: u0 [0.05], background [0, ...]
@@ -26,7 +27,8 @@ Configuration keys (x first in ``grid``; defaults in brackets):
                                           context keys are then taken from the file)
     steps        steps to run                                     (required)
     every        steps between diagnostics records               [steps, at most 100]
-    fusion       0 automatic, 1 one step per launch, 2 two where supported  [0]
+    fusion       0 automatic, 1 one step per launch, 2 two where supported,
+                 3 as 2 with the row-accumulating D2Q37 kernel (FP32 rounding, not bitwise)  [0]
     graph_steps  replay steps from a HIP graph of this many steps (multiple of 4) [0]
     output       JSON-lines file for the records                 [standard output]
     checkpoint_out  write a checkpoint at the end                 [none]
@@ -52,7 +54,8 @@ _INIT = {"rest": set(), "tgv": {"u0", "background"},
          "waves": {"shear_amp", "thermal_amp", "k", "kt", "background"},
          "double_shear_layer": {"u0", "sharpness", "delta"},
          "random_multimode": {"seed", "kmax", "umax"}, "checkpoint": {"path"}}
-_DIMS = {"D2Q9": 2, "D3Q27": 3, "D2Q37": 2}
+_DIMS = {"D2Q9": 2, "D3Q27": 3, "D2Q37": 2, "E9A": 2, "E9B": 2, "E9C": 2, "E9D": 2, "E7A": 2, "E7B": 2, "E7C": 2,
+         "E7D": 2}
 
 
 def load_config(source) -> dict:

@@ -259,10 +259,14 @@ def test_run_config_validation(tmp_path):
                  "init: {kind: waves, shear_amp: 0.001, thermal_amp: 0.001}\n")
     c = load_config(str(y))
     assert c["grid"] == [16, 12, 1] and c["thermal"] and c["init"]["kind"] == "waves"
+    c = load_config({"lattice": "E7C", "grid": [20, 10], "thermal": True, "steps": 4, "fusion": 3,
+                     "init": {"kind": "waves", "shear_amp": 0.001}})   # a 2D rule of Fig. 2
+    assert c["grid"] == [20, 10, 1] and c["fusion"] == 3
     bad = [
         ({"lattice": "D3Q27", "grid": [8, 8, 8]}, "steps"),
         ({"lattice": "D3Q19", "grid": [8, 8, 8], "steps": 1}, "lattice"),
         ({"lattice": "D2Q9", "grid": [8, 8, 2], "steps": 1}, "2D"),
+        ({"lattice": "E9B", "grid": [8, 8, 2], "steps": 1}, "2D"),
         ({"lattice": "D3Q27", "grid": [8, 8], "steps": 1}, "nz"),
         ({"lattice": "D3Q27", "grid": [8, 8, 4], "steps": 1, "init": {"kind": "tgv"}}, "cubic"),
         ({"lattice": "D2Q9", "grid": [8, 6], "steps": 1, "init": {"kind": "double_shear_layer"}}, "square"),

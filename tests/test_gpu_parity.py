@@ -688,6 +688,7 @@ def test_device_moments_and_energy_spectrum(cm):
     ("D3Q27", (6, 10, 70), "f32", False, False),
     ("D3Q27", (6, 10, 70), "f16", False, False),
     ("D2Q37", (24, 40), "bf16", True, False),
+    ("E7B", (12, 30), "f64", True, False),     # a 2D rule of Fig. 2: its name round-trips
     ("D3Q27", (4, 8, 64), "f32", False, True),
 ])
 def test_checkpoint_resume_is_bitwise(cm, orc, tmp_path, kind, shape, storage, thermal, closure):
