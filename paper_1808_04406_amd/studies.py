@@ -672,9 +672,9 @@ def closure_leverage(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
     random multi-mode runs at Re = 1e5 filtered to 64^3 (one coarse step =
     2 fine steps).  On held-out data: the one-step objective with constant
     omega_3 and omega_5 over [0.6, 1.94] (even orders tied to omega_2, the
-    stable setting), with constant even-order rates untied, the linear
-    stability of those untied rates, and networks trained from the stable
-    fixed rates with two learning rates."""
+    stable setting), with constant even-order rates untied, with the
+    second-order rate itself raised (the network does not set it), and
+    networks trained from the stable fixed rates with two learning rates."""
     import torch
     u0, re = 0.05, 1.0e5
     tau_f = 0.5 + 3.0 * u0 * (n_fine / (2 * math.pi)) / re
@@ -711,14 +711,21 @@ def closure_leverage(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
     stable = _constant_net([1.0] * 4, seed=1, scale=0.1)
     base = obj(stable, test)
     res = {"n_fine": n_fine, "n_coarse": nc, "tau_coarse": tau_c, "objective_stable_fixed_test": base,
-           "omega3_sweep": [], "omega5_sweep": [], "even_untied_sweep": [], "trained": []}
+           "omega3_sweep": [], "omega5_sweep": [], "even_untied_sweep": [], "tau2_sweep": [], "trained": []}
+    # the second-order rate, which the network does not set: the coarse
+    # context's tau_2 (orders 4 and 6 tied to it) from the physical value up
+    for f in (1.0, 10.0, 100.0, 1.0e3, 2.0e3, 5.0e3, 1.0e4, 2.0e4, 3.3e4, 1.0e5):
+        t2 = 0.5 + f * (tau_c - 0.5)
+        ctx.set_tau([t2])
+        res["tau2_sweep"].append({"tau2_over_physical": f, "tau2": t2, "ratio": obj(stable, test) / base})
+    ctx.set_tau([tau_c])
     for w in (0.6, 0.8, 1.0, 1.2, 1.4, 1.6, 1.8, 1.94):
         res["omega3_sweep"].append({"omega3": w, "ratio": obj(_constant_net([w, 1.0, 1.0, 1.0], 1, 0.1), test) / base})
         res["omega5_sweep"].append({"omega5": w, "ratio": obj(_constant_net([1.0, 1.0, w, 1.0], 1, 0.1), test) / base})
     for w in (0.8, 1.2, 1.6, 1.9, 1.94):
         res["even_untied_sweep"].append({"omega4_omega6": w,
                                          "ratio": obj(_constant_net([1.0, w, 1.0, w], 1, 0.1), test, tie=False) / base})
-    for r_ in res["omega3_sweep"] + res["omega5_sweep"] + res["even_untied_sweep"]:
+    for r_ in res["omega3_sweep"] + res["omega5_sweep"] + res["even_untied_sweep"] + res["tau2_sweep"]:
         print("leverage", r_, flush=True)
     for lr_ in (lr, 5 * lr):
         ctx.closure_load(stable, sigma)
