@@ -242,6 +242,10 @@ __global__ __launch_bounds__(kD2Threads) void k_step2_d37(Step2D37Args A) {
 // the 148-row ring, four workgroups share a CU, and each SIMD runs two waves.
 // The moments are summed in another order than in the single-step kernel,
 // so the result agrees with two single steps to FP32 rounding, not bitwise.
+// Measured on one MI355X it is no faster than the ring kernel: the second
+// wave per SIMD raises VALU use, but twice the workgroups means chunks of
+// half the height, whose six lead-in rows add as much work.  It is selected
+// explicitly (steps-per-launch mode 3), never automatically.
 constexpr int kD2AccLds = 2 * 37 * kD2Threads;   // floats
 constexpr int kD2AccPerCU = (160 * 1024) / (kD2AccLds * 4);
 constexpr uint32_t kD2AccSlots = 256u * kD2AccPerCU;
