@@ -202,6 +202,39 @@ def test_thermal_two_step_past_2gib(cm, orc):
     assert err <= 2 * TOL["f32"] * dev
 
 
+def test_thermal_two_step_falls_back_past_4gib(cm):
+    """D2Q37 5800^2 FP32: the 37 planes take 4.98 GB, beyond the 32-bit
+    buffer offsets of both two-step kernels, so steps-per-launch modes 2
+    and 3 run single steps instead and give bitwise the populations of mode
+    1 (compared on the device)."""
+    import torch
+    n = 5800
+    nbytes = cm.state_bytes("D2Q37", (n, n), "f32")
+    assert nbytes >= 2 ** 32
+    r = cm.lattice_info("D2Q37")["r"]
+    rho, u, th = inputs.waves2d(n, n, shear_amp=0.01 / r, thermal_amp=0.01, k=(2, 1), background=(0.0, 0.1))
+    tau = {2: 0.6, 3: 0.55, 4: 0.6}
+    out = []
+    for fuse in (1, 2, 3):
+        ctx = cm.Context("D2Q37", (n, n), storage="f32", thermal=True, tau=tau)
+        try:
+            ctx.set_step_fusion(fuse)
+            ctx.init_fields(rho, u, th)
+            ctx.step(3)
+            assert ctx.step_count() == 3
+            buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            ctx.store_state_device(buf)
+            ctx.sync()
+            out.append(buf)
+        finally:
+            ctx.destroy()
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+    g = out[0].view(torch.float32)
+    assert torch.isfinite(g).all().item()
+    del out, g, buf
+    torch.cuda.empty_cache()
+
+
 def test_closure_128_sampled(cm, orc):
     n, u0, re = 128, 0.05, 1.0e5
     rho, u = inputs.tgv3d(n, u0)
