@@ -318,6 +318,57 @@ def closure_loss_grad(cfg: Cfg, f, fbar, params, norm, tie_even=False):
     return loss.value, grad
 
 
+def _momentum_mismatch(S1, target, pairs_nodes):
+    """Momentum after the next streaming, sum_i e_i S1_i(x - e_i), minus the
+    target's momentum sum_i e_i target_i(x); [N, 3]."""
+    e = lattice("D3Q27")["e"].astype(np.float64)
+    N = pairs_nodes
+    j2 = gather_nodes("D3Q27", S1, np.arange(N)) @ e
+    jbar = np.ascontiguousarray(target, np.float64).reshape(27, N).T @ e
+    return j2 - jbar
+
+
+def closure_momentum_objective(cfg: Cfg, S, target, params, norm, tie_even=False):
+    """Closure objective on the momentum two coarse steps ahead (not in the
+    paper): S [27, nz, ny, nx] post-collision populations, target [27, nz,
+    ny, nx] populations two steps later.  One closure step (pull, collide
+    with network rates) gives S1; the second step's collision conserves
+    momentum, so the momentum after two steps is that of S1 pulled once
+    more.  Objective (1/N) sum_x |j2(x) - jbar(x)|^2; its gradient is
+    sum_y sum_i lam_i(y) d S1_i(y) / d params with the adjoint
+    lam_i(y) = (2/N) e_i . (j2 - jbar)(y + e_i), evaluated as the gradient
+    of the one-step objective for the target S1 - lam w N / 2, whose
+    residual 2 (S1 - target) / (w N) is lam.  Returns (objective, gradient,
+    adjoint field D = (2/N)(j2 - jbar) [3, nz, ny, nx])."""
+    S = np.ascontiguousarray(S, np.float64)
+    shape = S.shape[1:]
+    N = int(np.prod(shape))
+    fin = gather_nodes("D3Q27", S, np.arange(N))
+    f1, _ = collide_closure(cfg, fin, params, norm, tie_even)
+    S1 = np.ascontiguousarray(f1.T.reshape((27,) + shape))
+    dj = _momentum_mismatch(S1, target, N)
+    loss = float(np.mean(np.sum(dj * dj, axis=1)))
+    D = (2.0 / N) * dj.T.reshape((3,) + shape)
+    lam = momentum_adjoint(D)
+    w = lattice("D3Q27")["w"]
+    _, grad = closure_loss_grad(cfg, fin, f1 - lam * w[None, :] * (N / 2.0), params, norm, tie_even)
+    return loss, grad, D
+
+
+def momentum_adjoint(D):
+    """lam_i(y) = sum_d e_{i,d} D_d(y + e_i) for a field D [3, nz, ny, nx];
+    returns [N, 27]."""
+    e = lattice("D3Q27")["e"]
+    shape = D.shape[1:]
+    lam = np.zeros((int(np.prod(shape)), 27))
+    for i in range(27):
+        ex, ey, ez = (int(v) for v in e[i])
+        # value at y + e_i: roll by -e_i along (z, y, x)
+        sh = np.roll(D, shift=(-ez, -ey, -ex), axis=(1, 2, 3))
+        lam[:, i] = (ex * sh[0] + ey * sh[1] + ez * sh[2]).reshape(-1)
+    return lam
+
+
 MLP_NQ = 27 + 2 * 32   # rounded quantities per node: inputs x, activations h1, h2
 
 

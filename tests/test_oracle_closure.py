@@ -6,7 +6,10 @@ only chooses the rates omega_3..omega_6 of eq:omega).
 * inputs vanish at equilibrium and for orders 0 and 1;
 * a network with W3 = 0 and constant logits reproduces the plain collision;
 * the analytic gradient of the training objective against central finite
-  differences.
+  differences;
+* the momentum objective (two coarse steps ahead): its adjoint node by
+  node, its value at constant rates against two plain oracle steps, and its
+  gradient against central finite differences.
 """
 import numpy as np
 import pytest
@@ -279,3 +282,83 @@ def test_bounds_cover_a_perturbed_evaluation(orc):
                                      f[k:k + 1]) for k in range(len(f))])
     assert np.abs(fs - r["fs"]).max() > 0          # the perturbation changes some roundings
     assert (np.abs(fs - r["fs"]) <= r["bound_fs"] * (1 + 1e-9) + 1e-15).all()
+
+
+# --- the momentum objective (two coarse steps ahead) ------------------------
+
+def grid_state(orc, shape, seed, eps=0.03):
+    cfg = orc.Cfg(lattice="D3Q27")
+    rho, u, _ = inputs.random_fields(shape, seed, drho=0.03, umax=0.05)
+    S = orc.init_equilibrium(cfg, rho, u)
+    return S * inputs.perturbation(S.shape, seed + 1, eps)
+
+
+def test_momentum_adjoint_by_brute_force(orc):
+    """lam_i(y) = sum_d e_{i,d} D_d(y + e_i), periodic, node by node."""
+    shape = (3, 4, 5)
+    D = np.random.default_rng(20).normal(size=(3,) + shape)
+    lam = orc.momentum_adjoint(D)
+    e = orc.lattice("D3Q27")["e"]
+    nz, ny, nx = shape
+    for node in range(nz * ny * nx):
+        z, y, x = node // (ny * nx), (node // nx) % ny, node % nx
+        for i in range(27):
+            ex, ey, ez = e[i]
+            zz, yy, xx = (z + ez) % nz, (y + ey) % ny, (x + ex) % nx
+            want = ex * D[0, zz, yy, xx] + ey * D[1, zz, yy, xx] + ez * D[2, zz, yy, xx]
+            assert lam[node, i] == pytest.approx(want, abs=1e-15)
+
+
+@pytest.mark.parametrize("tie", [False, True])
+def test_momentum_objective_at_constant_rates_is_two_plain_steps(orc, tie):
+    """A constant network: the objective equals the momentum mismatch after
+    two steps of the plain collision (orc.run), computed from the momentum
+    moments of the stepped state."""
+    shape = (4, 5, 6)
+    S = grid_state(orc, shape, 21)
+    target = grid_state(orc, shape, 23)
+    P = random_params(24)
+    W1, b1, W2, b2, W3, b3 = unpack(P)
+    W3[:] = 0.0
+    rates = np.array([0.9, 1.3, 0.7, 1.8])
+    b3[:] = np.log((rates - 0.5) / 1.45 / (1 - (rates - 0.5) / 1.45))
+    tau2 = 0.55
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: tau2})
+    loss, g, D = orc.closure_momentum_objective(cfg, S, target, P, np.ones(27), tie_even=tie)
+    om = {3: rates[0], 4: rates[1], 5: rates[2], 6: rates[3]}
+    if tie:
+        om[4] = om[6] = 1.0 / tau2
+    S2 = S.copy()
+    orc.run(orc.Cfg(lattice="D3Q27", tau={2: tau2, **{n: 1.0 / om[n] for n in om}}), S2, 2)
+    rho2, u2, _ = orc.moments("D3Q27", S2)
+    rhot, ut, _ = orc.moments("D3Q27", target)
+    dj = rho2[None] * u2 - rhot[None] * ut
+    assert loss == pytest.approx(float(np.mean(np.sum(dj * dj, axis=0))), rel=1e-12)
+    assert np.allclose(D, 2.0 / rho2.size * dj, rtol=1e-10, atol=1e-18)
+
+
+@pytest.mark.parametrize("tie", [False, True])
+def test_momentum_objective_gradient_matches_finite_differences(orc, tie):
+    shape = (3, 4, 5)
+    S = grid_state(orc, shape, 31)
+    target = grid_state(orc, shape, 33)
+    norm = np.random.default_rng(34).uniform(0.002, 0.02, 27)
+    P = random_params(35, scale=0.3)
+    cfg = orc.Cfg(lattice="D3Q27", tau={2: 0.55})
+    L0, g, _ = orc.closure_momentum_objective(cfg, S, target, P, norm, tie_even=tie)
+    assert L0 > 0 and np.abs(g).max() > 0
+    rng = np.random.default_rng(36)
+    idx = np.concatenate([rng.choice(864, 4, replace=False), 864 + rng.choice(32, 2, replace=False),
+                          896 + rng.choice(1024, 4, replace=False), 1920 + rng.choice(32, 2, replace=False),
+                          1952 + rng.choice(128, 4, replace=False), 2080 + np.arange(4)])
+    h = 1e-4
+    for k in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        fd = (orc.closure_momentum_objective(cfg, S, target, Pp, norm, tie_even=tie)[0]
+              - orc.closure_momentum_objective(cfg, S, target, Pm, norm, tie_even=tie)[0]) / (2 * h)
+        if tie and 2080 <= k and (k - 2080) % 2 == 1:
+            assert g[k] == 0.0 and abs(fd) < 1e-13   # tied outputs do not act
+        else:
+            assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-13), k
