@@ -402,6 +402,24 @@ int cmlb_closure_objective(cmlb_ctx *ctx, const cmlb_batch *batch, float *object
  * the batch objective; *objective receives its value before the update. */
 int cmlb_closure_train_step(cmlb_ctx *ctx, const cmlb_batch *batch, float lr, float *objective);
 
+/* Objective of cmlb_closure_objective and cmlb_closure_train_step (not in
+ * the paper; default CMLB_CLOSURE_OBJ_POPULATIONS):
+ *   CMLB_CLOSURE_OBJ_POPULATIONS  the population mismatch described with
+ *       cmlb_batch, the target being the state one coarse step later;
+ *   CMLB_CLOSURE_OBJ_MOMENTUM  the momentum two coarse steps ahead, the
+ *       target being the state two coarse steps later: the state is
+ *       streamed and collided with the network's rates (f1), streamed once
+ *       more, and the objective is the mean over nodes of
+ *       |sum_i e_i f1_i(x - e_i) - sum_i e_i target_i(x)|^2 (the second
+ *       collision conserves momentum).  The library keeps two device
+ *       buffers of 27 and 3 FP32 values per node and pair for it.
+ * The one-step population mismatch is dominated by the non-equilibrium
+ * part of the populations, which scales with the lattice spacing; the
+ * momentum carries none.  CMLB_EINVAL for other values. */
+#define CMLB_CLOSURE_OBJ_POPULATIONS 0
+#define CMLB_CLOSURE_OBJ_MOMENTUM 1
+int cmlb_closure_set_objective(cmlb_ctx *ctx, int kind);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,7 @@ def lib():
         L.cmlb_closure_get.argtypes = [vp, fp]
         L.cmlb_closure_objective.argtypes = [vp, P(Batch), fp, fp]
         L.cmlb_closure_train_step.argtypes = [vp, P(Batch), ctypes.c_float, fp]
+        L.cmlb_closure_set_objective.argtypes = [vp, c_int]
         _lib = L
     return _lib
 
@@ -411,6 +412,14 @@ class Context:
         self._check(lib().cmlb_closure_tie_even(self.h, 1 if on else 0))
         if getattr(self, "_closure", None) is not None:
             self._closure["tie_even"] = bool(on)
+
+    CLOSURE_OBJECTIVES = {"populations": 0, "momentum": 1}
+
+    def closure_set_objective(self, kind):
+        """Objective of closure_objective / closure_train_step: "populations"
+        (target one coarse step later) or "momentum" (target two coarse steps
+        later; see cmlb_closure_set_objective)."""
+        self._check(lib().cmlb_closure_set_objective(self.h, self.CLOSURE_OBJECTIVES[kind]))
 
     def closure_get(self):
         p = np.zeros(CLOSURE_NPARAM, np.float32)

@@ -202,6 +202,10 @@ struct cmlb_ctx {
     int cl_blocks = 0;
     int cl_step = 0;
     int cl_tie_even = 0;
+    int cl_objective = 0;         // CMLB_CLOSURE_OBJ_POPULATIONS or CMLB_CLOSURE_OBJ_MOMENTUM
+    float* cl_f1 = nullptr;       // momentum objective: closure step of each pair [pair][27][nodes]
+    float* cl_D = nullptr;        //   and the mismatch field [pair][3][nodes]
+    int64_t cl_pairs_cap = 0;     //   pairs the two buffers hold
 };
 
 namespace {
@@ -444,6 +448,8 @@ void cmlb_destroy(cmlb_ctx* c) {
     if (c->cl_net) (void)hipFree(c->cl_net);
     if (c->cl_partials) (void)hipFree(c->cl_partials);
     if (c->cl_grad) (void)hipFree(c->cl_grad);
+    if (c->cl_f1) (void)hipFree(c->cl_f1);
+    if (c->cl_D) (void)hipFree(c->cl_D);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->ev) (void)hipEventDestroy(c->ev);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1010,10 +1016,47 @@ static int closure_gradient(cmlb_ctx* c, const cmlb_batch* b) {
         }
     }
     StepArgs a = base_args(c);
-    launch_closure_train(static_cast<const float*>(b->state), static_cast<const float*>(b->target), b->n_pairs, a.g,
-                         (float)c->p.rho0, (float)c->omega[2], c->cl_net, c->cl_partials, c->cl_blocks, c->cl_grad,
-                         c->stream);
+    const float* target = static_cast<const float*>(b->target);
+    int mode = 0;
+    if (c->cl_objective == CMLB_CLOSURE_OBJ_MOMENTUM) {
+        // the closure step of each pair's state, then the momentum mismatch
+        // field D that the training kernel takes as its adjoint input
+        const uint64_t N = nodes_of(a.g);
+        if (b->n_pairs > c->cl_pairs_cap) {
+            if (c->cl_f1) (void)hipFree(c->cl_f1);
+            if (c->cl_D) (void)hipFree(c->cl_D);
+            c->cl_f1 = c->cl_D = nullptr;
+            c->cl_pairs_cap = 0;
+            if ((e = hipMalloc(&c->cl_f1, (size_t)b->n_pairs * 27 * N * sizeof(float))) != hipSuccess ||
+                (e = hipMalloc(&c->cl_D, (size_t)b->n_pairs * 3 * N * sizeof(float))) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, CMLB_ENOMEM, "momentum objective scratch");
+            }
+            c->cl_pairs_cap = b->n_pairs;
+        }
+        for (int64_t k = 0; k < b->n_pairs; ++k) {
+            StepArgs sa = a;
+            sa.src = static_cast<const float*>(b->state) + (uint64_t)k * 27 * N;
+            sa.dst = c->cl_f1 + (uint64_t)k * 27 * N;
+            launch_step_closure(sa, c->cl_net, c->stream);
+        }
+        launch_closure_momentum(c->cl_f1, target, b->n_pairs, a.g, c->cl_D, c->stream);
+        target = c->cl_D;
+        mode = 1;
+    }
+    launch_closure_train(static_cast<const float*>(b->state), target, b->n_pairs, a.g, (float)c->p.rho0,
+                         (float)c->omega[2], c->cl_net, c->cl_partials, c->cl_blocks, c->cl_grad, mode, c->stream);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "closure training launch");
+    return CMLB_OK;
+}
+
+int cmlb_closure_set_objective(cmlb_ctx* c, int kind) {
+    if (!c) return CMLB_EINVAL;
+    int rc = closure_ready(c, false);
+    if (rc) return rc;
+    if (kind != CMLB_CLOSURE_OBJ_POPULATIONS && kind != CMLB_CLOSURE_OBJ_MOMENTUM)
+        return fail(c, CMLB_EINVAL, "objective must be CMLB_CLOSURE_OBJ_POPULATIONS or CMLB_CLOSURE_OBJ_MOMENTUM");
+    c->cl_objective = kind;
     return CMLB_OK;
 }
 

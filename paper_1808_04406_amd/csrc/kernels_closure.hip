@@ -112,19 +112,24 @@ void k_step_closure(StepArgs a, const ClosureNet* __restrict__ net) {
 }
 
 // ---------------------------------------------------------------------------
-// Training: objective (1/N) sum_nodes sum_i (f*_i - fbar_i)^2 / w_i over
-// pairs (state, target); f* is the closure collision of the pulled state.
-// One wavefront per block; each processes 64 consecutive nodes of a row per
-// tile, and each lane accumulates 34 fixed gradient entries over its tiles.
+// Training.  Mode 0: objective (1/N) sum_nodes sum_i (f*_i - fbar_i)^2 / w_i
+// over pairs (state, target); f* is the closure collision of the pulled
+// state.  Mode 1 (momentum two steps ahead): target holds the field
+// D = (2/N)(j2 - jbar) [pair][3][nodes] of k_closure_momentum, the adjoint of
+// f*_i at node y is lam_i(y) = e_i . D(y + e_i), and the objective share of a
+// node is |D|^2 N / 4.  One wavefront per block; each processes 64
+// consecutive nodes of a row per tile, and each lane accumulates 34 fixed
+// gradient entries over its tiles.
 // ---------------------------------------------------------------------------
 struct TrainArgs {
     const float* state;   // [pair][27][nodes], rows unpadded
-    const float* target;  // [pair][27][nodes]
+    const float* target;  // mode 0: [pair][27][nodes]; mode 1: [pair][3][nodes]
     GridArgs g;
     int64_t n_pairs;
     float rho0;
     float omega2;
     float inv_count;      // 1 / (n_pairs * nodes)
+    int mode;
 };
 
 constexpr int kGradPerLane = 34;   // 14 (W1, b1) + 17 (W2, b2) + 3 (W3, b3) entries of 64 lanes
@@ -206,13 +211,31 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
                 if constexpr (order >= 2) h[p] -= om[order] * neq[p];
             });
             tp_inverse<3, float>(h, m.u);
-            // residuals and the objective (h now holds f* - w rho0)
-            static_for<0, 27>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                const float e = h[i] - Tg[i * plane + node];
-                loss += e * e * inv_w27(i) * t.inv_count;
-                h[i] = 2.0f * e * inv_w27(i) * t.inv_count;
-            });
+            if (t.mode == 0) {
+                // residuals and the objective (h now holds f* - w rho0)
+                static_for<0, 27>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const float e = h[i] - Tg[i * plane + node];
+                    loss += e * e * inv_w27(i) * t.inv_count;
+                    h[i] = 2.0f * e * inv_w27(i) * t.inv_count;
+                });
+            } else {
+                // adjoint of f*_i: e_i . D at the node f*_i streams to, y + e_i
+                const float* Dp = t.target + pair * 3 * plane;
+                const float d0 = Dp[node], d1 = Dp[plane + node], d2 = Dp[2 * plane + node];
+                loss += (d0 * d0 + d1 * d1 + d2 * d2) * (0.25f / t.inv_count);
+                static_for<0, 27>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
+                    // xs3[1 - e] is x + e
+                    const uint64_t nb = ((uint64_t)zs3[1 - ez] * ny + ys3[1 - ey]) * nx + xs3[1 - ex];
+                    float lam = 0.0f;
+                    if constexpr (ex != 0) lam += float(ex) * Dp[nb];
+                    if constexpr (ey != 0) lam += float(ey) * Dp[plane + nb];
+                    if constexpr (ez != 0) lam += float(ez) * Dp[2 * plane + nb];
+                    h[i] = lam;
+                });
+            }
             // d objective / d omega_n = -sum_{|p| = n} (K^-T r)_p neq_p
             tp3_inverse_adjoint(h, m.u);
             float dom[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -289,6 +312,42 @@ __global__ __launch_bounds__(64) void k_closure_train(TrainArgs t, const Closure
     if (lane == 0) out[kNParam] = loss;
 }
 
+// Momentum mismatch two steps ahead: for each pair and node x,
+// j2(x) = sum_i e_i f1_i(x - e_i) (f1: the closure step of the state; the
+// next collision conserves momentum), jbar(x) = sum_i e_i target_i(x), and
+// D = 2 inv_count (j2 - jbar), written [pair][3][nodes].  Deviations carry
+// the momenta of the populations (sum_i e_i w_i = 0).
+__global__ __launch_bounds__(256) void k_closure_momentum(const float* __restrict__ f1,
+                                                          const float* __restrict__ target, GridArgs g,
+                                                          int64_t n_pairs, float inv_count, float* __restrict__ D) {
+    const uint64_t plane = nodes_of(g);
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= plane * (uint64_t)n_pairs) return;
+    const uint64_t pair = id / plane, node = id % plane;
+    const uint32_t nx = g.nx, ny = g.ny, nz = g.nz;
+    const uint32_t x = node % nx, y = (node / nx) % ny, z = node / ((uint64_t)nx * ny);
+    const uint32_t xs3[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys3[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    const uint32_t zs3[3] = {z + 1 == nz ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+    const float* F = f1 + pair * 27 * plane;
+    const float* T = target + pair * 27 * plane;
+    float j[3] = {0.0f, 0.0f, 0.0f};
+    static_for<0, 27>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
+        const float v = F[i * plane + ((uint64_t)zs3[ez + 1] * ny + ys3[ey + 1]) * nx + xs3[ex + 1]]
+                        - T[i * plane + node];
+        if constexpr (ex != 0) j[0] += float(ex) * v;
+        if constexpr (ey != 0) j[1] += float(ey) * v;
+        if constexpr (ez != 0) j[2] += float(ez) * v;
+    });
+    float* out = D + pair * 3 * plane;
+    static_for<0, 3>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        out[k * plane + node] = 2.0f * inv_count * j[k];
+    });
+}
+
 // Sum the per-block partial rows in block order (deterministic).
 __global__ __launch_bounds__(256) void k_closure_reduce(const float* __restrict__ partials, int nblocks,
                                                         float* __restrict__ grad) {
@@ -329,8 +388,16 @@ void launch_step_closure(const StepArgs& a, const void* net, hipStream_t s) {
                        static_cast<const ClosureNet*>(net));
 }
 
+void launch_closure_momentum(const float* f1, const float* target, int64_t n_pairs, const GridArgs& g, float* D,
+                             hipStream_t s) {
+    const uint64_t n = nodes_of(g) * (uint64_t)n_pairs;
+    const float inv_count = (float)(1.0 / (double)n);
+    hipLaunchKernelGGL(k_closure_momentum, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, f1, target, g, n_pairs,
+                       inv_count, D);
+}
+
 void launch_closure_train(const float* state, const float* target, int64_t n_pairs, const GridArgs& g, float rho0,
-                          float omega2, const void* net, float* partials, int nblocks, float* grad,
+                          float omega2, const void* net, float* partials, int nblocks, float* grad, int mode,
                           hipStream_t s) {
     TrainArgs t;
     t.state = state;
@@ -340,6 +407,7 @@ void launch_closure_train(const float* state, const float* target, int64_t n_pai
     t.rho0 = rho0;
     t.omega2 = omega2;
     t.inv_count = (float)(1.0 / ((double)n_pairs * (double)nodes_of(g)));
+    t.mode = mode;
     hipLaunchKernelGGL(k_closure_train, dim3(nblocks), dim3(64), 0, s, t, static_cast<const ClosureNet*>(net),
                        partials);
     hipLaunchKernelGGL(k_closure_reduce, dim3((kPartialStride + 255) / 256), dim3(256), 0, s, partials, nblocks,

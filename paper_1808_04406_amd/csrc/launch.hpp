@@ -72,8 +72,15 @@ size_t closure_net_bytes();
 int closure_partial_stride();
 void launch_closure_pack(const float* params, const float* norm, int tie_even, void* net, hipStream_t s);
 void launch_step_closure(const StepArgs& a, const void* net, hipStream_t s);
+// mode 0: population objective against target [pair][27][nodes]; mode 1:
+// momentum objective, target = the field D of launch_closure_momentum.
 void launch_closure_train(const float* state, const float* target, int64_t n_pairs, const GridArgs& g, float rho0,
-                          float omega2, const void* net, float* partials, int nblocks, float* grad, hipStream_t s);
+                          float omega2, const void* net, float* partials, int nblocks, float* grad, int mode,
+                          hipStream_t s);
+// D = (2/N)(j2 - jbar) [pair][3][nodes]: j2 the momentum of f1 [pair][27][nodes]
+// after one more streaming, jbar that of target [pair][27][nodes].
+void launch_closure_momentum(const float* f1, const float* target, int64_t n_pairs, const GridArgs& g, float* D,
+                             hipStream_t s);
 void launch_closure_adam(float* params, float* m1, float* m2, const float* grad, float lr, int step, hipStream_t s);
 
 // Box filter of a D3Q27 state to FP32 deviations on the coarse grid.

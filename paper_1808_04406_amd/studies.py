@@ -742,6 +742,131 @@ def closure_leverage(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
     return res
 
 
+def closure_momentum(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), train_steps=4000, lrs=(0.03, 0.1, 0.3),
+                     tgv_coarse_steps=600, every=50, stream=None):
+    """The closure trained on the momentum two coarse steps ahead
+    (cmlb_closure_set_objective): 128^3 random multi-mode runs at Re = 1e5
+    filtered to 64^3, targets two coarse steps (four fine steps) after each
+    state.  On the held-out seed: the objective at constant rates (omega_3,
+    omega_5, untied even orders, tau_2) relative to the stable fixed rates,
+    networks trained from the stable fixed rates, and the 64^3 Taylor-Green
+    rollout (Re = 1e5) of the stable fixed rates, the best constant omega_3
+    and the trained network against the filtered 128^3 run."""
+    import torch
+    u0, re = 0.05, 1.0e5
+    tau_f = 0.5 + 3.0 * u0 * (n_fine / (2 * math.pi)) / re
+    tau_c = 0.5 + (tau_f - 0.5) / factor
+    nc = n_fine // factor
+    data = {}
+    for seed in seeds:
+        rho, u = inputs.random_multimode(n_fine, seed, kmax=4, umax=u0)
+        fine = cmlb.Context("D3Q27", (n_fine,) * 3, storage="f32", tau=_tgv_rates(tau_f), stream=stream)
+        fine.init_fields(rho, u)
+        fine.step(100 * factor)
+        pairs = []
+        for _ in range(3):
+            a = torch.empty(27 * nc ** 3, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            fine.box_filter(factor, a)
+            fine.step(2 * factor)
+            fine.box_filter(factor, b)
+            pairs.append((a, b))
+            fine.step(40 * factor - 2 * factor)
+        fine.sync()
+        fine.destroy()
+        data[seed] = pairs
+    train = [p for s_ in seeds if s_ not in held_out for p in data[s_]]
+    test = [p for s_ in held_out for p in data[s_]]
+    sigma = _input_scales(train[0][0].cpu().numpy(), nc)
+    ctx = cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)
+
+    def obj(params, pairs, tie=True):
+        ctx.closure_load(params, sigma)
+        ctx.closure_tie_even(tie)
+        ctx.closure_set_objective("momentum")
+        return float(np.mean([ctx.closure_objective(a, b, grad=False) for a, b in pairs]))
+
+    stable = _constant_net([1.0] * 4, seed=1, scale=0.1)
+    base = obj(stable, test)
+    res = {"n_fine": n_fine, "n_coarse": nc, "tau_coarse": tau_c, "objective_stable_fixed_test": base,
+           "omega3_sweep": [], "omega5_sweep": [], "even_untied_sweep": [], "tau2_sweep": [], "trained": []}
+    for w in (0.55, 0.6, 0.7, 0.8, 1.0, 1.2, 1.4, 1.8):
+        res["omega3_sweep"].append({"omega3": w, "ratio": obj(_constant_net([w, 1.0, 1.0, 1.0], 1, 0.1), test) / base})
+        res["omega5_sweep"].append({"omega5": w, "ratio": obj(_constant_net([1.0, 1.0, w, 1.0], 1, 0.1), test) / base})
+    for w in (0.8, 1.2, 1.6, 1.9):
+        res["even_untied_sweep"].append({"omega4_omega6": w,
+                                         "ratio": obj(_constant_net([1.0, w, 1.0, w], 1, 0.1), test, tie=False) / base})
+    for f in (0.5, 2.0, 10.0, 100.0):
+        ctx.set_tau([0.5 + f * (tau_c - 0.5)])
+        res["tau2_sweep"].append({"tau2_over_physical": f, "ratio": obj(stable, test) / base})
+    ctx.set_tau([tau_c])
+    for r_ in res["omega3_sweep"] + res["omega5_sweep"] + res["even_untied_sweep"] + res["tau2_sweep"]:
+        print("momentum objective", r_, flush=True)
+    best3 = min(res["omega3_sweep"], key=lambda r_: r_["ratio"])["omega3"]
+    nets = {}
+    for lr_ in lrs:
+        ctx.closure_load(stable, sigma)
+        ctx.closure_tie_even(True)
+        ctx.closure_set_objective("momentum")
+        for it in range(train_steps):
+            a, b = train[it % len(train)]
+            ctx.closure_train_step(a, b, lr_ * (1.0 - it / train_steps))
+        P = ctx.closure_get().astype(np.float64)
+        nets[lr_] = P
+        row = {"lr": lr_, "steps": train_steps, "ratio_test": obj(P, test) / base,
+               "ratio_train": obj(P, train) / obj(stable, train)}
+        res["trained"].append(row)
+        print("trained", row, flush=True)
+    ctx.destroy()
+    best_lr = min(res["trained"], key=lambda r_: r_["ratio_test"])["lr"]
+    # Taylor-Green rollout: coarse runs from the filtered fine initial state
+    rho, u = inputs.tgv3d(n_fine, u0)
+    fine = cmlb.Context("D3Q27", (n_fine,) * 3, storage="f32", tau=_tgv_rates(tau_f), stream=stream)
+    fine.init_fields(rho, u)
+    del rho, u
+    runs = {"stable_fixed": _constant_net([1.0] * 4, 1, 0.1),
+            f"constant_omega3_{best3}": _constant_net([best3, 1.0, 1.0, 1.0], 1, 0.1),
+            "trained": nets[best_lr]}
+    ctxs = {}
+    buf = torch.empty(27 * nc ** 3, dtype=torch.float32, device="cuda")
+    fine.box_filter(factor, buf)
+    for k, P in runs.items():
+        c = cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)
+        c.closure_load(P, sigma)
+        c.closure_tie_even(True)
+        c.closure_enable(True)
+        c.load_state_device(buf)
+        ctxs[k] = c
+    probe = cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)
+    hist = {k: {"ke": [], "enstrophy": []} for k in list(runs) + ["filtered_fine"]}
+    t_axis = []
+    for t in range(0, tgv_coarse_steps + 1, every):
+        if t:
+            fine.step(every * factor)
+            for c in ctxs.values():
+                c.step(every)
+        fine.box_filter(factor, buf)
+        probe.load_state_device(buf)
+        g = probe.reduce(allow_unstable=True)
+        hist["filtered_fine"]["ke"].append(g["ke"])
+        hist["filtered_fine"]["enstrophy"].append(g["enstrophy"])
+        for k, c in ctxs.items():
+            g = c.reduce(allow_unstable=True)
+            hist[k]["ke"].append(g["ke"])
+            hist[k]["enstrophy"].append(g["enstrophy"])
+        t_axis.append(t)
+    for c in list(ctxs.values()) + [probe, fine]:
+        c.destroy()
+    ref = hist["filtered_fine"]
+    res["rollout"] = {"steps": t_axis, "histories": hist, "errors": {}}
+    for k in runs:
+        eke = float(np.max(np.abs(np.array(hist[k]["ke"]) - ref["ke"]) / np.array(ref["ke"])))
+        ez = float(np.max(np.abs(np.array(hist[k]["enstrophy"]) - ref["enstrophy"]) / np.array(ref["enstrophy"])))
+        res["rollout"]["errors"][k] = {"max_rel_ke": eke, "max_rel_enstrophy": ez}
+        print("rollout", k, res["rollout"]["errors"][k], flush=True)
+    return res
+
+
 def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=400, pairs_per_seed=3, gap=400,
             train_steps=600, lr=2e-3, tgv_coarse_steps=1250, every=50, stream=None):
     """Learned closure: data from fine random multi-mode runs at Re = 1e5
@@ -872,8 +997,8 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precision", "thermal", "closure", "closure_leverage", "modes", "fig2", "dsl",
-                                      "dsl_factors", "galilean", "tgv"])
+    ap.add_argument("study", choices=["precision", "thermal", "closure", "closure_leverage", "closure_momentum", "modes",
+                                      "fig2", "dsl", "dsl_factors", "galilean", "tgv"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--every", type=int, default=None)
@@ -891,6 +1016,8 @@ def main(argv=None):
             res = closure(n_fine=a.n or 512, stream=stream)
         elif a.study == "closure_leverage":
             res = closure_leverage(n_fine=a.n or 128, stream=stream)
+        elif a.study == "closure_momentum":
+            res = closure_momentum(n_fine=a.n or 128, stream=stream)
         elif a.study == "modes":
             res = modes(stream=stream)
         elif a.study == "fig2":
