@@ -386,9 +386,12 @@ int cmlb_closure_get(cmlb_ctx *ctx, float *params);
 /* A training batch: n_pairs consecutive (state, target) pairs in device
  * memory, each Q * nx*ny*nz FP32 deviations, unpadded [i][z][y][x] (the
  * box filter's output layout).  The
- * state is pulled (streamed) and collided with the network's rates; the
- * objective is the mean over all nodes of sum_i (f*_i - fbar_i)^2 / w_i
- * against the target.  nx must be a multiple of 64. */
+ * state is pulled (streamed) and collided with the network's rates.  Under
+ * the default objective the target is the state one coarse step later and
+ * the objective is the mean over all nodes of sum_i (f*_i - fbar_i)^2 / w_i;
+ * under CMLB_CLOSURE_OBJ_MOMENTUM the target is the state two coarse steps
+ * later and only its momentum is compared (cmlb_closure_set_objective).
+ * nx must be a multiple of 64. */
 typedef struct cmlb_batch {
     const void *state;
     const void *target;
