@@ -401,9 +401,32 @@ typedef struct cmlb_batch {
 /* Objective and its gradient (host outputs; grad may be NULL). */
 int cmlb_closure_objective(cmlb_ctx *ctx, const cmlb_batch *batch, float *objective, float *grad);
 
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on
- * the batch objective; *objective receives its value before the update. */
+/* One Adam step with learning rate lr on the batch objective (moments kept
+ * on the device and reset by cmlb_closure_load); *objective receives its
+ * value before the update. */
 int cmlb_closure_train_step(cmlb_ctx *ctx, const cmlb_batch *batch, float lr, float *objective);
+
+/* Adam's constants for cmlb_closure_train_step (training infrastructure, not
+ * in the paper): P -= lr mhat / (sqrt(vhat) + eps), m = beta1 m + (1 - beta1) g,
+ * v = beta2 v + (1 - beta2) g^2, mhat and vhat divided by 1 - beta^t at step
+ * t.  Defaults 0.9, 0.999, 1e-8.  The objectives scale with the flow's
+ * amplitude and the grid (the momentum objective is about 1e-12 on 128^3
+ * from 512^3 at Mach 0.09), and eps must lie well below sqrt(vhat), the
+ * gradient's size, or it shrinks every step.  beta1, beta2 in [0, 1); eps a
+ * positive normal FP32 number; else CMLB_EINVAL and nothing changes.  Kept
+ * across cmlb_closure_load.  Applies from the next step. */
+int cmlb_closure_set_adam(cmlb_ctx *ctx, double beta1, double beta2, double eps);
+
+/* Outputs whose weights cmlb_closure_train_step leaves unchanged (training
+ * infrastructure, not in the paper): bit j (0..3) of mask freezes the rate
+ * of order 3 + j, i.e. row j of W3 and b3[j], and their Adam moments.  With
+ * that row of W3 zero the order's rate stays the constant its b3 entry
+ * gives.  An order whose rate moves the objective little can still be
+ * driven by Adam (whose steps do not shrink with the gradient) into rates
+ * that are linearly unstable, e.g. omega_5 near 1.95 with omega_3 near 0.5.
+ * mask in [0, 15], else CMLB_EINVAL.  Default 0; kept across
+ * cmlb_closure_load. */
+int cmlb_closure_freeze(cmlb_ctx *ctx, int mask);
 
 /* Objective of cmlb_closure_objective and cmlb_closure_train_step (not in
  * the paper; default CMLB_CLOSURE_OBJ_POPULATIONS):

@@ -113,6 +113,8 @@ def lib():
         L.cmlb_closure_objective.argtypes = [vp, P(Batch), fp, fp]
         L.cmlb_closure_train_step.argtypes = [vp, P(Batch), ctypes.c_float, fp]
         L.cmlb_closure_set_objective.argtypes = [vp, c_int]
+        L.cmlb_closure_set_adam.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.cmlb_closure_freeze.argtypes = [vp, c_int]
         _lib = L
     return _lib
 
@@ -420,6 +422,21 @@ class Context:
         (target one coarse step later) or "momentum" (target two coarse steps
         later; see cmlb_closure_set_objective)."""
         self._check(lib().cmlb_closure_set_objective(self.h, self.CLOSURE_OBJECTIVES[kind]))
+
+    def closure_set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam's constants for closure_train_step (cmlb_closure_set_adam);
+        eps must lie well below the gradient's size."""
+        self._check(lib().cmlb_closure_set_adam(self.h, float(beta1), float(beta2), float(eps)))
+
+    def closure_freeze(self, orders=()):
+        """Orders (3..6) whose rate weights closure_train_step leaves
+        unchanged (cmlb_closure_freeze)."""
+        mask = 0
+        for n in orders:
+            if n not in (3, 4, 5, 6):
+                raise ValueError(f"order {n} is not set by the network")
+            mask |= 1 << (n - 3)
+        self._check(lib().cmlb_closure_freeze(self.h, mask))
 
     def closure_get(self):
         p = np.zeros(CLOSURE_NPARAM, np.float32)

@@ -203,6 +203,8 @@ struct cmlb_ctx {
     int cl_step = 0;
     int cl_tie_even = 0;
     int cl_objective = 0;         // CMLB_CLOSURE_OBJ_POPULATIONS or CMLB_CLOSURE_OBJ_MOMENTUM
+    float cl_beta1 = 0.9f, cl_beta2 = 0.999f, cl_eps = 1e-8f;   // Adam
+    int cl_frozen = 0;            // bit j: Adam leaves output j's weights unchanged
     float* cl_f1 = nullptr;       // momentum objective: closure step of each pair [pair][27][nodes]
     float* cl_D = nullptr;        //   and the mismatch field [pair][3][nodes]
     int64_t cl_pairs_cap = 0;     //   pairs the two buffers hold
@@ -1060,6 +1062,25 @@ int cmlb_closure_set_objective(cmlb_ctx* c, int kind) {
     return CMLB_OK;
 }
 
+int cmlb_closure_set_adam(cmlb_ctx* c, double beta1, double beta2, double eps) {
+    if (!c) return CMLB_EINVAL;
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return fail(c, CMLB_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+    if (!(eps >= 1.17549435e-38 && eps <= 3.4e38))
+        return fail(c, CMLB_EINVAL, "eps must be a positive normal FP32 number");
+    c->cl_beta1 = (float)beta1;
+    c->cl_beta2 = (float)beta2;
+    c->cl_eps = (float)eps;
+    return CMLB_OK;
+}
+
+int cmlb_closure_freeze(cmlb_ctx* c, int mask) {
+    if (!c) return CMLB_EINVAL;
+    if (mask < 0 || mask > 15) return fail(c, CMLB_EINVAL, "freeze mask must lie in [0, 15]");
+    c->cl_frozen = mask;
+    return CMLB_OK;
+}
+
 int cmlb_closure_objective(cmlb_ctx* c, const cmlb_batch* b, float* objective, float* grad) {
     if (!c) return CMLB_EINVAL;
     if (!objective) return fail(c, CMLB_EINVAL, "objective is NULL");
@@ -1083,7 +1104,8 @@ int cmlb_closure_train_step(cmlb_ctx* c, const cmlb_batch* b, float lr, float* o
     if ((rc = closure_gradient(c, b))) return rc;
     float* P = c->cl_params;
     c->cl_step++;
-    launch_closure_adam(P, P + CMLB_CLOSURE_NPARAM, P + 2 * CMLB_CLOSURE_NPARAM, c->cl_grad, lr, c->cl_step, c->stream);
+    launch_closure_adam(P, P + CMLB_CLOSURE_NPARAM, P + 2 * CMLB_CLOSURE_NPARAM, c->cl_grad, lr, c->cl_beta1,
+                        c->cl_beta2, c->cl_eps, c->cl_frozen, c->cl_step, c->stream);
     launch_closure_pack(P, P + 3 * CMLB_CLOSURE_NPARAM, c->cl_tie_even, c->cl_net, c->stream);
     hipError_t e;
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "adam launch");

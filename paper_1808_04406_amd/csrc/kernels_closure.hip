@@ -1,6 +1,8 @@
 // Learned-closure kernels (D3Q27, FP32 storage): weight packing, the fused
 // stream + collide step with network rates, the training forward/backward
 // pass, the deterministic gradient reduction and the Adam update.
+#include <cmath>
+
 #include "closure.hpp"
 #include "launch.hpp"
 
@@ -358,18 +360,23 @@ __global__ __launch_bounds__(256) void k_closure_reduce(const float* __restrict_
     grad[e] = (float)s;
 }
 
-// Adam on the FP32 master weights.
+// Adam on the FP32 master weights; c1, c2 undo the moments' start-up bias.
+// Bit j of `frozen` keeps output j's weights (row j of W3 and b3[j]) and
+// their moments unchanged.
 __global__ __launch_bounds__(256) void k_closure_adam(float* __restrict__ P, float* __restrict__ m1,
                                                       float* __restrict__ m2, const float* __restrict__ grad,
-                                                      float lr, float c1, float c2) {
+                                                      float lr, float b1, float b2, float eps, float c1, float c2,
+                                                      int frozen) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kNParam) return;
+    const int out = e >= kOb3 ? e - kOb3 : (e >= kOW3 ? (e - kOW3) / kNH : -1);
+    if (out >= 0 && ((frozen >> out) & 1)) return;
     const float g = grad[e];
-    const float a = 0.9f * m1[e] + 0.1f * g;
-    const float b = 0.999f * m2[e] + 0.001f * g * g;
+    const float a = b1 * m1[e] + (1.0f - b1) * g;
+    const float b = b2 * m2[e] + (1.0f - b2) * g * g;
     m1[e] = a;
     m2[e] = b;
-    P[e] -= lr * (a * c1) / (sqrtf(b * c2) + 1e-8f);
+    P[e] -= lr * (a * c1) / (sqrtf(b * c2) + eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,10 +421,12 @@ void launch_closure_train(const float* state, const float* target, int64_t n_pai
                        grad);
 }
 
-void launch_closure_adam(float* P, float* m1, float* m2, const float* grad, float lr, int step, hipStream_t s) {
-    const float c1 = 1.0f / (1.0f - powf(0.9f, (float)step));
-    const float c2 = 1.0f / (1.0f - powf(0.999f, (float)step));
-    hipLaunchKernelGGL(k_closure_adam, dim3((kNParam + 255) / 256), dim3(256), 0, s, P, m1, m2, grad, lr, c1, c2);
+void launch_closure_adam(float* P, float* m1, float* m2, const float* grad, float lr, float b1, float b2, float eps,
+                         int frozen, int step, hipStream_t s) {
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, step)));
+    hipLaunchKernelGGL(k_closure_adam, dim3((kNParam + 255) / 256), dim3(256), 0, s, P, m1, m2, grad, lr, b1, b2, eps,
+                       c1, c2, frozen);
 }
 
 }  // namespace cmlb

@@ -81,7 +81,8 @@ void launch_closure_train(const float* state, const float* target, int64_t n_pai
 // after one more streaming, jbar that of target [pair][27][nodes].
 void launch_closure_momentum(const float* f1, const float* target, int64_t n_pairs, const GridArgs& g, float* D,
                              hipStream_t s);
-void launch_closure_adam(float* params, float* m1, float* m2, const float* grad, float lr, int step, hipStream_t s);
+void launch_closure_adam(float* params, float* m1, float* m2, const float* grad, float lr, float beta1, float beta2,
+                         float eps, int frozen, int step, hipStream_t s);
 
 // Box filter of a D3Q27 state to FP32 deviations on the coarse grid.
 int launch_box_filter(int storage, const StepArgs& a, int factor, float* dst, hipStream_t s);
