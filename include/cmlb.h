@@ -144,14 +144,21 @@ int cmlb_copy_bandwidth(int device, uint64_t bytes, int planes, int reps, double
 
 /* Layout of the population state (device memory, storage type): structure
  * of arrays, population i of node (x, y, z) at
- *     i * plane + (z * ny + y) * pitch + x,    plane = pitch * ny * nz,
+ *     i * plane + (z * ny + y) * pitch + x,
  * where pitch is nx rounded up to a multiple of 128 bytes, or nx itself when
  * that would add more than one eighth (so every x-row of a large grid starts
  * on a 128-byte line, which the pulls need to stream at full rate).  D3Q27
  * FP32 states whose rows are already a multiple of 32 bytes (nx % 8 == 0)
  * are not padded: their default two-step kernel streams such rows at full
- * rate.  Entries with x >= nx are never read.  cmlb_state_bytes gives the
- * buffer size.
+ * rate.  plane is pitch * ny * nz, except for D3Q27 states in BF16 or FP16
+ * storage, whose planes of at least 1 MiB are padded to their byte size
+ * rounded up to 8 KiB plus 4 KiB, so that the 27 planes, streamed together,
+ * start 4 KiB apart modulo 8 KiB (their one-step kernel runs 3 % faster so
+ * at 512^3; the FP32 and FP64 two-step kernels and the 2D row sweeps were
+ * no faster or slower).  Padding entries are never read; the library
+ * zeroes its own buffers once at creation.
+ * cmlb_state_layout gives pitch and plane, cmlb_state_bytes (Q * plane
+ * elements) the buffer size.
  * Host-side arrays (fields, cmlb_get/set_populations, training batches, the
  * box filter's output) are unpadded, [component][z][y][x]. */
 
@@ -159,6 +166,11 @@ int cmlb_copy_bandwidth(int device, uint64_t bytes, int planes, int reps, double
  * cmlb_create; host only, no device needed).  Sizes the buffers of
  * cmlb_create_external. */
 int cmlb_state_bytes(const cmlb_params *p, size_t *bytes);
+
+/* Row pitch and population-plane stride, in elements, of the state for
+ * parameters p (layout of the state above; validated as by cmlb_create;
+ * host only).  CMLB_EINVAL for NULL outputs or invalid parameters. */
+int cmlb_state_layout(const cmlb_params *p, uint64_t *pitch, uint64_t *plane);
 
 /* Create a context: validates p, allocates two population buffers of
  * cmlb_state_bytes bytes on p->device.  The state is
@@ -343,10 +355,19 @@ int cmlb_get_scale(const cmlb_ctx *ctx, double *scale);
 
 /* Copy the current population buffer to / from device memory in the
  * context's own layout and storage type (cmlb_state_bytes bytes, rows
- * padded to the pitch).  Loading marks the state initialised and resets the
+ * and planes padded as in the layout of the state).  Loading marks the state initialised and resets the
  * step count. */
 int cmlb_store_state_device(cmlb_ctx *ctx, void *dst);
 int cmlb_load_state_device(cmlb_ctx *ctx, const void *src);
+
+/* Load the state from FP32 deviations f_i - w_i rho0 in device memory,
+ * unpadded [i][z][y][x] (Q * nx * ny * nz floats: the layout of the box
+ * filter's output and of training batches), encoded into the context's
+ * storage type (times its scale s_i) and layout.  Asynchronous on the
+ * context stream; marks the state initialised and resets the step count.
+ * The caller keeps ownership of src, which must stay valid until the
+ * stream has run the copy. */
+int cmlb_load_deviations_device(cmlb_ctx *ctx, const float *src);
 
 /* Box filter for coarse-graining (D3Q27 contexts): the populations of
  * factor^3 blocks of nodes are averaged (a linear filter, so mass and

@@ -5,8 +5,11 @@ they sit in device memory (deviations in the storage type, structure of
 arrays), so that a resumed run continues bitwise as if it had never
 stopped.  The header records what the context needs to be rebuilt: lattice,
 grid, storage, collision model, thermal flag, rho0, theta0, the relaxation
-times and storage scales in use, the step counter, and the learned closure
-(FP32 master weights, input scales, switches) when one is loaded.
+times and storage scales in use, the step counter, the state's row pitch
+and plane stride, and the learned closure (FP32 master weights, input
+scales, switches) when one is loaded.  Version 2 pads large population
+planes (cmlb.h, layout of the state); a file whose layout differs from the
+rebuilt context's is refused.
 
 Layout: b"CMLBCKPT", uint32 version, uint64 header length, header (UTF-8
 JSON), population bytes.
@@ -21,7 +24,7 @@ import numpy as np
 from . import cmlb
 
 MAGIC = b"CMLBCKPT"
-VERSION = 1
+VERSION = 2
 
 _NAMES = {
     "lattice": {v: k for k, v in reversed(list(cmlb.LATTICES.items()))},   # the first name of an alias
@@ -50,6 +53,7 @@ def save(ctx, path):
         "scale": [float(s) for s in ctx.get_scale()],
         "steps": int(ctx.step_count()),
         "bytes": int(nbytes),
+        "layout": list(cmlb.state_layout(_NAMES["lattice"][p.lattice], ctx.shape, _NAMES["storage"][p.storage])),
         "closure": None,
     }
     if ctx._closure is not None:
@@ -84,6 +88,9 @@ def load(path, stream=None, device=0):
                        tau={int(k): v for k, v in h["tau"].items()}, scale=h["scale"], device=device,
                        stream=stream)
     try:
+        layout = list(cmlb.state_layout(h["lattice"], tuple(h["shape"]), h["storage"]))
+        if h.get("layout") != layout:
+            raise ValueError(f"{path}: state layout (pitch, plane) {h.get('layout')}, this library uses {layout}")
         data = np.fromfile(path, dtype=np.uint8, offset=offset)
         if data.size != h["bytes"]:
             raise ValueError(f"{path}: {data.size} population bytes, expected {h['bytes']}")

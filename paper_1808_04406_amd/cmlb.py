@@ -89,6 +89,7 @@ def lib():
         L.cmlb_step_batch.argtypes = [P(vp), c_int, c_i64]
         L.cmlb_copy_bandwidth.argtypes = [c_int, ctypes.c_uint64, c_int, c_int, dp]
         L.cmlb_state_bytes.argtypes = [P(Params), P(ctypes.c_size_t)]
+        L.cmlb_state_layout.argtypes = [P(Params), P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.cmlb_sync.argtypes = [vp]
         L.cmlb_get_moments.argtypes = [vp, dp, dp, dp]
         L.cmlb_get_moments_device.argtypes = [vp, vp, vp, vp]
@@ -105,6 +106,7 @@ def lib():
         fp = P(ctypes.c_float)
         L.cmlb_store_state_device.argtypes = [vp, vp]
         L.cmlb_load_state_device.argtypes = [vp, vp]
+        L.cmlb_load_deviations_device.argtypes = [vp, vp]
         L.cmlb_box_filter.argtypes = [vp, c_int, vp]
         L.cmlb_closure_load.argtypes = [vp, fp, fp]
         L.cmlb_closure_enable.argtypes = [vp, c_int]
@@ -173,14 +175,25 @@ def _stream_handle(stream):
 
 
 def state_bytes(lattice, shape, storage="f32", **kw):
-    """cmlb_state_bytes: bytes of one population buffer (x-rows padded to the
-    pitch); the size of each external buffer."""
+    """cmlb_state_bytes: bytes of one population buffer (rows and planes
+    padded); the size of each external buffer."""
     p = make_params(lattice, shape, storage, **kw)
     n = ctypes.c_size_t()
     rc = lib().cmlb_state_bytes(ctypes.byref(p), ctypes.byref(n))
     if rc:
         raise CmlbError(rc, lib().cmlb_create_error().decode())
     return n.value
+
+
+def state_layout(lattice, shape, storage="f32", **kw):
+    """cmlb_state_layout: (pitch, plane) in elements; population i of node
+    (x, y, z) sits at i * plane + (z * ny + y) * pitch + x."""
+    p = make_params(lattice, shape, storage, **kw)
+    pitch, plane = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().cmlb_state_layout(ctypes.byref(p), ctypes.byref(pitch), ctypes.byref(plane))
+    if rc:
+        raise CmlbError(rc, lib().cmlb_create_error().decode())
+    return pitch.value, plane.value
 
 
 def copy_bandwidth(nbytes=4 << 30, planes=27, reps=10, device=0):
@@ -384,6 +397,13 @@ class Context:
         need = self.state()[1]
         self._check(lib().cmlb_load_state_device(self.h, _device_ptr(src, "src", self.params.device,
                                                                      min_bytes=need)))
+
+    def load_deviations_device(self, src):
+        """Load the state from unpadded FP32 deviations [Q][z][y][x] on the
+        device (a box filter's output or a training batch entry)."""
+        need = 4 * self.Q * int(np.prod(self.shape))
+        self._check(lib().cmlb_load_deviations_device(self.h, _device_ptr(src, "src", self.params.device,
+                                                                          min_bytes=need)))
 
     def box_filter(self, factor, dst):
         """Mean over factor^3 blocks into an FP32 device tensor (coarse layout)."""

@@ -153,11 +153,15 @@ int lattice_q(int lattice) {
     return lattice == CMLB_D2Q9 ? 9 : (lattice == CMLB_D3Q27 ? 27 : make_tab_h2(lattice).q);
 }
 
-// Bytes of one population buffer: Q planes of pitch * ny * nz elements.
-size_t state_bytes_of(const cmlb_params* p) {
-    const size_t e = storage_bytes(p->storage);
+// Population-plane stride in elements (pitch * ny * nz, padded by state_plane).
+uint64_t state_plane_of(const cmlb_params* p) {
     const uint64_t pitch = cmlb::state_pitch(p->lattice, p->storage, (uint32_t)p->nx);
-    return (size_t)lattice_q(p->lattice) * pitch * (uint64_t)p->ny * (uint64_t)p->nz * e;
+    return cmlb::state_plane(p->lattice, p->storage, pitch * (uint64_t)p->ny * (uint64_t)p->nz);
+}
+
+// Bytes of one population buffer: Q planes.
+size_t state_bytes_of(const cmlb_params* p) {
+    return (size_t)lattice_q(p->lattice) * state_plane_of(p) * storage_bytes(p->storage);
 }
 
 }  // namespace
@@ -232,7 +236,7 @@ StepArgs base_args(const cmlb_ctx* c) {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.pitch = state_pitch(c->p.lattice, c->p.storage, (uint32_t)c->p.nx);
-    a.g = make_grid((uint32_t)c->p.nx, (uint32_t)c->p.ny, (uint32_t)c->p.nz, a.pitch);
+    a.g = make_grid((uint32_t)c->p.nx, (uint32_t)c->p.ny, (uint32_t)c->p.nz, state_plane_of(&c->p));
     a.rho0 = c->p.rho0;
     a.theta0 = c->p.theta0;
     for (int n = 0; n < 8; ++n) a.omega[n] = c->omega[n];
@@ -348,6 +352,12 @@ int create_impl(const cmlb_params* p, void* fa, void* fb, cmlb_ctx** out) {
                 cmlb_destroy(c);
                 return CMLB_ENOMEM;
             }
+            // row and plane padding is never written by the kernels: zero it once
+            if ((e = hipMemsetAsync(c->f[k], 0, bytes, c->stream)) != hipSuccess) {
+                g_create_error = std::string("hipMemsetAsync population buffer: ") + hipGetErrorString(e);
+                cmlb_destroy(c);
+                return CMLB_EDEVICE;
+            }
         }
     }
     *out = c;
@@ -420,6 +430,15 @@ int cmlb_state_bytes(const cmlb_params* p, size_t* bytes) {
     const std::string why = validate(p);
     if (!why.empty()) { g_create_error = why; return CMLB_EINVAL; }
     *bytes = state_bytes_of(p);
+    return CMLB_OK;
+}
+
+int cmlb_state_layout(const cmlb_params* p, uint64_t* pitch, uint64_t* plane) {
+    if (!pitch || !plane) return CMLB_EINVAL;
+    const std::string why = validate(p);
+    if (!why.empty()) { g_create_error = why; return CMLB_EINVAL; }
+    *pitch = cmlb::state_pitch(p->lattice, p->storage, (uint32_t)p->nx);
+    *plane = state_plane_of(p);
     return CMLB_OK;
 }
 
@@ -913,6 +932,19 @@ int cmlb_load_state_device(cmlb_ctx* c, const void* src) {
     return CMLB_OK;
 }
 
+int cmlb_load_deviations_device(cmlb_ctx* c, const float* src) {
+    if (!c) return CMLB_EINVAL;
+    if (!src) return fail(c, CMLB_EINVAL, "src is NULL");
+    if (hipSetDevice(c->p.device) != hipSuccess) return fail(c, CMLB_EDEVICE, "hipSetDevice failed");
+    StepArgs a = base_args(c);
+    launch_encode_deviations(c->p.lattice, c->p.storage, c->f[c->cur], src, a, c->stream);
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "encode kernel launch");
+    c->initialised = true;
+    c->steps = 0;
+    return CMLB_OK;
+}
+
 int cmlb_box_filter(cmlb_ctx* c, int factor, void* dst) {
     if (!c) return CMLB_EINVAL;
     if (!dst) return fail(c, CMLB_EINVAL, "dst is NULL");
@@ -1038,6 +1070,8 @@ static int closure_gradient(cmlb_ctx* c, const cmlb_batch* b) {
         }
         for (int64_t k = 0; k < b->n_pairs; ++k) {
             StepArgs sa = a;
+            sa.g.plane = N;                    // batch arrays are unpadded [27][z][y][x],
+            sa.pitch = (uint32_t)c->p.nx;      // not in the state's own layout
             sa.src = static_cast<const float*>(b->state) + (uint64_t)k * 27 * N;
             sa.dst = c->cl_f1 + (uint64_t)k * 27 * N;
             launch_step_closure(sa, c->cl_net, c->stream);

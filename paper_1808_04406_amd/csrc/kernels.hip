@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, FieldArgs fa) {
 struct CodecArgs {
     void* stor;         // the state: [Q][plane], rows padded to the pitch
     double* full;       // [Q][node], unpadded
+    const float* dev;   // [Q][node], unpadded FP32 deviations f - w rho0 (k_encode_dev)
     GridArgs g;
     uint32_t pitch;
     uint64_t plane;     // nodes (the loop bound of the codecs)
@@ -175,6 +176,23 @@ __global__ __launch_bounds__(256) void k_encode(CodecArgs c) {
         static_for<0, LatInfo<LAT>::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double v = (c.full[(uint64_t)i * c.plane + n] - c.w[i] * c.rho0) * (double)c.s[i];
+            dst[(uint64_t)i * c.g.plane + node_offset(c.g.nx, c.pitch, n)] = S::from_double(v);
+        });
+    }
+}
+
+// Encode unpadded FP32 deviations (the box filter's output layout) into the
+// state's storage type and layout.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_encode_dev(CodecArgs c) {
+    using S = Store<ST>;
+    using T = typename S::T;
+    T* dst = static_cast<T*>(c.stor);
+    for (uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; n < c.plane;
+         n += (uint64_t)gridDim.x * blockDim.x) {
+        static_for<0, LatInfo<LAT>::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double v = (double)c.dev[(uint64_t)i * c.plane + n] * (double)c.s[i];
             dst[(uint64_t)i * c.g.plane + node_offset(c.g.nx, c.pitch, n)] = S::from_double(v);
         });
     }
@@ -336,14 +354,14 @@ __global__ __launch_bounds__(256) void k_box_filter(StepArgs a, int factor, floa
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t pitch) {
+GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz, uint64_t plane) {
     GridArgs g;
     g.nx = nx;
     g.ny = ny;
     g.nz = nz;
     uint32_t bs = nx >= 256 ? 256u : ((nx + 63u) / 64u) * 64u;
     g.nchunks = (nx + bs - 1) / bs;
-    g.plane = (uint64_t)pitch * ny * nz;
+    g.plane = plane;
     return g;
 }
 
@@ -457,6 +475,7 @@ int launch_codec(int lattice, int storage, bool decode, void* stor, double* full
     CodecArgs c;
     c.stor = stor;
     c.full = full;
+    c.dev = nullptr;
     c.g = a.g;
     c.pitch = a.pitch;
     c.plane = nodes_of(a.g);
@@ -476,6 +495,28 @@ int launch_codec(int lattice, int storage, bool decode, void* stor, double* full
     }
 #undef L_DEC
 #undef L_ENC
+    return 0;
+}
+
+int launch_encode_deviations(int lattice, int storage, void* stor, const float* dev, const StepArgs& a,
+                             hipStream_t s) {
+    CodecArgs c;
+    c.stor = stor;
+    c.full = nullptr;
+    c.dev = dev;
+    c.g = a.g;
+    c.pitch = a.pitch;
+    c.plane = nodes_of(a.g);
+    c.rho0 = a.rho0;
+    for (int i = 0; i < 37; ++i) {
+        c.w[i] = 0.0;
+        c.s[i] = a.s[i];
+        c.inv_s[i] = a.inv_s[i];
+    }
+    dim3 grid = flat_grid(nodes_of(a.g)), block(256);
+#define L_ENCD(L, S) hipLaunchKernelGGL((k_encode_dev<L, S>), grid, block, 0, s, c)
+    CMLB_DISPATCH(L_ENCD)
+#undef L_ENCD
     return 0;
 }
 

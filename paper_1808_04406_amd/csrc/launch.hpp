@@ -5,7 +5,7 @@
 
 namespace cmlb {
 
-GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t pitch);
+GridArgs make_grid(uint32_t nx, uint32_t ny, uint32_t nz, uint64_t plane);
 
 // Step-kernel launch shape: one block per x-segment of each of `rows` rows,
 // segments of up to max_block nodes (a whole row when it fits, so that the
@@ -53,6 +53,8 @@ int launch_step2_d37(int storage, int model, const StepArgs& a, int mode, hipStr
 int launch_step2(int lattice, int storage, int model, const StepArgs& a, int mode, hipStream_t s);
 int launch_init(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
 int launch_moments(int lattice, int storage, const StepArgs& a, const FieldArgs& f, hipStream_t s);
+int launch_encode_deviations(int lattice, int storage, void* stor, const float* dev, const StepArgs& a,
+                             hipStream_t s);
 int launch_codec(int lattice, int storage, bool decode, void* stor, double* full, const StepArgs& a,
                  const double* w, hipStream_t s);
 

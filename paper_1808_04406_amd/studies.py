@@ -865,7 +865,7 @@ def closure_momentum(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
         c.closure_load(P, sigma)
         c.closure_tie_even(True)
         c.closure_enable(True)
-        c.load_state_device(buf)
+        c.load_deviations_device(buf)
         ctxs[k] = c
     probe = cmlb.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c}, stream=stream)
     hist = {k: {"ke": [], "enstrophy": []} for k in list(runs) + ["filtered_fine"]}
@@ -876,7 +876,7 @@ def closure_momentum(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
             for c in ctxs.values():
                 c.step(every)
         fine.box_filter(factor, buf)
-        probe.load_state_device(buf)
+        probe.load_deviations_device(buf)
         g = probe.reduce(allow_unstable=True)
         hist["filtered_fine"]["ke"].append(g["ke"])
         hist["filtered_fine"]["enstrophy"].append(g["enstrophy"])
@@ -994,7 +994,7 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
     runs["learned"].closure_enable(True)
     fine.box_filter(factor, buf)
     for c in runs.values():
-        c.load_state_device(buf)
+        c.load_deviations_device(buf)
     hist = {k: {"ke": [], "enstrophy": [], "nonfinite": []} for k in list(runs) + ["filtered_fine"]}
     tt = []
     for t in range(0, tgv_coarse_steps + 1, every):
@@ -1003,7 +1003,7 @@ def closure(n_fine=512, factor=4, seeds=tuple(range(8)), held_out=(7,), spinup=4
             for c in runs.values():
                 c.step(every)
         fine.box_filter(factor, buf)
-        probe.load_state_device(buf)
+        probe.load_deviations_device(buf)
         items = [("filtered_fine", probe)] + list(runs.items())
         for name, c in items:
             g = c.reduce(allow_unstable=True)

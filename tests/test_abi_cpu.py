@@ -287,8 +287,10 @@ def test_run_config_validation(tmp_path):
 
 def test_state_bytes_pitch_rule(cm):
     """x-rows are padded to a multiple of 128 bytes when that adds at most one
-    eighth, except D3Q27 FP32 rows that are a multiple of 32 bytes (cmlb.h,
-    layout of the state); host-only query."""
+    eighth, except D3Q27 FP32 rows that are a multiple of 32 bytes; D3Q27
+    planes in 16-bit storage of at least 1 MiB are padded to their bytes
+    rounded up to 8 KiB plus 4 KiB (cmlb.h, layout of the state); host-only
+    queries."""
     cases = [  # lattice, shape (nz, ny, nx), storage, expected pitch
         ("D3Q27", (250, 250, 250), "f32", 256),
         ("D3Q27", (4, 6, 252), "f32", 256),      # 1008-byte rows: 16-byte aligned
@@ -303,14 +305,29 @@ def test_state_bytes_pitch_rule(cm):
         ("D2Q37", (5, 260), "f64", 272),
         ("D2Q37", (5, 260), "bf16", 260),        # 320 would add 23 %
         ("D2Q9", (19, 70), "f32", 70),
+        ("D3Q27", (256, 256, 256), "f32", 256),   # 64 MiB planes, FP32: unpadded
+        ("D3Q27", (100, 100, 100), "f64", 112),
+        ("D2Q37", (2048, 2048), "f32", 2048),
+        ("D2Q37", (1024, 1024), "bf16", 1024),    # 2D lattices: unpadded
+        ("D3Q27", (512, 512, 512), "bf16", 512),  # 16-bit D3Q27: padded
+        ("D3Q27", (250, 250, 250), "f16", 256),   # 32,000,000-byte planes
+        ("D3Q27", (128, 64, 64), "bf16", 64),     # exactly 1 MiB
+        ("D3Q27", (127, 64, 64), "f16", 64),      # just under 1 MiB
     ]
     elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
     Q = {"D2Q9": 9, "D3Q27": 27, "D2Q37": 37}
     for lattice, shape, storage, pitch in cases:
         rows = int(np.prod(shape[:-1]))
-        assert cm.state_bytes(lattice, shape, storage) == Q[lattice] * rows * pitch * elem[storage], (lattice, shape)
+        plane_bytes = rows * pitch * elem[storage]
+        if lattice == "D3Q27" and elem[storage] == 2 and plane_bytes >= 1 << 20:
+            plane_bytes = -(-plane_bytes // 8192) * 8192 + 4096
+        assert cm.state_layout(lattice, shape, storage) == (pitch, plane_bytes // elem[storage]), (lattice, shape)
+        assert cm.state_bytes(lattice, shape, storage) == Q[lattice] * plane_bytes, (lattice, shape)
+    assert cm.state_layout("D3Q27", (512, 512, 512), "bf16")[1] * 2 == (256 << 20) + 4096
     with pytest.raises(cm.CmlbError):
         cm.state_bytes("D3Q27", (0, 8, 8))
+    with pytest.raises(cm.CmlbError):
+        cm.state_layout("D3Q27", (0, 8, 8))
 
 
 def test_bench_refuses_several_gpus():

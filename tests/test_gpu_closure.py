@@ -393,6 +393,40 @@ def test_momentum_objective_matches_oracle(cm, orc, tie):
     assert np.abs(r["grad"][2080:2084]).max() > 0
 
 
+def test_momentum_objective_equals_two_plain_steps(cm, orc):
+    """On 64^3, at constant rates (W3 = 0), the momentum objective of an
+    unpadded batch equals the mismatch of two plain steps of the same state,
+    run by a plain context with those rates (in its own layout) and read
+    through cmlb_get_moments."""
+    import torch
+    from paper_1808_04406_amd import studies
+    shape = (64, 64, 64)
+    w = orc.lattice("D3Q27")["w"][:, None, None, None]
+    e = orc.lattice("D3Q27")["e"][:, :3].astype(np.float64)
+    S = (near_eq_state(orc, shape, 95) - w).astype(np.float32)
+    T = (near_eq_state(orc, shape, 97) - w).astype(np.float32)
+    st = torch.from_numpy(S.reshape(1, 27, -1)).cuda()
+    tg = torch.from_numpy(T.reshape(1, 27, -1)).cuda()
+    ctx = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.6})
+    plain = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.6, 3: 1.0, 4: 0.6, 5: 1.0, 6: 0.6})
+    try:
+        ctx.closure_load(studies._constant_net([1.0] * 4, seed=1, scale=0.1), np.ones(27))
+        ctx.closure_tie_even(True)
+        ctx.closure_set_objective("momentum")
+        obj = ctx.closure_objective(st, tg, grad=False)
+        plain.set_populations(S.astype(np.float64) + w)
+        plain.step(2)
+        rho, u, _ = plain.get_moments()
+    finally:
+        ctx.destroy()
+        plain.destroy()
+    j2 = rho[None] * u
+    jbar = np.einsum("id,i...->d...", e, T.astype(np.float64) + w)
+    ref = float(np.mean(np.sum((j2 - jbar) ** 2, axis=0)))
+    print(f"momentum objective {obj:.6e}, two plain steps {ref:.6e}")
+    assert abs(obj - ref) <= 1e-4 * ref
+
+
 def test_momentum_trained_closure_beats_fixed_rates(cm):
     """What training on the momentum objective (cmlb_closure_set_objective:
     the momentum two coarse steps ahead) gains over the method without the
@@ -477,7 +511,8 @@ def test_momentum_trained_closure_beats_fixed_rates(cm):
             c.closure_load(params, sigma)
             c.closure_tie_even(True)
             c.closure_enable(True)
-            c.load_state_device(buf)
+            c.load_deviations_device(buf)
+            c.sync()
         probe = cm.Context("D3Q27", (nc,) * 3, storage="f32", tau={2: tau_c})
         ctxs["probe"] = probe
         err = {k: [0.0, 0.0] for k in runs}
@@ -485,7 +520,7 @@ def test_momentum_trained_closure_beats_fixed_rates(cm):
             fine.step(50 * factor)
             fine.box_filter(factor, buf)
             fine.sync()
-            probe.load_state_device(buf)
+            probe.load_deviations_device(buf)
             ref = probe.reduce()
             for k in runs:
                 ctxs[k].step(50)

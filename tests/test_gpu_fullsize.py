@@ -40,18 +40,24 @@ def tgv512():
     return n, rho, u, {2: t2, 3: 1.0, 4: t2, 5: 1.0, 6: t2}
 
 
+def cm_layout(ctx, storage):
+    """(pitch, plane) of a D3Q27 context's state (cmlb_state_layout)."""
+    from paper_1808_04406_amd import cmlb
+    return cmlb.state_layout("D3Q27", ctx.shape, storage)
+
+
 def sampled_state(ctx, storage, nodes, scale, w):
     """Stored populations of the given nodes, decoded (f = g / s + w rho0) on the host.
-    The state's x-rows are padded to a pitch (header: layout of the state)."""
+    The state's x-rows and planes are padded (header: layout of the state)."""
     import torch
     _, nbytes, _ = ctx.state()
     nz, ny, nx = ctx.shape
-    elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[storage]
-    pitch = nbytes // (27 * ny * nz * elem)
+    pitch, plane = cm_layout(ctx, storage)
     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     ctx.store_state_device(buf)
     ctx.sync()
     g = buf.view(getattr(torch, TORCH_DTYPE[storage])).view(27, -1)
+    assert g.shape[1] == plane
     offs = (nodes // nx) * pitch + nodes % nx
     sel = g[:, torch.from_numpy(offs).cuda()].double().cpu().numpy()
     del buf, g

@@ -458,6 +458,30 @@ def test_device_fields_on_torch_stream(cm, orc):
     assert np.abs(g_u - o_u).max() < 1e-13
 
 
+@pytest.mark.parametrize("shape,storage", [((64, 64, 64), "f32"), ((4, 6, 250), "bf16"), ((3, 5, 300), "f64"),
+                                           ((128, 128, 128), "f16")])
+def test_load_deviations_device(cm, orc, shape, storage):
+    """cmlb_load_deviations_device: unpadded FP32 deviations land in the
+    state's own storage and layout (128^3 FP16 has padded planes, the 250-
+    and 300-wide grids padded rows), read back through cmlb_get_populations:
+    exact for FP32 and FP64 storage, one rounding of dev * s for the 16-bit
+    forms."""
+    import torch
+    w = orc.lattice("D3Q27")["w"][:, None, None, None]
+    dev = (0.01 * np.random.default_rng(5).standard_normal((27,) + shape)).astype(np.float32)
+    scale = f16_scales(w[:, 0, 0, 0]) if storage == "f16" else np.ones(27)
+    ctx = cm.Context("D3Q27", shape, storage=storage, scale=scale if storage == "f16" else None)
+    try:
+        ctx.load_deviations_device(torch.from_numpy(dev).cuda())
+        assert ctx.step_count() == 0
+        f = ctx.get_populations()
+    finally:
+        ctx.destroy()
+    s = scale[:, None, None, None]
+    ref = quantise(dev.astype(np.float64) * s, storage) / s + w
+    assert np.array_equal(f, ref)
+
+
 @pytest.mark.parametrize("kind,shape,storage,thermal", [("D3Q27", (2, 3, 300), "f32", False),
                                                         ("D2Q37", (4, 260), "f64", True)])
 def test_init_fields_on_padded_rows(cm, orc, kind, shape, storage, thermal):
