@@ -83,14 +83,14 @@ def load(path, stream=None, device=0):
     times and closure are those saved."""
     import torch
     h, offset = read_header(path)
+    layout = list(cmlb.state_layout(h["lattice"], tuple(h["shape"]), h["storage"]))
+    if h.get("layout") != layout:
+        raise ValueError(f"{path}: state layout (pitch, plane) {h.get('layout')}, this library uses {layout}")
     ctx = cmlb.Context(h["lattice"], tuple(h["shape"]), storage=h["storage"], model=h["model"],
                        thermal=h["thermal"], rho0=h["rho0"], theta0=h["theta0"],
                        tau={int(k): v for k, v in h["tau"].items()}, scale=h["scale"], device=device,
                        stream=stream)
     try:
-        layout = list(cmlb.state_layout(h["lattice"], tuple(h["shape"]), h["storage"]))
-        if h.get("layout") != layout:
-            raise ValueError(f"{path}: state layout (pitch, plane) {h.get('layout')}, this library uses {layout}")
         data = np.fromfile(path, dtype=np.uint8, offset=offset)
         if data.size != h["bytes"]:
             raise ValueError(f"{path}: {data.size} population bytes, expected {h['bytes']}")

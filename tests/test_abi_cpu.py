@@ -146,6 +146,14 @@ def test_checkpoint_header_errors(tmp_path):
     old.write_bytes(checkpoint.MAGIC + struct.pack("<IQ", 99, len(hb)) + hb)
     with pytest.raises(ValueError):
         checkpoint.read_header(str(old))
+    # a state stored in another layout (an unpadded 16-bit 512^3 state) is
+    # refused before any device work
+    h = {"lattice": "D3Q27", "shape": [512, 512, 512], "storage": "bf16", "layout": [512, 512 ** 3]}
+    hb = json.dumps(h).encode()
+    other = tmp_path / "w.bin"
+    other.write_bytes(checkpoint.MAGIC + struct.pack("<IQ", checkpoint.VERSION, len(hb)) + hb)
+    with pytest.raises(ValueError, match="layout"):
+        checkpoint.load(str(other))
 
 
 # ---------------------------------------------------------------------------
