@@ -238,6 +238,9 @@ __host__ __device__ inline uint64_t state_plane(int lattice, int storage, uint64
     return (lattice == kD3Q27 && (storage == kBF16 || storage == kF16)) ? plane_stride(elems, 2u) : elems;
 }
 
+// Raw buffer resource word 3 for gfx9-family devices (32-bit data, no swizzle).
+constexpr int kBufferWord3 = 0x00020000;
+
 // Row stride of a state.  D3Q27 FP32 states are stepped two steps per launch
 // by default, and that kernel, which moves 64-node tile rows, streams rows
 // aligned to 32 bytes as fast as padded ones (padding them measured slower),

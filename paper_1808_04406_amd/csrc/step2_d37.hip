@@ -90,9 +90,6 @@ constexpr D37Groups make_d37_groups() {
 }
 inline constexpr D37Groups kGroups37 = make_d37_groups();
 
-// Raw buffer resource word 3 for gfx9-family devices (32-bit data, no swizzle).
-constexpr int kBufferWord3 = 0x00020000;
-
 // PAD: x-rows padded to the pitch (otherwise the row stride is nx).
 // Addressing: the state (37 planes) is below 4 GiB, so each population is
 // reached through a raw buffer resource on its base with a 32-bit lane

@@ -67,13 +67,22 @@ struct Step2Args {
 };
 
 // PAD: x-rows padded to the pitch (otherwise the row stride is nx).
-template <int ST, bool PAD>
+// B32 (FP32 states below 4 GiB): the pulls go through one raw buffer
+// resource, with a lane offset that is fixed for the whole z-march (the
+// pulled row and column within a plane) and a scalar offset (population
+// plane plus z-plane), so the loads need no per-population address
+// arithmetic and no 64-bit per-population base addresses in scalar
+// registers (which otherwise spill to vector-register lanes): 1.5 % faster
+// at 256^3.  The stores stay global non-temporal stores; buffer stores
+// with the same cache policy measured 3.5 % slower.
+template <int ST, bool PAD, bool B32>
 __global__ __launch_bounds__(Tb2Geom<ST>::Threads) void k_step2_tp(Step2Args A) {
     using S = Store<ST>;
     using T = typename S::T;
     using R = typename S::R;
     using Tile = Tb2Tile<ST>;
     static_assert(!S::kScaled && sizeof(R) == sizeof(T), "unscaled storage of the arithmetic type only");
+    static_assert(!B32 || ST == kF32, "buffer addressing for FP32 states only");
     constexpr int TX = Tile::TX, TY = Tile::TY, RX = Tile::RX, RN = Tile::RN;
     __shared__ R lds[54 * RN];
     R* sD = lds;             // [9][RN]     e_z = -1 group, plane q
@@ -94,6 +103,9 @@ __global__ __launch_bounds__(Tb2Geom<ST>::Threads) void k_step2_tp(Step2Args A) 
     char* __restrict__ dst = static_cast<char*>(a.dst);
     const uint64_t plane_bytes = a.g.plane * sizeof(T);
     const uint32_t rowb = (PAD ? a.pitch : nx) * (uint32_t)sizeof(T);
+    const uint32_t plane_b = (uint32_t)plane_bytes;   // B32: 27 planes below 2^32 bytes
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(src), 0, (int)(27u * plane_b), kBufferWord3);
 
     // First step: region node r of this thread, its pulled x offsets and y rows.
     const bool act1 = t < RN;
@@ -103,6 +115,18 @@ __global__ __launch_bounds__(Tb2Geom<ST>::Threads) void k_step2_tp(Step2Args A) 
     const uint32_t xoff[3] = {wrap_inc(gx, nx) * (uint32_t)sizeof(T), gx * (uint32_t)sizeof(T),
                               wrap_dec(gx, nx) * (uint32_t)sizeof(T)};   // x - e for e = -1, 0, +1
     const uint32_t ysrc[3] = {wrap_inc(gy, ny), gy, wrap_dec(gy, ny)};
+    // In-plane byte offsets of the nine pulled (y, x) rows and columns: the
+    // same for every plane of the z-march, so only the plane offset, uniform
+    // across the workgroup, changes from one iteration to the next.
+    uint32_t xyoff[3][3];
+    static_for<0, 3>([&](auto Y) {
+        constexpr int ey = decltype(Y)::value;
+        static_for<0, 3>([&](auto X) {
+            constexpr int ex = decltype(X)::value;
+            xyoff[ey][ex] = ysrc[ey] * rowb + xoff[ex];
+        });
+    });
+    const uint32_t zb = ny * rowb;   // bytes of one z-plane of a population
     // Second step: tile node of this thread.
     const bool in2 = t < TX * TY;
     const int ix = t % TX, iy = t / TX;
@@ -115,12 +139,17 @@ __global__ __launch_bounds__(Tb2Geom<ST>::Threads) void k_step2_tp(Step2Args A) 
     const R rho0 = R(a.rho0);
 
     auto load_state = [&](R (&h)[27], uint32_t qz) {
-        const uint32_t zs[3] = {wrap_inc(qz, nz), qz, wrap_dec(qz, nz)};
+        const uint32_t zo[3] = {wrap_inc(qz, nz) * zb, qz * zb, wrap_dec(qz, nz) * zb};
         static_for<0, 27>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int ex = TP<3>::ex(i), ey = TP<3>::ey(i), ez = TP<3>::ez(i);
-            const uint32_t off = (zs[ez + 1] * ny + ysrc[ey + 1]) * rowb + xoff[ex + 1];
-            h[i] = S::load(reinterpret_cast<const T*>(src + i * plane_bytes + off));
+            if constexpr (B32) {
+                h[i] = __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 rsrc, (int)xyoff[ey + 1][ex + 1], (int)((uint32_t)i * plane_b + zo[ez + 1]), 0));
+            } else {
+                const uint32_t off = zo[ez + 1] + xyoff[ey + 1][ex + 1];
+                h[i] = S::load(reinterpret_cast<const T*>(src + i * plane_bytes + off));
+            }
         });
     };
     const int J = (int)(zend - z0) + 1;   // iterations j = 0..J: first step at plane z0 - 1 + j
@@ -269,8 +298,17 @@ int launch2(const StepArgs& a, const Tb2Cost& cost, bool force, hipStream_t s) {
         if (P.cost_us >= 2.0 * single_us) return -1;
     }
     constexpr int threads = Tb2Geom<ST>::Threads;
-    if (a.pitch != a.g.nx) hipLaunchKernelGGL((k_step2_tp<ST, true>), dim3(P.blocks), dim3(threads), 0, s, P.A);
-    else hipLaunchKernelGGL((k_step2_tp<ST, false>), dim3(P.blocks), dim3(threads), 0, s, P.A);
+    const bool pad = a.pitch != a.g.nx;
+    if constexpr (ST == kF32) {
+        // buffer addressing when the 27 planes span less than 4 GiB
+        if (27ull * a.g.plane * sizeof(float) < (1ull << 32)) {
+            if (pad) hipLaunchKernelGGL((k_step2_tp<ST, true, true>), dim3(P.blocks), dim3(threads), 0, s, P.A);
+            else hipLaunchKernelGGL((k_step2_tp<ST, false, true>), dim3(P.blocks), dim3(threads), 0, s, P.A);
+            return 0;
+        }
+    }
+    if (pad) hipLaunchKernelGGL((k_step2_tp<ST, true, false>), dim3(P.blocks), dim3(threads), 0, s, P.A);
+    else hipLaunchKernelGGL((k_step2_tp<ST, false, false>), dim3(P.blocks), dim3(threads), 0, s, P.A);
     return 0;
 }
 }  // namespace
