@@ -70,6 +70,9 @@ def test_null_context_is_rejected(cm):
     assert L.cmlb_sync(None) == cm.EINVAL
     assert L.cmlb_closure_set_adam(None, 0.9, 0.999, 1e-8) == cm.EINVAL
     assert L.cmlb_closure_freeze(None, 4) == cm.EINVAL
+    assert L.cmlb_load_deviations_device(None, None) == cm.EINVAL
+    p = cm.make_params("D3Q27", (8, 8, 8))
+    assert L.cmlb_state_layout(ctypes.byref(p), None, None) == cm.EINVAL
     g = ctypes.c_double()
     assert L.cmlb_copy_bandwidth(0, 1 << 20, 5, 1, ctypes.byref(g)) == cm.EINVAL     # planes 1 or 27
     assert L.cmlb_copy_bandwidth(0, 1 << 20, 27, 0, ctypes.byref(g)) == cm.EINVAL    # reps >= 1
