@@ -143,6 +143,43 @@ def test_thermal_waves_1024_two_steps(cm, orc, fuse):
     assert err <= 2 * TOL["f32"] * dev
 
 
+@pytest.mark.parametrize("nz", [151, 152])
+def test_two_step_addressing_at_4gib(cm, nz):
+    """D3Q27 512 x 512 x nz FP32: with nz = 151 the 27 planes take 4.275 GB,
+    just below 2^32 bytes, and the two-step kernel pulls through one buffer
+    resource whose offsets reach the top of the 32-bit range (out-of-range
+    buffer reads return zero, so an offset error would show as wrong values,
+    not as a fault); with nz = 152 (4.303 GB) it takes its global-load form.
+    Either way two steps in one launch equal two single-step launches
+    bitwise, compared on the device."""
+    import torch
+    shape = (nz, 512, 512)
+    nbytes = cm.state_bytes("D3Q27", shape, "f32")
+    assert (nbytes < 2 ** 32) == (nz == 151)
+    rho, u, _ = inputs.random_fields(shape, 11, drho=0.02, umax=0.04)
+    out = []
+    for fuse in (1, 2):
+        ctx = cm.Context("D3Q27", shape, storage="f32", tau={2: 0.52, 3: 1.0, 4: 0.52, 5: 1.0, 6: 0.52})
+        try:
+            ctx.set_step_fusion(fuse)
+            ctx.init_fields(rho, u)
+            ctx.step(2)
+            buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            ctx.store_state_device(buf)
+            ctx.sync()
+            out.append(buf)
+        finally:
+            ctx.destroy()
+    del rho, u
+    same = torch.equal(out[0], out[1])
+    top = out[1].view(torch.float32)[-512 * 512:]   # the last population's top plane
+    nonzero = int((top != 0).sum().item())
+    del out, top, buf
+    torch.cuda.empty_cache()
+    assert same
+    assert nonzero > 0.99 * 512 * 512
+
+
 def test_thermal_two_step_past_2gib(cm, orc):
     """D2Q37 4096^2 FP32 (a 2.48 GB state, so population offsets pass 2^31
     in the two-step kernels' 32-bit buffer addressing): two steps in one
