@@ -756,9 +756,10 @@ def closure_momentum(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
     even orders, tau_2) relative to the stable fixed rates, networks trained
     from the stable fixed rates (Adam's eps 1e-6 of the first gradient's RMS
     size) that set omega_3 and omega_5 or omega_3 alone (omega_5 frozen at
-    1), and the coarse Taylor-Green rollout
-    (Re = 1e5) of the stable fixed rates, the best constant omega_3 and the
-    two trained networks against the filtered fine run."""
+    1; from the stable rates and from the best constant omega_3), and the
+    coarse Taylor-Green rollout (Re = 1e5) of the stable fixed rates, the
+    best constant omega_3 and the trained networks against the filtered
+    fine run."""
     import torch
     u0, re = 0.05, 1.0e5
     tau_f = 0.5 + 3.0 * u0 * (n_fine / (2 * math.pi)) / re
@@ -824,11 +825,15 @@ def closure_momentum(n_fine=128, factor=2, seeds=(0, 1, 2, 3), held_out=(3,), tr
     # (its rate barely moves the objective, and Adam's steps do not shrink
     # with the gradient, so it can reach the linearly unstable corner
     # omega_5 -> 1.95 with omega_3 -> 0.5).
-    variants = {"omega3_omega5": (), "omega3": (5,)}
+    # A third network sets omega_3 alone starting from the best constant
+    # omega_3 of the sweep instead of the stable fixed rates.
+    variants = {"omega3_omega5": (), "omega3": (5,), "omega3_from_best": (5,)}
+    start = {"omega3_omega5": stable, "omega3": stable,
+             "omega3_from_best": _constant_net([best3, 1.0, 1.0, 1.0], 1, 0.1)}
     nets = {}
     for name, frozen in variants.items():
         for lr_ in lrs:
-            ctx.closure_load(stable, sigma)
+            ctx.closure_load(start[name], sigma)
             ctx.closure_tie_even(True)
             ctx.closure_set_objective("momentum")
             ctx.closure_freeze(frozen)
